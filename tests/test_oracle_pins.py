@@ -1,0 +1,336 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test names the passage it pins. None of them re-types the oracle's own
+formula: they check closed forms derived by hand, identities with other
+library routines, invariants, limits and exact special cases.
+"""
+import math
+
+import mpmath
+import numpy as np
+import pytest
+
+from oracle import binary_lbm as O
+
+
+def _rng(seed=1603):
+    return np.random.default_rng(seed)
+
+
+# --- P1: Eq. (m) ------------------------------------------------------------
+def test_moment_matrix_rows_orthogonal():
+    """Rows of the printed M are mutually orthogonal with squared norms
+    (9, 36, 36, 6, 12, 6, 12, 4, 4); a mistyped entry breaks this."""
+    g = O.M @ O.M.T
+    assert np.array_equal(g, np.diag([9, 36, 36, 6, 12, 6, 12, 4, 4]).astype(float))
+    assert np.allclose(O.M_INV @ O.M, np.eye(9), atol=1e-15)
+
+
+def test_velocity_order_matches_moment_rows():
+    """R2: rows 3 and 5 of M are c_x and c_y, row 7 is c_x^2 - c_y^2, row 8 is
+    c_x c_y; directions 2<->4, 5<->7, 6<->8 are opposite (DBB pairs)."""
+    assert np.array_equal(O.M[3], O.CX) and np.array_equal(O.M[5], O.CY)
+    assert np.array_equal(O.M[7], O.CX ** 2 - O.CY ** 2)
+    assert np.array_equal(O.M[8], O.CX * O.CY)
+    for a, b in ((2, 4), (5, 7), (6, 8), (1, 3)):
+        assert O.CX[a] == -O.CX[b] and O.CY[a] == -O.CY[b]
+    # e = -4 + 3|c|^2 and eps = 4 - 21/2 |c|^2 + 9/2 |c|^4 (Lallemand-Luo basis)
+    c2 = O.CX ** 2 + O.CY ** 2
+    assert np.array_equal(O.M[1], -4 + 3 * c2)
+    assert np.array_equal(O.M[2], 4 - 10.5 * c2 + 4.5 * c2 ** 2)
+
+
+# --- P2: Eq. (feq) ------------------------------------------------------------
+@pytest.mark.parametrize("s", [1.0, 0.5, 0.1, 0.2])
+def test_equilibrium_moments_closed_form(s):
+    """Moments of Eq. (feq), derived by hand from the D2Q9 lattice isotropy:
+    sum f = rho, sum c f = rho u, sum c c f = rho s c_s^2 I + rho u u, and the
+    full moment vector M f^eq =
+    (rho, rho(2s-4) + 3 rho|u|^2, rho(4-3s) - 3 rho|u|^2, rho ux, -rho ux,
+     rho uy, -rho uy, rho(ux^2-uy^2), rho ux uy)."""
+    rng = _rng()
+    rho = rng.uniform(0.3, 10.0, 50)
+    ux = rng.uniform(-0.1, 0.1, 50)
+    uy = rng.uniform(-0.1, 0.1, 50)
+    feq = O.f_equilibrium(rho, ux, uy, s)
+    cx = O.CX[:, None].astype(float)
+    cy = O.CY[:, None].astype(float)
+    assert np.allclose(feq.sum(0), rho, rtol=1e-14)
+    assert np.allclose((cx * feq).sum(0), rho * ux, rtol=1e-13, atol=1e-15)
+    assert np.allclose((cy * feq).sum(0), rho * uy, rtol=1e-13, atol=1e-15)
+    assert np.allclose((cx * cx * feq).sum(0), rho * s / 3 + rho * ux * ux, rtol=1e-13)
+    assert np.allclose((cy * cy * feq).sum(0), rho * s / 3 + rho * uy * uy, rtol=1e-13)
+    assert np.allclose((cx * cy * feq).sum(0), rho * ux * uy, rtol=1e-13, atol=1e-16)
+    u2 = ux * ux + uy * uy
+    meq = np.stack([rho, rho * (2 * s - 4) + 3 * rho * u2, rho * (4 - 3 * s) - 3 * rho * u2,
+                    rho * ux, -rho * ux, rho * uy, -rho * uy, rho * (ux * ux - uy * uy), rho * ux * uy])
+    assert np.allclose(O.M @ feq, meq, rtol=1e-13, atol=1e-14)
+
+
+def test_equilibrium_weights_and_eos():
+    """sum_i w_i alpha_si = 1, and at rest the species pressure
+    rho_s s_s c_s^2 equals n_s k_B T with k_B T = m_min c_s^2 (Eq. (P))."""
+    for s in (1.0, 0.1, 0.5, 0.37):
+        assert abs(np.dot(O.W, O.alpha_weights(s)) - 1.0) < 1e-15
+    m_a, m_b, m_min = 4.0, 40.0, 4.0
+    rho_b = 7.3
+    feq = O.f_equilibrium(rho_b, 0.0, 0.0, m_min / m_b)
+    p_b = 0.5 * ((O.CX ** 2 + O.CY ** 2) * feq).sum()        # trace/2 of the pressure tensor
+    assert abs(p_b - (rho_b / m_b) * m_min * O.CS2) < 1e-14
+
+
+def test_species_density_reproduces_mole_fraction_and_pressure():
+    """R13: rho_s = x_s P/(s_s c_s^2) gives back x_a = C_l (Eq. (C)) and
+    P = n k_B T (Eq. (P))."""
+    p = O.Params(nx=8, ny=4, m_a=20, m_b=40, cl_in=0.3, cl_out=0.3, theta=3, kn_out=0.05, dbb_r=0.87)
+    ra, rb = O.species_density(p, 0.77, 0.3)
+    na, nb = ra / p.m_a, rb / p.m_b
+    assert abs(na / (na + nb) - 0.3) < 1e-15
+    assert abs((na + nb) * p.m_min * O.CS2 - 0.77) < 1e-15
+
+
+# --- P3: BGK limit (text after Eq. (S)) ---------------------------------------
+def test_mrt_with_equal_times_is_bgk():
+    rng = _rng(3)
+    p = O.Params(nx=6, ny=5, m_a=4, m_b=40, cl_in=0.5, cl_out=0.5, theta=1, kn_out=0.1,
+                 dbb_r=1.16, tau_bgk=0.83, periodic_x=True, periodic_y=True, mfp_off=True)
+    f = O.initial_state(p) * (1 + 0.05 * rng.standard_normal((2, 9, 5, 6)))
+    post = O.collide(f, p)
+    rho_s = f.sum(1)
+    rho = rho_s.sum(0)
+    ux = np.tensordot(O.CX.astype(float), f, ([0], [1])).sum(0) / rho
+    uy = np.tensordot(O.CY.astype(float), f, ([0], [1])).sum(0) / rho
+    for sig in range(2):
+        feq = O.f_equilibrium(rho_s[sig], ux, uy, p.s[sig])
+        assert np.allclose(post[sig], f[sig] - (f[sig] - feq) / 0.83, rtol=1e-13, atol=1e-15)
+
+
+# --- P4: homogeneous relaxation -------------------------------------------------
+def test_homogeneous_mixture_relaxes_geometrically():
+    """Periodic box, uniform state, MFP off: streaming is the identity and rho_s,
+    the mixture u and therefore every tau are constant, so each moment obeys
+    m_k(t) - m_k^eq = (1 - 1/tau_k)^t (m_k(0) - m_k^eq). In particular the
+    species velocity difference decays as (1 - 1/tau_d)^t (the coupling of
+    Eq. (feq) through the mixture velocity)."""
+    p = O.Params(nx=4, ny=3, m_a=4, m_b=40, cl_in=0.4, cl_out=0.4, theta=1, kn_out=0.3,
+                 dbb_r=1.0, periodic_x=True, periodic_y=True, mfp_off=True)
+    rng = _rng(4)
+    node = np.empty((2, 9))
+    node[0] = O.f_equilibrium(1.3, 0.04, -0.01, p.s[0]) * (1 + 0.1 * rng.standard_normal(9))
+    node[1] = O.f_equilibrium(9.0, -0.02, 0.015, p.s[1]) * (1 + 0.1 * rng.standard_normal(9))
+    f0 = np.broadcast_to(node[:, :, None, None], (2, 9, 3, 4)).copy()
+    rho_s = node.sum(1)
+    rho = rho_s.sum()
+    ux = (node @ O.CX).sum() / rho
+    uy = (node @ O.CY).sum() / rho
+    rt = O.relaxation_times(rho_s[0], rho_s[1], p, y=np.array(1.5))
+    taus = np.array([O.TAU_RHO, O.TAU_E, O.TAU_EPS, rt.tau_d, rt.tau_q, rt.tau_d, rt.tau_q,
+                     rt.tau_s, rt.tau_s], dtype=float)
+    f = f0
+    for t in range(1, 41):
+        f = O.step(f, p)
+        for sig in range(2):
+            m0 = O.M @ node[sig]
+            meq = O.M @ O.f_equilibrium(rho_s[sig], ux, uy, p.s[sig])
+            expect = meq + (1 - 1 / taus) ** t * (m0 - meq)
+            got = O.M @ f[sig, :, 1, 2]
+            assert np.allclose(got, expect, rtol=1e-11, atol=1e-13), (t, sig)
+    # velocity difference decays at rate (1 - 1/tau_d)
+    va = (O.CX @ f[0, :, 0, 0]) / rho_s[0]
+    vb = (O.CX @ f[1, :, 0, 0]) / rho_s[1]
+    va0 = (O.CX @ node[0]) / rho_s[0]
+    vb0 = (O.CX @ node[1]) / rho_s[1]
+    assert abs((va - vb) - (1 - 1 / rt.tau_d) ** 40 * (va0 - vb0)) < 1e-13
+
+
+# --- P5: psi and E1 (Sec. 3.1) ---------------------------------------------------
+def test_e1_against_mpmath():
+    xs = np.concatenate([np.geomspace(1e-6, 1, 40), np.linspace(1, 40, 80), [60.0, 120.0]])
+    ref = np.array([float(mpmath.e1(mpmath.mpf(float(x)))) for x in xs])
+    got = O.e1(xs)
+    assert np.max(np.abs(got - ref) / ref) < 5e-15
+
+
+def test_psi_is_one_minus_two_e3():
+    """psi(a) = 1 + (a-1)e^-a - a^2 E1(a) equals 1 - 2 E_3(a): the half-space
+    average over free-flight directions of a path truncated at distance a (in
+    mean free paths) from a wall. E_3 by mpmath's generalized exponential
+    integral, an independent routine."""
+    xs = np.concatenate([np.geomspace(1e-4, 1, 20), np.linspace(1.1, 30, 40)])
+    ref = np.array([1 - 2 * float(mpmath.expint(3, mpmath.mpf(float(x)))) for x in xs])
+    assert np.max(np.abs(O.psi(xs) - ref)) < 1e-14
+
+
+def test_psi_limits_and_derivative():
+    assert O.psi(np.array([0.0]))[0] == 0.0
+    assert abs(O.psi(np.array([1.0]))[0] - (1 - float(mpmath.e1(1)))) < 1e-15
+    assert abs(O.psi(np.array([60.0]))[0] - 1.0) < 1e-15
+    xs = np.array([1e-3, 0.3, 1.0, 2.5, 7.0, 20.0])
+    h = 1e-6
+    fd = (O.psi(xs + h) - O.psi(xs - h)) / (2 * h)
+    assert np.allclose(O.dpsi(xs), fd, atol=1e-8)
+    assert O.dpsi(np.array([0.0]))[0] == 2.0
+
+
+# --- P6: relaxation times ------------------------------------------------------------
+BASE = dict(nx=8, ny=8, m_a=4.0, m_b=40.0, cl_in=0.5, cl_out=0.5, theta=2.0, kn_out=0.1, dbb_r=1.16)
+
+
+def test_tau_s_consistent_with_mean_free_path_relation():
+    """Eq. (taos) inverts Eq. (EQFrb): lambda_e = sqrt(3 pi m_x/(2 m_min)) c_s^2 (tau_s - 1/2)
+    with lambda_e = lambda Psi(y)."""
+    rng = _rng(6)
+    p = O.Params(**BASE)
+    ra = rng.uniform(0.3, 2.0, (8, 5))
+    rb = rng.uniform(3.0, 12.0, (8, 5))
+    rt = O.relaxation_times(ra, rb, p)
+    y = (np.arange(8) + 0.5)[:, None]
+    lam_e = rt.lam * O.wall_function(y, rt.lam, 8.0)
+    back = np.sqrt(3 * math.pi * rt.m_x / (2 * p.m_min)) * O.CS2 * (rt.tau_s - 0.5)
+    assert np.allclose(back, lam_e, rtol=1e-14)
+
+
+def test_mean_free_path_scaling_and_partial_paths():
+    """R5/R6: lambda is Kn_out * H at the outlet pressure and varies as 1/P;
+    x_s lambda_s = lambda."""
+    p = O.Params(**BASE)
+    ra, rb = O.species_density(p, O.P_OUT, 0.5)
+    rt = O.relaxation_times(np.array([[ra]]), np.array([[rb]]), p, y=np.array([[0.5]]))
+    assert abs(rt.lam[0, 0] - 0.1 * 8) < 1e-15
+    ra2, rb2 = O.species_density(p, 2 * O.P_OUT, 0.5)
+    rt2 = O.relaxation_times(np.array([[ra2]]), np.array([[rb2]]), p, y=np.array([[0.5]]))
+    assert abs(rt2.lam[0, 0] - 0.4) < 1e-15
+
+
+def test_tau_d_symmetry_and_scaling():
+    """Eq. (EQFrsp) is symmetric under exchanging the species, invariant under
+    scaling every mass, and with Psi == 1 tau_d - 1/2 is proportional to lambda."""
+    rng = _rng(7)
+    ra = rng.uniform(0.5, 2.0, (8, 3))
+    rb = rng.uniform(3.0, 9.0, (8, 3))
+    p = O.Params(**BASE)
+    t1 = O.relaxation_times(ra, rb, p).tau_d
+    # k_B T = m_min c_s^2, so scaling every mass at fixed mass densities leaves
+    # x_s, P, lambda and the mass ratios -- hence tau_d -- unchanged
+    q = O.Params(**{**BASE, "m_a": 10.0, "m_b": 100.0})
+    t2 = O.relaxation_times(ra, rb, q).tau_d
+    assert np.allclose(t1, t2, rtol=1e-13)
+    # exchange of labels: equal masses so both orders are legal
+    pe = O.Params(**{**BASE, "m_a": 30.0, "m_b": 30.0})
+    ta = O.relaxation_times(ra, rb, pe).tau_d
+    tb = O.relaxation_times(rb, ra, pe).tau_d
+    assert np.allclose(ta, tb, rtol=1e-14)
+    # homogeneity in lambda with the MFP correction off
+    po = O.Params(**{**BASE, "mfp_off": True})
+    pk = O.Params(**{**BASE, "mfp_off": True, "kn_out": 0.3})
+    d1 = O.relaxation_times(ra, rb, po).tau_d - 0.5
+    d3 = O.relaxation_times(ra, rb, pk).tau_d - 0.5
+    assert np.allclose(d3, 3 * d1, rtol=1e-14)
+
+
+def test_tau_q_unbounded_limit_is_single_species_slip_relation():
+    """With Psi == 1 the wall derivative vanishes and Eq. (taoq) reduces to
+    tau_q = 1/2 + (3 + 4 pi tau~^2 A2)/(16 tau~) (24 varsigma^2 = 4 pi, R9)."""
+    a1, a2 = O.slip_constants(1.0)
+    assert abs(a1 - 0.8183) < 1e-15
+    for tt in (0.05, 0.3, 1.2, 7.0):
+        got = O.tau_q_formula(tt, 0.0, 1.0)
+        assert abs(got - (0.5 + (3 + 4 * math.pi * tt * tt * a2) / (16 * tt))) < 1e-13
+
+
+def test_tau_q_wall_values_are_limits_of_tau_s():
+    """R7/R8: tau~_s(0) and tau~'_s(0) in Eq. (taoq) are the value and the
+    y-derivative of tau_s(y) - 1/2 (Eq. (taos)) at the wall, at the node's
+    lambda and m_x. Checked by evaluating tau_s near y = 0."""
+    p = O.Params(**BASE)
+    ra, rb = 0.8, 8.5
+    rt_far = O.relaxation_times(np.array([[ra]]), np.array([[rb]]), p, y=np.array([[3.5]]))
+    lam = rt_far.lam[0, 0]
+    k = math.sqrt(6 * p.m_min / (math.pi * rt_far.m_x[0, 0]))
+    # psi'' ~ 2 ln(alpha) near 0, so a one-sided difference has error ~ h ln h
+    h = 1e-8
+    ts = [O.relaxation_times(np.array([[ra]]), np.array([[rb]]), p, y=np.array([[y]])).tau_s[0, 0] - 0.5
+          for y in (1e-300, h)]
+    tt0 = ts[0]
+    dtt0 = (ts[1] - ts[0]) / h
+    expect = O.tau_q_formula(tt0, dtt0, 1.0)
+    assert abs(rt_far.tau_q[0, 0] - expect) / expect < 2e-6
+    assert tt0 < lam * k  # the wall cuts the free paths
+
+
+# --- DBB (Eqs. (bot), (bot2)), P7 ----------------------------------------------------
+def test_dbb_returns_exactly_the_outgoing_mass():
+    """R12: zero normal mass flux at every wall node, for any r."""
+    rng = _rng(8)
+    for r in (0.0, 0.6, 1.16, 1.9):
+        p = O.Params(nx=7, ny=5, m_a=4, m_b=40, cl_in=0.5, cl_out=0.5, theta=1, kn_out=0.1,
+                     dbb_r=r, periodic_x=True)
+        fpost = rng.uniform(0.01, 1.0, (2, 9, 5, 7))
+        fnew = O.stream(fpost, p)
+        for sig in range(2):
+            assert np.allclose(fnew[sig, [2, 5, 6], 0].sum(0), fpost[sig, [4, 7, 8], 0].sum(0), rtol=1e-14)
+            assert np.allclose(fnew[sig, [4, 7, 8], 4].sum(0), fpost[sig, [2, 5, 6], 4].sum(0), rtol=1e-14)
+        if r == 0.0:  # plain half-way bounce-back
+            assert np.array_equal(fnew[:, 2, 0], fpost[:, 4, 0])
+            assert np.array_equal(fnew[:, 7, 4], fpost[:, 5, 4])
+
+
+def test_dbb_keeps_wall_equilibrium_at_rest():
+    """At rest the wall equilibrium of R12 is the species equilibrium itself, so
+    an equilibrium state at rest is a fixed point of stream + DBB for any r."""
+    for r in (0.3, 1.16):
+        p = O.Params(nx=6, ny=4, m_a=20, m_b=40, cl_in=0.3, cl_out=0.3, theta=1, kn_out=0.1,
+                     dbb_r=r, periodic_x=True)
+        f = O.initial_state(p)
+        assert np.allclose(O.stream(f, p), f, rtol=1e-15)
+
+
+@pytest.mark.parametrize("r", [0.0, 1.16])
+def test_species_mass_conserved_with_walls(r):
+    """Periodic ends + DBB walls: every species' total mass is conserved
+    (collision conserves rho_s; DBB passes no mass)."""
+    rng = _rng(9)
+    p = O.Params(nx=12, ny=6, m_a=4, m_b=40, cl_in=0.5, cl_out=0.5, theta=1, kn_out=0.1,
+                 dbb_r=r, periodic_x=True)
+    f = O.initial_state(p)
+    f = f * (1 + 0.02 * rng.standard_normal(f.shape))
+    m0 = f.sum(axis=(1, 2, 3))
+    f, _ = O.run(p, 400, f0=f)
+    m1 = f.sum(axis=(1, 2, 3))
+    assert np.all(np.abs(m1 - m0) / m0 < 1e-13)
+
+
+# --- Inlet/outlet (Eqs. (rho1), (rho2)), P8 -------------------------------------------
+def test_inlet_outlet_impose_mean_density_and_mole_fraction():
+    rng = _rng(10)
+    p = O.Params(nx=10, ny=6, m_a=4, m_b=40, cl_in=0.7, cl_out=0.3, theta=2.5, kn_out=0.2, dbb_r=1.1)
+    fpost = O.initial_state(p) * (1 + 0.03 * rng.standard_normal((2, 9, 6, 10)))
+    fnew = O.stream(fpost, p)
+    rin, rout = O.boundary_densities(p)
+    for sig in range(2):
+        assert abs(fnew[sig, :, :, 0].sum() / 6 - rin[sig]) < 1e-13 * rin[sig]
+        assert abs(fnew[sig, :, :, -1].sum() / 6 - rout[sig]) < 1e-13 * rout[sig]
+        # the column is a multiple of the linear extrapolation of the inner layers
+        ext = 2 * fnew[sig, :, :, 1] - fnew[sig, :, :, 2]
+        ratio = fnew[sig, :, :, 0] / ext
+        assert np.allclose(ratio, ratio.flat[0], rtol=1e-13)
+    d = O.diagnostics(fnew, p)
+    assert abs(d.cl_profile[0] - 0.7) < 1e-14 and abs(d.cl_profile[-1] - 0.3) < 1e-14
+
+
+def test_initial_state_has_zero_separation():
+    """R18 with C_in = C_out: C_l(x) = C_in everywhere, so CL(0) = 0."""
+    p = O.Params(nx=20, ny=5, m_a=4, m_b=40, cl_in=0.5, cl_out=0.5, theta=2, kn_out=0.1, dbb_r=1.16)
+    d = O.diagnostics(O.initial_state(p), p)
+    assert abs(d.cl) < 1e-15 and np.allclose(d.cl_profile, 0.5, atol=1e-15)
+
+
+# --- P9: equal masses ----------------------------------------------------------------
+def test_equal_masses_do_not_separate():
+    """m_a = m_b and C_in = C_out: the two species are the same gas, f_a/f_b stays
+    C/(1 - C) at every node and CL stays 0 (Eq. (CL))."""
+    p = O.Params(nx=30, ny=6, m_a=10, m_b=10, cl_in=0.3, cl_out=0.3, theta=2, kn_out=0.2, dbb_r=0.74)
+    f, _ = O.run(p, 300)
+    assert np.allclose(f[0] / f[1], 0.3 / 0.7, rtol=1e-12)
+    d = O.diagnostics(f, p)
+    assert abs(d.cl) < 1e-13 and abs(d.cl_tilde) < 1e-13
