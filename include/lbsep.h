@@ -1,0 +1,160 @@
+/*
+ * lbsep -- binary-gas-mixture lattice Boltzmann channel solver for MI355X (gfx950).
+ *
+ * C ABI of the hot path of Wang, Xu & Guo, "Lattice Boltzmann simulation of
+ * separation phenomenon in a binary gaseous flow through a microchannel"
+ * (arXiv:1603.08221):
+ *   - Sec. 2: an L x H channel between two reservoirs, pressure ratio theta,
+ *     light-species mole fraction C_l (Eq. (C)), outlet Knudsen number Kn_out;
+ *     separation degree CL (Eq. (CL)) and mean separation C~_l (Eq. (Clline)).
+ *   - Sec. 3.1: two coupled D2Q9 populations (Eq. (MRT)), MRT collision
+ *     (Eqs. (MR), (m), (S)) towards the species equilibrium built on the mixture
+ *     velocity (Eq. (feq)), effective relaxation times with the mean-free-path
+ *     wall function (Eqs. (EQFrb), (taos), (EQFrsp)).
+ *   - Sec. 3.2: diffuse-bounce-back walls (Eqs. (bot), (bot2), (taoq), (A12))
+ *     and the extrapolation-correction pressure inlet/outlet (Eqs. (rho1), (rho2)).
+ *
+ * Lattice units: delta_x = delta_t = 1, c_s^2 = 1/3, H = ny. Outlet pressure
+ * P_out = 1/3 (so that n_out * m_min = 1); P_in = theta * P_out.
+ *
+ * Conventions for every call:
+ *   - Return 0 on success, a negative LBSEP_E* code on failure; the message of
+ *     the last failure on the calling thread is in lbsep_last_error().
+ *   - No C++ exception crosses this boundary. The library never allocates
+ *     device memory: the caller owns the workspace and every host buffer; the
+ *     library owns only the small host-side handle.
+ *   - Work is enqueued on the HIP stream given to lbsep_init, in order. Calls
+ *     marked "synchronises" wait for that stream before returning.
+ *   - A handle is not thread-safe; use one handle per thread or serialise.
+ *
+ * State layout (lbsep_get_state / lbsep_set_state): populations of the
+ * pre-collision state f_si(x, y, t), dense, index ((s * 9 + i) * ny + j) * nx + x,
+ * s = 0 light species (a), 1 heavy (b); i in the D2Q9 order
+ * c_0..c_8 = (0,0) (1,0) (0,1) (-1,0) (0,-1) (1,1) (-1,1) (-1,-1) (1,-1);
+ * j = row across the channel (node centre y = j + 1/2, walls at y = 0 and y = ny);
+ * x = column along the flow (column 0 = inlet node, nx-1 = outlet node).
+ * Element type: double for LBSEP_F64, float for LBSEP_F32.
+ */
+#ifndef LBSEP_H
+#define LBSEP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ------------------------------------------------------- */
+#define LBSEP_OK 0
+#define LBSEP_EINVAL (-1)     /* an argument outside its documented range           */
+#define LBSEP_ESIZE (-2)      /* workspace smaller than lbsep_workspace_bytes()      */
+#define LBSEP_EDEVICE (-3)    /* a HIP runtime call failed                           */
+#define LBSEP_ENONFINITE (-4) /* the diagnostics saw NaN/Inf or a non-positive density */
+#define LBSEP_ERANGE (-5)     /* a requested history record is no longer kept       */
+
+/* ---- flags (lbsep_params.flags) -------------------------------------- */
+#define LBSEP_PERIODIC_X 0x1u /* no inlet/outlet: columns wrap (test mode)                   */
+#define LBSEP_PERIODIC_Y 0x2u /* no walls: rows wrap (test mode; requires LBSEP_MFP_OFF)      */
+#define LBSEP_MFP_OFF 0x4u    /* wall function Psi == 1 (unbounded mean free path)            */
+#define LBSEP_BGK_TEST 0x8u   /* every relaxation time = tau_bgk (BGK limit after Eq. (S))    */
+
+/* ---- storage / arithmetic type (lbsep_params.dtype) ------------------ */
+#define LBSEP_F64 0 /* populations stored and collided in double                         */
+#define LBSEP_F32 1 /* populations stored and collided in float; reductions in double    */
+
+/* Problem statement (Sec. 2) plus the DBB inputs of Sec. 3.2. */
+typedef struct lbsep_params {
+  int32_t nx;       /* columns along the flow (channel length L): >= 6, or >= 1 with PERIODIC_X */
+  int32_t ny;       /* rows across the channel (H = ny lattice units, the N of Eq. (taoq)): >= 2  */
+  double m_a;       /* molecular mass of the light species, > 0                                   */
+  double m_b;       /* molecular mass of the heavy species, >= m_a (only ratios matter)          */
+  double cl_in;     /* light-species mole fraction at the inlet, in (0, 1)                        */
+  double cl_out;    /* light-species mole fraction at the outlet, in (0, 1)                       */
+  double theta;     /* pressure ratio P_in / P_out, > 0                                          */
+  double kn_out;    /* Kn_out = lambda_out / H, > 0                                              */
+  double dbb_r;     /* DBB equilibrium fraction r of Eqs. (bot), (bot2), in [0, 2); both species */
+  double accom;     /* accommodation coefficient alpha of Eq. (A12), in (0, 1]                   */
+  double tau_bgk;   /* relaxation time for LBSEP_BGK_TEST, > 0.5; ignored otherwise             */
+  uint32_t flags;   /* LBSEP_PERIODIC_X | LBSEP_PERIODIC_Y | LBSEP_MFP_OFF | LBSEP_BGK_TEST      */
+  int32_t dtype;    /* LBSEP_F64 or LBSEP_F32                                                    */
+  int32_t hist_cap; /* per-step diagnostic records kept on the device (ring), >= 1               */
+} lbsep_params;
+
+typedef struct lbsep_channel lbsep_channel;
+
+/* Device workspace needed for these parameters (bytes, 256-byte aligned start
+ * required). Returns 0 if the parameters are invalid (see lbsep_last_error). */
+size_t lbsep_workspace_bytes(const lbsep_params* params);
+
+/* Bytes of one state (2 * 9 * ny * nx elements of the storage type). */
+size_t lbsep_state_bytes(const lbsep_params* params);
+
+/* Create a channel in the caller's device workspace and set the initial state:
+ * local equilibrium at rest with pressure and C_l linear in x between the
+ * inlet and outlet values. The diagnostics of t = 0 are recorded.
+ *   params      : copied; validated (LBSEP_EINVAL).
+ *   dev_ws      : device pointer, 256-byte aligned, ws_bytes >= lbsep_workspace_bytes.
+ *   hip_stream  : hipStream_t the channel enqueues on (NULL = default stream).
+ *   out         : receives the handle; *out is NULL on failure.
+ * Enqueues work; does not synchronise. */
+int lbsep_init(const lbsep_params* params, void* dev_ws, size_t ws_bytes, void* hip_stream,
+               lbsep_channel** out);
+
+/* Advance nsteps >= 0 time steps. Each step is one fused sweep: pull-streaming
+ * of both species (Eq. (MRT)), DBB at the walls (Eqs. (bot), (bot2)), the
+ * inlet/outlet correction (Eqs. (rho1), (rho2)), moments (Eq. (rhou)),
+ * relaxation times (Eqs. (taos), (EQFrsp), (taoq)), MRT collision
+ * (Eq. (MR)), and the reduction of the new state to C_l(x), CL and C~_l
+ * (Eqs. (C), (CL), (Clline)) recorded for that step. Enqueues only. */
+int lbsep_step(lbsep_channel* ch, int64_t nsteps);
+
+/* Current time level t (number of steps since the initial/loaded state plus its t). */
+int64_t lbsep_time(const lbsep_channel* ch);
+
+/* Diagnostics of the current state: CL (Eq. (CL)), C~_l (Eq. (Clline)), the
+ * column of the smallest C_l (first on ties), and optionally the profile
+ * C_l(x) (nx doubles) of Eq. (C) over each cross-section. Any pointer may be
+ * NULL. Synchronises. LBSEP_ENONFINITE if any step since init saw NaN/Inf or a
+ * non-positive column density. */
+int lbsep_read_cl(lbsep_channel* ch, double* cl, double* cl_tilde, int32_t* x_min, double* cl_profile);
+
+/* Column sums of the current state, host [4][nx]: sum_j n_a, sum_j n_b,
+ * sum_j rho_a u_ax, sum_j rho_b u_bx (species velocity of Eq. (rhou)).
+ * Synchronises. */
+int lbsep_read_column_sums(lbsep_channel* ch, double* host);
+
+/* Per-step records for time levels t0 .. t0+count-1, host [count][4]:
+ * (t, CL, C~_l, x_min). LBSEP_ERANGE if a level is older than the last
+ * hist_cap steps or newer than the current time. Synchronises. */
+int lbsep_read_history(lbsep_channel* ch, int64_t t0, int64_t count, double* host);
+
+/* Moments of the current state, host [6][ny][nx] doubles: rho_a, rho_b,
+ * u_ax, u_ay, u_bx, u_by (species velocities of Eq. (rhou)). Uses the
+ * workspace; synchronises. */
+int lbsep_read_moments(lbsep_channel* ch, double* host);
+
+/* Write the current pre-collision state (layout above) to device memory
+ * dev_dst (lbsep_state_bytes bytes). Enqueues only. */
+int lbsep_get_state(lbsep_channel* ch, void* dev_dst);
+
+/* Replace the state by dev_src (device, layout above, lbsep_state_bytes
+ * bytes) at time level t >= 0 and record its diagnostics. Enqueues only. */
+int lbsep_set_state(lbsep_channel* ch, const void* dev_src, int64_t t);
+
+/* DBB coefficient from a velocity slip coefficient c_m, Eq. (R) first form:
+ * r = 2 - 2 / (1 + (c_m / 3) sqrt(pi m_x / (2 k_B T))), k_B T = m_min c_s^2,
+ * m_x = cl m_a + (1 - cl) m_b. Returns NaN on invalid input. */
+double lbsep_dbb_r_from_cm(double c_m, double m_a, double m_b, double cl);
+
+/* Release the host handle (the workspace stays the caller's). NULL is a no-op. */
+void lbsep_destroy(lbsep_channel* ch);
+
+/* Message of the last failure on this thread ("" if none). */
+const char* lbsep_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBSEP_H */

@@ -409,18 +409,21 @@ def step(f: np.ndarray, p: Params) -> np.ndarray:
 # ---------------------------------------------------------------------------
 # Initial state (R18) and diagnostics (Eqs. (C), (CL), (Clline); R16).
 # ---------------------------------------------------------------------------
-def initial_state(p: Params) -> np.ndarray:
+def initial_state(p: Params, x0: int = 0, x1: int | None = None) -> np.ndarray:
     """Local equilibrium at rest with pressure and light mole fraction linear in
-    x between (P_in, C_l,in) at column 0 and (P_out, C_l,out) at column nx-1."""
-    x = np.arange(p.nx, dtype=np.float64)
+    x between (P_in, C_l,in) at column 0 and (P_out, C_l,out) at column nx-1
+    (R18). Optionally only the columns [x0, x1) of that state."""
+    x1 = p.nx if x1 is None else x1
+    x = np.arange(x0, x1, dtype=np.float64)
     frac = x / (p.nx - 1) if p.nx > 1 else np.zeros_like(x)
     pres = p_in(p) + (P_OUT - p_in(p)) * frac
     cl = p.cl_in + (p.cl_out - p.cl_in) * frac
     rho_a, rho_b = species_density(p, pres, cl)
-    f = np.empty((2, 9, p.ny, p.nx))
-    zeros = np.zeros((p.ny, p.nx))
-    f[0] = f_equilibrium(np.broadcast_to(rho_a, (p.ny, p.nx)), zeros, zeros, p.s[0])
-    f[1] = f_equilibrium(np.broadcast_to(rho_b, (p.ny, p.nx)), zeros, zeros, p.s[1])
+    nx = x1 - x0
+    f = np.empty((2, 9, p.ny, nx))
+    zeros = np.zeros((p.ny, nx))
+    f[0] = f_equilibrium(np.broadcast_to(rho_a, (p.ny, nx)), zeros, zeros, p.s[0])
+    f[1] = f_equilibrium(np.broadcast_to(rho_b, (p.ny, nx)), zeros, zeros, p.s[1])
     return f
 
 

@@ -1,0 +1,208 @@
+// Device arithmetic of one lattice node: the mean-free-path wall function,
+// the effective relaxation times and the MRT collision of one species.
+//
+// Paper: Wang, Xu & Guo, arXiv:1603.08221, Sec. 3.1 (Eqs. (MR), (m), (S),
+// (feq), (rhou), (EQFrb), (taos), (EQFrsp)) and Sec. 3.2 (Eqs. (taoq), (A12)).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "e1_table.h"
+
+namespace lbsep {
+
+// Precision traits: table, cut-off and math entry points per storage type.
+template <typename T> struct E1Traits;
+
+template <> struct E1Traits<double> {
+  static constexpr int kSeg = LBSEP_E1_F64_NSEG;
+  static constexpr int kDeg = LBSEP_E1_F64_DEG;
+  static constexpr int kSer = LBSEP_E1_F64_NSER;
+  __device__ static double ser(int k) { return lbsep_e1_series_f64[k]; }
+  __device__ static double cheb(int s, int k) { return lbsep_e1_cheb_f64[s][k]; }
+  __device__ static double ex(double a) { return exp(a); }
+  __device__ static double ln(double a) { return log(a); }
+  __device__ static double rsq(double a) { return 1.0 / sqrt(a); }
+};
+
+template <> struct E1Traits<float> {
+  static constexpr int kSeg = LBSEP_E1_F32_NSEG;
+  static constexpr int kDeg = LBSEP_E1_F32_DEG;
+  static constexpr int kSer = LBSEP_E1_F32_NSER;
+  __device__ static float ser(int k) { return lbsep_e1_series_f32[k]; }
+  __device__ static float cheb(int s, int k) { return lbsep_e1_cheb_f32[s][k]; }
+  __device__ static float ex(float a) { return expf(a); }
+  __device__ static float ln(float a) { return logf(a); }
+  __device__ static float rsq(float a) { return 1.0f / sqrtf(a); }
+};
+
+// psi(a) = 1 + (a - 1) e^-a - a^2 E1(a) (wall function of Sec. 3.1) and
+// h(a) = e^-a - a E1(a) = psi'(a) / 2.
+//   a <= 1      : E1 = -gamma - ln a + S(a), S the entire series (Horner).
+//   1 < a < 2^n : E1 = e^-a G(a) / a with G(a) = a e^a E1(a) from the octave's
+//                 Chebyshev interpolant (Clenshaw), so psi = 1 + e^-a (a - 1 - a G).
+//   beyond      : psi = 1 and h = 0 to the storage precision.
+template <typename T>
+__device__ __forceinline__ void wall_psi(T a, T& psi, T& h) {
+  using E = E1Traits<T>;
+  if (!(a > T(0))) {
+    psi = T(0);
+    h = T(1);
+    return;
+  }
+  if (a <= T(1)) {
+    T s = E::ser(E::kSer - 1);
+#pragma unroll
+    for (int k = E::kSer - 2; k >= 0; --k) s = s * a + E::ser(k);
+    s *= a;
+    const T e1 = -T(LBSEP_EULER_GAMMA) - E::ln(a) + s;
+    const T ea = E::ex(-a);
+    psi = T(1) + (a - T(1)) * ea - a * a * e1;
+    h = ea - a * e1;
+    return;
+  }
+  const int seg = ilogb(a);
+  if (seg >= E::kSeg) {
+    psi = T(1);
+    h = T(0);
+    return;
+  }
+  // t = (2a - 3 * 2^seg) / 2^seg, exact
+  const T t = ldexp(a, 1 - seg) - T(3);
+  const T t2 = t + t;
+  T b1 = T(0), b2 = T(0);
+#pragma unroll
+  for (int k = E::kDeg; k >= 1; --k) {
+    const T b0 = E::cheb(seg, k) + t2 * b1 - b2;
+    b2 = b1;
+    b1 = b0;
+  }
+  const T g = E::cheb(seg, 0) + t * b1 - b2;
+  const T ea = E::ex(-a);
+  psi = T(1) + ea * (a - T(1) - a * g);
+  h = ea * (T(1) - g);
+}
+
+template <typename T>
+__device__ __forceinline__ T wall_psi_only(T a) {
+  T p, h;
+  wall_psi(a, p, h);
+  return p;
+}
+
+// Constants derived on the host from the problem statement.
+struct RelaxConsts {
+  double inv_m[2];  // 1 / m_sigma
+  double s[2];      // s_sigma = m_min / m_sigma
+  double lam_p;     // lambda * P = Kn_out * H * P_out (mean free path at pressure P is lam_p / P)
+  double kpref;     // sqrt(6 m_min / pi): k = kpref / sqrt(m_x) in Eq. (taos)
+  double dpref;     // (3/2) sqrt(3 m_0 m_a m_b / m_min): Eq. (EQFrsp) prefactor times m_x
+  double tq_a;      // 24 varsigma^2 A2 (= 4 pi A2), Eq. (taoq)
+  double tq_b;      // 30 varsigma A1, Eq. (taoq)
+  double height;    // H = ny
+  double tau_bgk;
+  int mfp_off;
+  int bgk;
+};
+
+// Relaxation times of one node from its species densities (recomputed every
+// step from the pre-collision state).
+template <typename T>
+__device__ __forceinline__ void relaxation_times(const RelaxConsts& c, int j, T rho_a, T rho_b, T& tau_s,
+                                                 T& tau_d, T& tau_q) {
+  using E = E1Traits<T>;
+  if (c.bgk) {
+    tau_s = tau_d = tau_q = T(c.tau_bgk);
+    return;
+  }
+  const T na = rho_a * T(c.inv_m[0]);
+  const T nb = rho_b * T(c.inv_m[1]);
+  const T inv_n = T(1) / (na + nb);
+  const T xa = na * inv_n;
+  const T xb = nb * inv_n;
+  const T mx = (rho_a + rho_b) * inv_n;                                  // m_x = rho / n
+  const T pres = T(1.0 / 3.0) * (T(c.s[0]) * rho_a + T(c.s[1]) * rho_b);  // P = n k_B T
+  const T lam = T(c.lam_p) / pres;                                       // mean free path at P
+  const T k = T(c.kpref) * E::rsq(mx);                                   // sqrt(6 m_min / (pi m_x))
+  T psi_m, psi_a, psi_b, tt0, dtt0;
+  if (c.mfp_off) {
+    psi_m = psi_a = psi_b = T(1);
+    tt0 = k * lam;
+    dtt0 = T(0);
+  } else {
+    const T il = pres / T(c.lam_p);                                      // 1 / lambda
+    const T y = T(j) + T(0.5);
+    const T yb = T(c.height) - y;
+    const T ay = y * il, ab = yb * il;
+    psi_m = T(0.5) * (wall_psi_only(ay) + wall_psi_only(ab));
+    // lambda_sigma = lambda / x_sigma  ->  y / lambda_sigma = x_sigma y / lambda
+    psi_a = T(0.5) * (wall_psi_only(xa * ay) + wall_psi_only(xa * ab));
+    psi_b = T(0.5) * (wall_psi_only(xb * ay) + wall_psi_only(xb * ab));
+    // wall values for Eq. (taoq): tau~_s(0) = k lam psi(H/lam) / 2 and
+    // tau~'_s(0) = (k/2) (psi'(0) - psi'(H/lam)) = k (1 - h(H/lam))
+    T pw, hw;
+    wall_psi(T(c.height) * il, pw, hw);
+    tt0 = T(0.5) * k * lam * pw;
+    dtt0 = k * (T(1) - hw);
+  }
+  tau_s = T(0.5) + lam * psi_m * k;                                      // Eq. (taos)
+  const T sa = E::rsq(psi_a) + E::rsq(psi_b);
+  tau_d = T(0.5) + T(c.dpref) * lam / (mx * sa * sa);                     // Eq. (EQFrsp)
+  tau_q = T(0.5) + (T(3) + T(c.tq_a) * tt0 * tt0) / (T(16) * tt0) +
+          dtt0 * (T(12) + T(c.tq_b) * tt0) / (T(16) * tt0 * tt0);         // Eq. (taoq)
+}
+
+// MRT collision of one species in the moment space of Eq. (m):
+// m' = m - S (m - m^eq), f' = M^-1 m'. m^eq is the moment vector of Eq. (feq)
+// with the mixture velocity (ux, uy), in closed form:
+// (rho, rho(2s-4) + 3 rho|u|^2, rho(4-3s) - 3 rho|u|^2, rho ux, -rho ux,
+//  rho uy, -rho uy, rho(ux^2 - uy^2), rho ux uy).
+// M^-1 = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4).
+template <typename T>
+__device__ __forceinline__ void collide_species(T f[9], T rho, T ux, T uy, T s, T w_e, T w_eps, T w_d, T w_q,
+                                                T w_s) {
+  const T sa = f[1] + f[2] + f[3] + f[4];
+  const T sd = f[5] + f[6] + f[7] + f[8];
+  T e = T(-4) * f[0] - sa + T(2) * sd;
+  T eps = T(4) * f[0] - T(2) * sa + sd;
+  T jx = f[1] - f[3] + f[5] - f[6] - f[7] + f[8];
+  T qx = T(-2) * (f[1] - f[3]) + f[5] - f[6] - f[7] + f[8];
+  T jy = f[2] - f[4] + f[5] + f[6] - f[7] - f[8];
+  T qy = T(-2) * (f[2] - f[4]) + f[5] + f[6] - f[7] - f[8];
+  T pxx = f[1] - f[2] + f[3] - f[4];
+  T pxy = f[5] - f[6] + f[7] - f[8];
+
+  const T u2 = ux * ux + uy * uy;
+  const T jxe = rho * ux, jye = rho * uy;
+  e -= w_e * (e - (rho * (T(2) * s - T(4)) + T(3) * rho * u2));
+  eps -= w_eps * (eps - (rho * (T(4) - T(3) * s) - T(3) * rho * u2));
+  jx -= w_d * (jx - jxe);
+  qx -= w_q * (qx + jxe);
+  jy -= w_d * (jy - jye);
+  qy -= w_q * (qy + jye);
+  pxx -= w_s * (pxx - rho * (ux * ux - uy * uy));
+  pxy -= w_s * (pxy - rho * ux * uy);
+
+  const T a0 = rho * T(1.0 / 9.0);
+  const T a1 = e * T(1.0 / 36.0);
+  const T a2 = eps * T(1.0 / 36.0);
+  const T a3 = jx * T(1.0 / 6.0);
+  const T a4 = qx * T(1.0 / 12.0);
+  const T a5 = jy * T(1.0 / 6.0);
+  const T a6 = qy * T(1.0 / 12.0);
+  const T a7 = pxx * T(0.25);
+  const T a8 = pxy * T(0.25);
+  const T axis = a0 - a1 - T(2) * a2;
+  const T diag = a0 + T(2) * a1 + a2;
+  f[0] = a0 - T(4) * a1 + T(4) * a2;
+  f[1] = axis + a3 - T(2) * a4 + a7;
+  f[2] = axis + a5 - T(2) * a6 - a7;
+  f[3] = axis - a3 + T(2) * a4 + a7;
+  f[4] = axis - a5 + T(2) * a6 - a7;
+  f[5] = diag + a3 + a4 + a5 + a6 + a8;
+  f[6] = diag - a3 - a4 + a5 + a6 - a8;
+  f[7] = diag - a3 - a4 - a5 - a6 + a8;
+  f[8] = diag + a3 + a4 - a5 - a6 - a8;
+}
+
+}  // namespace lbsep

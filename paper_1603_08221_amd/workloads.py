@@ -1,0 +1,94 @@
+"""Seeded synthetic workloads: channel configurations and random input states.
+
+This module holds inputs only -- parameter sets shaped like the paper's runs
+and seeded random population fields -- and none of the method's arithmetic.
+It is the one module that both the HIP path (through the tests and the
+benchmark) and the CPU oracle (in tests) draw inputs from.
+
+The paper's workloads are themselves synthetic parameter cases (Sec. 2,
+Table 1: He-Ar with mass ratio 1:10 and Ne-Ar with 1:2, C_l in {0.3, 0.5, 0.7},
+theta in {2..5}, Kn_out in {0.3..5}, a 20 x 700 lattice), so no dataset stands
+behind them.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, replace
+
+import numpy as np
+
+# Velocity-slip coefficient used for the DBB coefficient r (Eq. (R)): the
+# paper's c_m comes from collision integrals that it does not give, so the
+# single-gas value A1 at full accommodation, (2 - 1)/1 * (1 - 0.1817), is used.
+C_M_DEFAULT = 0.8183
+
+HE_AR = (4.0, 40.0)   # He : Ar = 1 : 10
+NE_AR = (20.0, 40.0)  # Ne : Ar = 1 : 2
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    nx: int
+    ny: int
+    m_a: float
+    m_b: float
+    cl_in: float
+    cl_out: float
+    theta: float
+    kn_out: float
+    steps: int
+    dtype: str = "f64"
+    c_m: float = C_M_DEFAULT
+    accom: float = 1.0
+
+    def with_(self, **kw) -> "Workload":
+        return replace(self, **kw)
+
+    @property
+    def nodes(self) -> int:
+        return self.nx * self.ny
+
+
+CONFIGS = {
+    # plain FP64 parity case: He-Ar, H = 8, L = 80, C = 0.5, theta = 2, Kn_out = 0.1, 2000 steps
+    "he_ar_8x80": Workload("he_ar_8x80", 80, 8, *HE_AR, 0.5, 0.5, 2.0, 0.1, 2000, "f64"),
+    # single channel FP32 vs FP64: Ne-Ar, H = 64, L = 1280, C = 0.3, theta = 3, Kn_out = 0.05
+    "ne_ar_64x1280": Workload("ne_ar_64x1280", 1280, 64, *NE_AR, 0.3, 0.3, 3.0, 0.05, 50000, "f32"),
+    # reduced-precision storage case: He-Ar, H = 256, L = 5120, C = 0.5, theta = 2, Kn_out = 0.2
+    "he_ar_256x5120": Workload("he_ar_256x5120", 5120, 256, *HE_AR, 0.5, 0.5, 2.0, 0.2, 100000, "f32"),
+    # adjoint case: He-Ar, H = 64, L = 1280, C = 0.5, theta = 2.5, Kn_out = 0.1, 10k steps
+    "he_ar_64x1280": Workload("he_ar_64x1280", 1280, 64, *HE_AR, 0.5, 0.5, 2.5, 0.1, 10000, "f64"),
+    # bandwidth probe above the 256 MB last-level cache: He-Ar, 512 x 10240
+    "he_ar_512x10240": Workload("he_ar_512x10240", 10240, 512, *HE_AR, 0.5, 0.5, 2.0, 0.2, 2000, "f32"),
+    # the paper's own geometry, Case 2 at Kn_out = 0.3, theta = 2 (Table 1, 20 x 700)
+    "paper_case2_20x700": Workload("paper_case2_20x700", 700, 20, *HE_AR, 0.5, 0.5, 2.0, 0.3, 20000, "f64"),
+}
+
+
+def batch_instances(n: int = 64, seed: int = 160308221):
+    """The batched-sweep table: n channels with seeded uneven sizes and
+    parameters (pair He-Ar / Ne-Ar with p = 1/2, H in {16..128}, L = 20 H,
+    C_l ~ U[0.1, 0.9] with C_out = C_in, theta ~ U[1.5, 4], Kn_out log-uniform
+    in [0.01, 1])."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n):
+        pair = HE_AR if rng.random() < 0.5 else NE_AR
+        h = int(rng.choice([16, 32, 48, 64, 96, 128]))
+        c = float(rng.uniform(0.1, 0.9))
+        out.append(Workload(f"inst{k:02d}", 20 * h, h, *pair, c, c, float(rng.uniform(1.5, 4.0)),
+                            float(10 ** rng.uniform(-2, 0)), 20000, "f32"))
+    return out
+
+
+def random_state(ny: int, nx: int, seed: int, scale=(1.0, 8.0), spread: float = 0.2,
+                 uniform: bool = False) -> np.ndarray:
+    """A seeded positive population field (2, 9, ny, nx) in float64: species
+    sigma gets scale[sigma] * (1 + spread * U(-1, 1)) per population. With
+    uniform=True every node holds the same values (a homogeneous box)."""
+    rng = np.random.default_rng(seed)
+    shape = (2, 9, 1, 1) if uniform else (2, 9, ny, nx)
+    f = 1.0 + spread * rng.uniform(-1.0, 1.0, size=shape)
+    f[0] *= scale[0] / 9.0
+    f[1] *= scale[1] / 9.0
+    return np.ascontiguousarray(np.broadcast_to(f, (2, 9, ny, nx)))

@@ -1,0 +1,48 @@
+"""Shared helpers of the GPU parity tests: build oracle parameters and runs from
+the same workload description the HIP path gets, and compare results."""
+import numpy as np
+
+from oracle import binary_lbm as O
+from paper_1603_08221_amd import lbsep
+
+FLAG_NAMES = {"periodic_x": lbsep.PERIODIC_X, "periodic_y": lbsep.PERIODIC_Y, "mfp_off": lbsep.MFP_OFF}
+
+
+def oracle_params(w, r, **modes):
+    return O.Params(nx=w.nx, ny=w.ny, m_a=w.m_a, m_b=w.m_b, cl_in=w.cl_in, cl_out=w.cl_out, theta=w.theta,
+                    kn_out=w.kn_out, dbb_r=r, accom=w.accom, **modes)
+
+
+def channel(w, r, dtype="f64", tau_bgk=None, hist_cap=4096, **modes):
+    flags = 0
+    for k, v in modes.items():
+        if v:
+            flags |= FLAG_NAMES[k]
+    if tau_bgk is not None:
+        flags |= lbsep.BGK_TEST
+    p = lbsep.make_params(w.nx, w.ny, w.m_a, w.m_b, w.cl_in, w.cl_out, w.theta, w.kn_out, r, accom=w.accom,
+                          tau_bgk=tau_bgk or 0.0, flags=flags, dtype=dtype, hist_cap=hist_cap)
+    return lbsep.Channel(p, device="cuda:0")
+
+
+def r_of(w):
+    """DBB coefficient of the workload, from the oracle's Eq. (R) (the same
+    number is handed to both sides)."""
+    return O.dbb_r_from_cm(w.c_m, w.m_a, w.m_b, w.cl_in)
+
+
+def field_errors(got, ref):
+    """Normwise relative error per moment field: max|got - ref| / max|ref|."""
+    return [float(np.max(np.abs(got[k] - ref[k])) / max(np.max(np.abs(ref[k])), 1e-300)) for k in range(len(ref))]
+
+
+def assert_moments(got, ref, tol, what=""):
+    errs = field_errors(got, ref)
+    names = ["rho_a", "rho_b", "u_ax", "u_ay", "u_bx", "u_by"]
+    bad = {names[k]: e for k, e in enumerate(errs) if not e <= tol}
+    assert not bad, f"{what}: moment fields beyond {tol:g}: {bad}"
+    return max(errs)
+
+
+def assert_cl(got, ref, rel, abs_):
+    assert abs(got - ref) <= rel * abs(ref) + abs_, (got, ref)

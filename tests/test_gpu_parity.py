@@ -1,0 +1,250 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Tolerances: FP64 storage 1e-12 normwise relative on every moment field and
+relative on CL (absolute 1e-14 when CL is ~0); FP32 storage 1e-5 normwise
+relative on moments and absolute on CL.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import binary_lbm as O
+from paper_1603_08221_amd import lbsep
+from paper_1603_08221_amd.workloads import CONFIGS, HE_AR, NE_AR, Workload, random_state
+
+from gpu_helpers import assert_cl, assert_moments, channel, oracle_params, r_of
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 1e-5
+
+
+def _run_both(w, steps, dtype="f64", **modes):
+    r = r_of(w)
+    ch = channel(w, r, dtype=dtype, **modes)
+    ch.step(steps)
+    mom = ch.read_moments()
+    cl = ch.read_cl(profile=True)
+    p = oracle_params(w, r, **modes)
+    f, _ = O.run(p, steps)
+    return ch, mom, cl, O.moment_fields(f, p), O.diagnostics(f, p)
+
+
+def test_fp64_he_ar_8x80_2000_steps():
+    w = CONFIGS["he_ar_8x80"]
+    print(f"[case] fp64 {w.name} {w.steps} steps", flush=True)
+    ch, mom, cl, ref, d = _run_both(w, w.steps)
+    err = assert_moments(mom, ref, TOL64, w.name)
+    assert_cl(cl["cl"], d.cl, TOL64, 1e-14)
+    assert_cl(cl["cl_tilde"], d.cl_tilde, TOL64, 1e-14)
+    assert cl["x_min"] == d.x_min
+    assert np.max(np.abs(cl["profile"] - d.cl_profile)) < 1e-13
+    sums = ch.read_column_sums()
+    assert np.allclose(sums[0], d.n_a, rtol=1e-12) and np.allclose(sums[1], d.n_b, rtol=1e-12)
+    assert np.allclose(sums[2], d.j_a, rtol=1e-10, atol=1e-13)
+    print(f"max field error {err:.2e}, CL {cl['cl']:.12e} vs {d.cl:.12e}")
+
+
+def test_fp64_history_matches_oracle_per_step():
+    w = CONFIGS["he_ar_8x80"]
+    r = r_of(w)
+    ch = channel(w, r)
+    ch.step(60)
+    hist = ch.read_history(0, 61)
+    assert np.array_equal(hist[:, 0], np.arange(61))
+    p = oracle_params(w, r)
+    f = O.initial_state(p)
+    d0 = O.diagnostics(f, p)
+    assert abs(hist[0, 1] - d0.cl) < 1e-14
+    for t in range(1, 61):
+        f = O.step(f, p)
+        d = O.diagnostics(f, p)
+        assert_cl(hist[t, 1], d.cl, TOL64, 1e-14)
+        assert_cl(hist[t, 2], d.cl_tilde, TOL64, 1e-14)
+        assert int(hist[t, 3]) == d.x_min
+
+
+@pytest.mark.parametrize("nx,ny,pair,cin,cout,theta,kn,steps", [
+    (150, 13, NE_AR, 0.3, 0.7, 3.0, 0.05, 300),    # ragged x tail, ragged rows, C_in != C_out
+    (200, 40, HE_AR, 0.7, 0.3, 2.0, 1.0, 200),     # several row tiles, high Kn
+    (40, 6, HE_AR, 0.3, 0.3, 4.0, 0.3, 300),       # one column strip holds both ends
+    (6, 2, NE_AR, 0.5, 0.5, 2.0, 0.5, 200),        # smallest channel
+    (333, 24, HE_AR, 0.5, 0.5, 5.0, 0.01, 150),    # tiny mean free path, large tau_q
+])
+def test_fp64_ragged_and_edge_shapes(nx, ny, pair, cin, cout, theta, kn, steps):
+    w = Workload("edge", nx, ny, *pair, cin, cout, theta, kn, steps)
+    print(f"[case] fp64 edge {nx}x{ny} {steps} steps", flush=True)
+    ch, mom, cl, ref, d = _run_both(w, steps)
+    assert_moments(mom, ref, TOL64, f"{nx}x{ny}")
+    assert_cl(cl["cl"], d.cl, TOL64, 1e-14)
+    assert cl["x_min"] == d.x_min
+
+
+def test_fp32_he_ar_8x80():
+    w = CONFIGS["he_ar_8x80"]
+    print("[case] fp32 he_ar_8x80 2000 steps", flush=True)
+    ch, mom, cl, ref, d = _run_both(w, w.steps, dtype="f32")
+    assert_moments(mom, ref, TOL32, "fp32")
+    assert abs(cl["cl"] - d.cl) < TOL32
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", TOL64), ("f32", TOL32)])
+def test_full_size_ne_ar_64x1280(dtype, tol):
+    """The benchmark's channel at its real size and launch configuration."""
+    w = CONFIGS["ne_ar_64x1280"]
+    steps = 40
+    print(f"[case] {dtype} {w.name} {steps} steps", flush=True)
+    ch, mom, cl, ref, d = _run_both(w, steps, dtype=dtype)
+    assert_moments(mom, ref, tol, w.name)
+    assert abs(cl["cl"] - d.cl) <= (tol * abs(d.cl) + 1e-14 if dtype == "f64" else tol)
+
+
+def _oracle_window(w, r, x0, x1, k):
+    """Oracle on the columns [x0, x1) of the full channel after k steps, from a
+    window wide enough that its artificial edges cannot reach [x0, x1)."""
+    pad = k + 3
+    lo, hi = max(0, x0 - pad), min(w.nx, x1 + pad)
+    f0 = O.initial_state(oracle_params(w, r), lo, hi)
+    pw = oracle_params(w.with_(nx=hi - lo), r)
+    f, _ = O.run(pw, k, f0=f0)
+    mf = O.moment_fields(f, pw)
+    return mf[..., x0 - lo:x1 - lo]
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", TOL64), ("f32", TOL32)])
+def test_largest_channel_sampled_windows(dtype, tol):
+    """512 x 10240 (the bandwidth probe): the oracle computes windows at the
+    inlet, the middle and the outlet column by column from the same initial
+    state; the GPU runs the whole channel."""
+    w = CONFIGS["he_ar_512x10240"]
+    r = r_of(w)
+    k = 12
+    print(f"[case] {dtype} {w.name} {k} steps, windows", flush=True)
+    ch = channel(w, r, dtype=dtype)
+    ch.step(k)
+    mom = ch.read_moments()
+    for x0, x1 in ((0, 40), (5100, 5164), (w.nx - 40, w.nx)):
+        ref = _oracle_window(w, r, x0, x1, k)
+        assert_moments(mom[..., x0:x1], ref, tol, f"window {x0}:{x1}")
+    del ch
+    torch.cuda.empty_cache()
+
+
+# ---- pins through the ABI ------------------------------------------------------
+def test_homogeneous_relaxation_through_abi():
+    """Periodic box, MFP off, uniform state: moments decay geometrically at
+    the rates 1/tau_k (oracle's tau of this state)."""
+    w = Workload("box", 16, 4, *HE_AR, 0.4, 0.4, 1.0, 0.3, 40)
+    r = 1.0
+    ch = channel(w, r, periodic_x=True, periodic_y=True, mfp_off=True)
+    f0 = random_state(4, 16, seed=11, uniform=True)
+    ch.set_state(torch.from_numpy(f0).cuda(), t=0)
+    ch.step(40)
+    got = ch.get_state().cpu().numpy()
+    p = oracle_params(w, r, periodic_x=True, periodic_y=True, mfp_off=True)
+    node = f0[:, :, 0, 0]
+    rho_s = node.sum(1)
+    rho = rho_s.sum()
+    ux, uy = (node @ O.CX).sum() / rho, (node @ O.CY).sum() / rho
+    rt = O.relaxation_times(rho_s[0], rho_s[1], p, y=np.array(0.5))
+    taus = np.array([O.TAU_RHO, O.TAU_E, O.TAU_EPS, rt.tau_d, rt.tau_q, rt.tau_d, rt.tau_q, rt.tau_s, rt.tau_s])
+    for s in range(2):
+        m0 = O.M @ node[s]
+        meq = O.M @ O.f_equilibrium(rho_s[s], ux, uy, p.s[s])
+        expect = meq + (1 - 1 / taus) ** 40 * (m0 - meq)
+        assert np.allclose(O.M @ got[s, :, 2, 5], expect, rtol=1e-11, atol=1e-13)
+
+
+def test_species_mass_conserved_with_walls_through_abi():
+    w = Workload("walls", 96, 10, *HE_AR, 0.5, 0.5, 1.0, 0.1, 2000)
+    r = 1.16
+    ch = channel(w, r, periodic_x=True)
+    f0 = random_state(10, 96, seed=12)
+    ch.set_state(torch.from_numpy(f0).cuda(), t=0)
+    m0 = f0.sum(axis=(1, 2, 3))
+    ch.step(2000)
+    m1 = ch.get_state().double().sum(dim=(1, 2, 3)).cpu().numpy()
+    assert np.all(np.abs(m1 - m0) / m0 < 1e-13)
+
+
+def test_equal_masses_do_not_separate_through_abi():
+    w = Workload("same", 100, 8, 10.0, 10.0, 0.3, 0.3, 2.0, 0.2, 500)
+    ch = channel(w, 0.74)
+    ch.step(500)
+    cl = ch.read_cl()
+    assert abs(cl["cl"]) < 1e-13 and abs(cl["cl_tilde"]) < 1e-13
+    f = ch.get_state().cpu().numpy()
+    assert np.allclose(f[0] / f[1], 0.3 / 0.7, rtol=1e-12)
+
+
+@pytest.mark.parametrize("mode", ["bgk", "periodic_y", "periodic_x_random"])
+def test_test_modes_match_oracle(mode):
+    rng_state = random_state(12, 70, seed=13)
+    w = Workload("mode", 70, 12, *NE_AR, 0.4, 0.4, 1.5, 0.2, 300)
+    r = 0.9
+    if mode == "bgk":
+        ch = channel(w, r, tau_bgk=0.8)
+        p = oracle_params(w, r, tau_bgk=0.8)
+        f, _ = O.run(p, 300)
+        ch.step(300)
+    else:
+        modes = dict(periodic_y=True, mfp_off=True) if mode == "periodic_y" else dict(periodic_x=True)
+        ch = channel(w, r, **modes)
+        p = oracle_params(w, r, **modes)
+        ch.set_state(torch.from_numpy(rng_state).cuda(), t=0)
+        f, _ = O.run(p, 300, f0=rng_state)
+        ch.step(300)
+    assert_moments(ch.read_moments(), O.moment_fields(f, p), TOL64, mode)
+
+
+# ---- state handling, determinism, errors ----------------------------------------------
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_state_roundtrip_resumes_bitwise(dtype):
+    w = CONFIGS["he_ar_8x80"].with_(nx=130, ny=9)
+    r = r_of(w)
+    a = channel(w, r, dtype=dtype)
+    a.step(100)
+    snap = a.get_state()
+    b = channel(w, r, dtype=dtype)
+    b.set_state(snap, t=a.t)
+    assert torch.equal(b.get_state(), snap)
+    a.step(50)
+    b.step(50)
+    assert a.t == b.t == 150
+    assert torch.equal(a.get_state(), b.get_state())
+    assert a.read_cl() == b.read_cl()
+
+
+def test_two_runs_are_bitwise_identical():
+    w = CONFIGS["ne_ar_64x1280"]
+    r = r_of(w)
+    out = []
+    for _ in range(2):
+        ch = channel(w, r, dtype="f64")
+        ch.step(200)
+        out.append((ch.read_moments(), ch.read_cl(profile=True)))
+    assert np.array_equal(out[0][0], out[1][0])
+    assert out[0][1]["cl"] == out[1][1]["cl"] and np.array_equal(out[0][1]["profile"], out[1][1]["profile"])
+
+
+def test_error_paths():
+    w = CONFIGS["he_ar_8x80"]
+    ch = channel(w, r_of(w), hist_cap=16)
+    ch.step(40)
+    with pytest.raises(lbsep.LbsepError) as e:
+        ch.read_history(0, 5)
+    assert e.value.code == lbsep.ERANGE
+    assert ch.read_history(25, 16).shape == (16, 4)
+    with pytest.raises(lbsep.LbsepError) as e:
+        ch.read_history(30, 20)
+    assert e.value.code == lbsep.ERANGE
+    bad = random_state(w.ny, w.nx, seed=3)
+    bad[1, 4, 3, 17] = np.nan
+    ch.set_state(torch.from_numpy(bad).cuda(), t=0)
+    ch.step(2)
+    with pytest.raises(lbsep.LbsepError) as e:
+        ch.read_cl()
+    assert e.value.code == lbsep.ENONFINITE
+    with pytest.raises(ValueError):
+        ch.set_state(torch.zeros(3, device="cuda"), 0)
