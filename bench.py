@@ -1,0 +1,215 @@
+"""Benchmark of the fused binary-mixture LBM step on one MI355X.
+
+Workload (default): the single Ne-Ar channel, H = 64, L = 1280 (81,920 nodes),
+C_l = 0.3, theta = 3, Kn_out = 0.05, populations initialised at local
+equilibrium with a linear pressure drop. A step is one fused sweep: both
+species pulled, DBB walls, inlet/outlet correction, moments, relaxation times,
+MRT collision and the FP64 reduction to C_l(x), CL and C~_l.
+
+Prints one JSON line: the FP32 path's throughput in node-MLUPS (one update =
+one node with both species' 9 populations), next to the plain FP64 path, the
+CL error of FP32 against FP64, the FP64 path against the CPU oracle on a short
+run, the roofline of the sweep kernel and the CPU oracle baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+BYTES_PER_POP = {"f64": 8, "f32": 4, "f16": 2}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_traffic.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1603_08221_amd", "csrc", n)
+                  for n in ("lbsep.hip", "lbsep_device.h", "e1_table.h")]
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str, dtype: str):
+    """HBM bytes per launch from the committed rocprofv3 PMC summary, if it was
+    taken on the current kernel source; else None."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    want = source_hash()
+    for line in open(TRAFFIC_FILE):
+        if line.startswith("#") or not line.strip():
+            continue
+        kv = dict(tok.split("=", 1) for tok in line.split())
+        if kv.get("workload") == workload and kv.get("dtype") == dtype and kv.get("source") == want:
+            return float(kv["bytes_per_launch"])
+    return None
+
+
+def make_channel(lbsep, w, dtype, hist_cap=1024):
+    r = lbsep.dbb_r_from_cm(w.c_m, w.m_a, w.m_b, w.cl_in)
+    p = lbsep.make_params(w.nx, w.ny, w.m_a, w.m_b, w.cl_in, w.cl_out, w.theta, w.kn_out, r, accom=w.accom,
+                          dtype=dtype, hist_cap=hist_cap)
+    return lbsep.Channel(p, device="cuda:0"), r
+
+
+def time_steps(torch, ch, steps):
+    """Run exactly `steps` sweeps between two stream synchronisations; return
+    (wall seconds, event milliseconds on the channel's stream)."""
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record(ch.stream)
+    ch.step(steps)
+    end.record(ch.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, start.elapsed_time(end)
+
+
+def cpu_baseline(w, r, seconds: float):
+    """The CPU oracle as it stands, on the same workload, for a bounded number
+    of steps (about `seconds` of CPU work), single BLAS thread."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import binary_lbm as O
+
+    p = O.Params(nx=w.nx, ny=w.ny, m_a=w.m_a, m_b=w.m_b, cl_in=w.cl_in, cl_out=w.cl_out, theta=w.theta,
+                 kn_out=w.kn_out, dbb_r=r, accom=w.accom)
+    with threadpool_limits(limits=1):
+        f = O.initial_state(p)
+        t0 = time.perf_counter()
+        n = 0
+        while time.perf_counter() - t0 < seconds:
+            f = O.step(f, p)
+            n += 1
+        dt = time.perf_counter() - t0
+    return {"value": w.nodes * n / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"{n} steps of {w.name} ({w.ny}x{w.nx}) from the initial state, NumPy FP64, "
+                      f"{dt:.1f} s, 1 BLAS thread"}
+
+
+def oracle_parity(lbsep, w, r, steps: int):
+    """CL and moments of the GPU FP64 path against the oracle after `steps` steps."""
+    import numpy as np
+
+    from oracle import binary_lbm as O
+
+    p = O.Params(nx=w.nx, ny=w.ny, m_a=w.m_a, m_b=w.m_b, cl_in=w.cl_in, cl_out=w.cl_out, theta=w.theta,
+                 kn_out=w.kn_out, dbb_r=r, accom=w.accom)
+    f, _ = O.run(p, steps)
+    d = O.diagnostics(f, p)
+    ref = O.moment_fields(f, p)
+    ch, _ = make_channel(lbsep, w, "f64")
+    ch.step(steps)
+    mom = ch.read_moments()
+    cl = ch.read_cl()["cl"]
+    rho_err = max(float(np.max(np.abs(mom[k] - ref[k])) / np.max(np.abs(ref[k]))) for k in (0, 1))
+    return {"steps": steps, "cl_abs_err": abs(cl - d.cl), "rho_rel_err": rho_err}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--warmup", type=int, default=1000)
+    ap.add_argument("--workload", default="ne_ar_64x1280")
+    ap.add_argument("--dtype", default="f32", choices=["f32", "f16", "f64"])
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 reference leg (profiling runs)")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="only run a plain device copy of this size (PMC calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs one channel on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+
+    from paper_1603_08221_amd import lbsep
+    from paper_1603_08221_amd.workloads import CONFIGS
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_calibration_mib:
+        n = args.copy_calibration_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": 5}))
+        return
+
+    w = CONFIGS[args.workload]
+    ch, r = make_channel(lbsep, w, args.dtype)
+    ch.step(args.warmup)
+    torch.cuda.synchronize()
+    wall, ev_ms = time_steps(torch, ch, args.steps)
+    t_total = ch.t
+    cl32 = ch.read_cl()
+    mlups = w.nodes * args.steps / wall / 1e6
+    per_launch_s = ev_ms / 1e3 / args.steps
+    alg_bytes = w.nodes * 36 * BYTES_PER_POP[args.dtype]
+    achieved = alg_bytes / per_launch_s / 1e9
+
+    out = {
+        "metric": "MLUPS (both species) + achieved HBM GB/s vs FP64 plain, at CL error <=1e-5",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.dtype != "f64" else "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "nx": w.nx, "ny": w.ny, "mixture": "Ne-Ar" if w.m_a == 20 else "He-Ar",
+                   "cl_in": w.cl_in, "theta": w.theta, "kn_out": w.kn_out, "dbb_r": r,
+                   "storage": {"f32": "f32 deviation", "f16": "f16 deviation", "f64": "f64"}[args.dtype],
+                   "parallelism": "single GPU"},
+        "gbps_algorithmic": round(achieved, 1),
+        "cl": cl32["cl"],
+        "t_final": t_total,
+    }
+
+    traffic = measured_traffic(w.name, args.dtype)
+    out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": round(achieved / HBM_PEAK_GBS, 4),
+                       "traffic": None if traffic is None else round(traffic)}
+    out["roofline_note"] = (f"sweep kernel, algorithmic bytes {alg_bytes} per launch "
+                            f"(36 populations x {BYTES_PER_POP[args.dtype]} B x {w.nodes} nodes) / "
+                            f"{per_launch_s * 1e6:.2f} us mean launch time (HIP events on the channel stream)")
+
+    if not args.no_fp64:
+        ch64, _ = make_channel(lbsep, w, "f64")
+        ch64.step(args.warmup)
+        wall64, ev64 = time_steps(torch, ch64, args.steps)
+        cl64 = ch64.read_cl()
+        out["fp64"] = {"mlups": round(w.nodes * args.steps / wall64 / 1e6, 1),
+                       "ms_per_step": wall64 * 1e3 / args.steps,
+                       "gbps_algorithmic": round(w.nodes * 288 / (ev64 / 1e3 / args.steps) / 1e9, 1),
+                       "cl": cl64["cl"]}
+        out["cl_err_vs_fp64"] = abs(cl32["cl"] - cl64["cl"])
+        out["cl_ok"] = out["cl_err_vs_fp64"] <= 1e-5
+        del ch64
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, r, args.cpu_seconds)
+        out["fp64_vs_oracle"] = oracle_parity(lbsep, w, r, 100)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -27,13 +27,22 @@
  *     marked "synchronises" wait for that stream before returning.
  *   - A handle is not thread-safe; use one handle per thread or serialise.
  *
- * State layout (lbsep_get_state / lbsep_set_state): populations of the
- * pre-collision state f_si(x, y, t), dense, index ((s * 9 + i) * ny + j) * nx + x,
- * s = 0 light species (a), 1 heavy (b); i in the D2Q9 order
- * c_0..c_8 = (0,0) (1,0) (0,1) (-1,0) (0,-1) (1,1) (-1,1) (-1,-1) (1,-1);
- * j = row across the channel (node centre y = j + 1/2, walls at y = 0 and y = ny);
- * x = column along the flow (column 0 = inlet node, nx-1 = outlet node).
- * Element type: double for LBSEP_F64, float for LBSEP_F32.
+ * Population layout (lbsep_get_populations / lbsep_set_populations, and the
+ * raw state of lbsep_get_state / lbsep_set_state): dense, element
+ * ((s * 9 + i) * ny + j) * nx + x, s = 0 light species (a), 1 heavy (b); i in
+ * the D2Q9 order c_0..c_8 = (0,0) (1,0) (0,1) (-1,0) (0,-1) (1,1) (-1,1)
+ * (-1,-1) (1,-1); j = row across the channel (node centre y = j + 1/2, walls
+ * at y = 0 and y = ny); x = column along the flow (column 0 = inlet node,
+ * nx-1 = outlet node). Populations are the pre-collision state f_si(x, y, t).
+ *
+ * Storage types (lbsep_params.dtype):
+ *   LBSEP_F64: f stored and collided in double. The raw state is f (double).
+ *   LBSEP_F32, LBSEP_F16: the deviation d = f - f0 from the rest equilibrium
+ *     f0_si(x) = w_i alpha_si rho0_s(x) (Eq. (feq) at u = 0), with rho0_s linear
+ *     in x from rho_s,in at x = 0 to rho_s,out at x = nx-1 (constant rho_s,in
+ *     with LBSEP_PERIODIC_X), is stored as float / IEEE binary16 and collided in
+ *     float. The raw state is d in the storage type (4 / 2 bytes).
+ * Column sums, CL and C~_l are always reduced in double.
  */
 #ifndef LBSEP_H
 #define LBSEP_H
@@ -60,8 +69,9 @@ extern "C" {
 #define LBSEP_BGK_TEST 0x8u   /* every relaxation time = tau_bgk (BGK limit after Eq. (S))    */
 
 /* ---- storage / arithmetic type (lbsep_params.dtype) ------------------ */
-#define LBSEP_F64 0 /* populations stored and collided in double                         */
-#define LBSEP_F32 1 /* populations stored and collided in float; reductions in double    */
+#define LBSEP_F64 0 /* populations stored and collided in double                              */
+#define LBSEP_F32 1 /* deviations from the rest equilibrium stored and collided in float     */
+#define LBSEP_F16 2 /* deviations stored as IEEE binary16, collided in float                 */
 
 /* Problem statement (Sec. 2) plus the DBB inputs of Sec. 3.2. */
 typedef struct lbsep_params {
@@ -77,7 +87,7 @@ typedef struct lbsep_params {
   double accom;     /* accommodation coefficient alpha of Eq. (A12), in (0, 1]                   */
   double tau_bgk;   /* relaxation time for LBSEP_BGK_TEST, > 0.5; ignored otherwise             */
   uint32_t flags;   /* LBSEP_PERIODIC_X | LBSEP_PERIODIC_Y | LBSEP_MFP_OFF | LBSEP_BGK_TEST      */
-  int32_t dtype;    /* LBSEP_F64 or LBSEP_F32                                                    */
+  int32_t dtype;    /* LBSEP_F64, LBSEP_F32 or LBSEP_F16                                         */
   int32_t hist_cap; /* per-step diagnostic records kept on the device (ring), >= 1               */
 } lbsep_params;
 
@@ -87,7 +97,7 @@ typedef struct lbsep_channel lbsep_channel;
  * required). Returns 0 if the parameters are invalid (see lbsep_last_error). */
 size_t lbsep_workspace_bytes(const lbsep_params* params);
 
-/* Bytes of one state (2 * 9 * ny * nx elements of the storage type). */
+/* Bytes of one raw state (2 * 9 * ny * nx elements of the storage type). */
 size_t lbsep_state_bytes(const lbsep_params* params);
 
 /* Create a channel in the caller's device workspace and set the initial state:
@@ -134,18 +144,39 @@ int lbsep_read_history(lbsep_channel* ch, int64_t t0, int64_t count, double* hos
  * workspace; synchronises. */
 int lbsep_read_moments(lbsep_channel* ch, double* host);
 
-/* Write the current pre-collision state (layout above) to device memory
- * dev_dst (lbsep_state_bytes bytes). Enqueues only. */
+/* Write the current raw state (storage representation, layout above) to
+ * device memory dev_dst (lbsep_state_bytes bytes): a bitwise checkpoint.
+ * Enqueues only. */
 int lbsep_get_state(lbsep_channel* ch, void* dev_dst);
 
-/* Replace the state by dev_src (device, layout above, lbsep_state_bytes
- * bytes) at time level t >= 0 and record its diagnostics. Enqueues only. */
+/* Replace the state by a raw state dev_src (device, as written by
+ * lbsep_get_state) at time level t >= 0 and record its diagnostics; stepping
+ * on from it reproduces the original run bitwise. Enqueues only. */
 int lbsep_set_state(lbsep_channel* ch, const void* dev_src, int64_t t);
+
+/* Write the current pre-collision populations f in double (2 * 9 * ny * nx
+ * doubles, layout above) to device memory dev_dst, whatever the storage type.
+ * Enqueues only. */
+int lbsep_get_populations(lbsep_channel* ch, double* dev_dst);
+
+/* Replace the state by the populations f given in double (device, layout
+ * above), converted to the storage type, at time level t >= 0, and record
+ * its diagnostics. Enqueues only. */
+int lbsep_set_populations(lbsep_channel* ch, const double* dev_src, int64_t t);
 
 /* DBB coefficient from a velocity slip coefficient c_m, Eq. (R) first form:
  * r = 2 - 2 / (1 + (c_m / 3) sqrt(pi m_x / (2 k_B T))), k_B T = m_min c_s^2,
  * m_x = cl m_a + (1 - cl) m_b. Returns NaN on invalid input. */
 double lbsep_dbb_r_from_cm(double c_m, double m_a, double m_b, double cl);
+
+/* The device wall function of Sec. 3.1, element-wise on n arguments:
+ * psi(alpha) = 1 + (alpha - 1) e^-alpha - alpha^2 E1(alpha) and
+ * h(alpha) = psi'(alpha) / 2 = e^-alpha - alpha E1(alpha), evaluated exactly as
+ * the sweep kernel does in the arithmetic of dtype (double for LBSEP_F64, float
+ * otherwise). dev_alpha, dev_psi, dev_h: device arrays of n doubles (dev_h may
+ * be NULL). Enqueues on hip_stream (NULL = default stream). */
+int lbsep_wall_function(const double* dev_alpha, double* dev_psi, double* dev_h, int64_t n, int32_t dtype,
+                        void* hip_stream);
 
 /* Release the host handle (the workspace stays the caller's). NULL is a no-op. */
 void lbsep_destroy(lbsep_channel* ch);

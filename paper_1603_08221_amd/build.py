@@ -21,6 +21,9 @@ FLAGS = [
     "-std=c++17",
     "-fPIC",
     "-shared",
+    # contract a*b+c only within one expression, so every kernel variant
+    # rounds a given formula the same way (bitwise resume across variants)
+    "-ffp-contract=on",
     # packed FP32 instructions stay off (the compiler would otherwise form them)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"),

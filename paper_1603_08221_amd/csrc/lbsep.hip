@@ -1,19 +1,35 @@
 // lbsep: fused sweep kernel and host implementation of include/lbsep.h.
 //
-// One time step = one launch of k_sweep<T, /*PULL=*/true, /*EVAL=*/false>:
+// One time step = one launch of k_sweep<Mode, /*PULL=*/true, /*EVAL=*/false>:
 // every thread owns one node (x, j) and
 //   1. pulls the 18 post-collision populations of the previous step from its
 //      neighbours (Eq. (MRT), pull form of the streaming),
 //   2. replaces the wall-crossing pulls by diffuse-bounce-back (Eqs. (bot),
 //      (bot2)) from its own post-collision populations,
-//   3. on the inlet/outlet columns, rebuilds the node from the first and second
-//      inner layers scaled by the column density correction (Eqs. (rho1), (rho2)),
+//   3. on the inlet/outlet columns, extrapolates the populations entering from
+//      the reservoir from the first and second inner layers and rescales the
+//      node to the corrected extrapolated density (Eqs. (rho1), (rho2)),
 //   4. computes moments (Eq. (rhou)), relaxation times (Eqs. (taos), (EQFrsp),
 //      (taoq)) and collides both species (Eq. (MR)),
 //   5. writes the 18 new post-collision populations, and
-//   6. adds its species number density and x-momentum to FP64 column sums,
-//      reduced to C_l(x), CL and C~_l (Eqs. (C), (CL), (Clline)) by the last
-//      block to finish (no second launch, deterministic summation order).
+//   6. adds its species number density and x-momentum to FP64 column sums of
+//      its tile. The reduction of those sums to C_l(x), CL and C~_l (Eqs. (C),
+//      (CL), (Clline)) is pipelined across launches: the lead blocks of sweep t
+//      reduce the tile sums of step t-1 to per-strip results, and one lead block
+//      turns the strip results of step t-2 into the record (t-2, CL, C~_l,
+//      x_min). The launch boundary orders producer and consumer, so the hot
+//      path has no fences or atomics; the summation order is fixed. Reading
+//      results first completes the last two levels (k_finalize).
+//
+// Storage modes (Mode<S, C, DEV>): FP64 stores f and computes in double.
+// FP32 and FP16 store the deviation d = f - f0(x) from the rest equilibrium
+// f0_si(x) = w_i alpha_si rho0_s(x) of a reference density linear in x
+// (rho0(0) = rho_in, rho0(nx-1) = rho_out) and compute in float: the
+// velocity, a small difference of O(1) populations, keeps the relative
+// precision of the storage type. Streaming d across one column adds the
+// constant -c_ix w_i alpha_si (d rho0 / dx); DBB and the extrapolation are the
+// same formulas on d (f0 is at rest and linear in x); the collision uses
+// rho - rho0 for the density terms.
 //
 // Layout in HBM (structure of arrays): population (s, i) of node (x, j) of a
 // state buffer is at element ((s * 9 + i) * ny + j) * pitch + x, pitch =
@@ -23,11 +39,14 @@
 // after init / set_state, the pre-collision state f(t)).
 //
 // Work decomposition: a block is 4 wavefronts = 64 columns x (4 * rpt) rows.
-// Blocks 0 and 1 own the inlet and outlet columns (they need whole-column sums
-// of the inner layers before they can rebuild the boundary nodes); blocks
-// 2..7 are idle; tiles follow, numbered so that each XCD (block id mod 8)
-// takes a contiguous run of tiles, vertically adjacent tiles first, which
-// keeps the halo rows of a tile in the same XCD's L2.
+// Lead blocks come first: 2 nend blocks own the inlet and outlet columns,
+// 128 rows each (they need whole-column sums of the inner layers before they
+// can rebuild the boundary nodes, so each end block sums the full column);
+// then nxt blocks reduce one column strip each of the previous step and one
+// block finishes the step before that; the lead count is rounded up to a
+// multiple of 8. Tiles follow, numbered so that each XCD (block id mod 8) takes a
+// contiguous run of tiles, vertically adjacent tiles first, which keeps the
+// halo rows of a tile in the same XCD's L2.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -46,53 +65,100 @@ namespace {
 constexpr int kTX = 64;         // columns per block (one wavefront across x)
 constexpr int kTY = 4;          // wavefronts per block
 constexpr int kThreads = kTX * kTY;
-constexpr int kLeadBlocks = 8;  // blocks 0..7: inlet, outlet, idle
+constexpr int kMaxEnd = 32;     // end blocks per inlet/outlet column: ny <= 128 * kMaxEnd
+
+template <typename S, typename C, bool DEV>
+struct Mode {
+  using St = S;  // storage type of a population
+  using Ct = C;  // arithmetic type
+  static constexpr bool kDev = DEV;
+};
+using ModeF64 = Mode<double, double, false>;
+using ModeF32 = Mode<float, float, true>;
+using ModeF16 = Mode<_Float16, float, true>;
 
 struct KParams {
   RelaxConsts rc;
   int nx, ny, pitch;
-  int nxt, nrt, rpt;  // column strips, row tiles, rows per thread
-  int tiles, chunk;   // nxt * nrt, ceil(tiles / 8)
-  long long plane;    // ny * pitch
+  int nxt, nrt, rpt;    // column strips, row tiles, rows per thread
+  int tiles, chunk;     // nxt * nrt, ceil(tiles / 8)
+  int lead;             // lead blocks (multiple of 8) before the first tile
+  int nend;             // blocks per inlet/outlet column (128 rows each)
+  long long plane;      // ny * pitch
   unsigned flags;
-  double r;           // DBB coefficient
+  double r;             // DBB coefficient
   double rho_bc[2][2];  // [inlet/outlet][species] densities of Eq. (rho2)
   double cl_in;
+  // deviation storage: rho0_s(x) = ref0[s] + slope[s] x, f0_si = wa[s][i] rho0_s
+  double ref0[2], slope[2];
+  double wa[2][9];
+  double corr[2][9];    // -c_ix wa[s][i] slope[s]: streaming across one column
 };
 
+// Reduction buffers are double-buffered by the parity of the time level.
 struct KBufs {
-  double* partials;    // [4][nrt][pitch] per row-tile column sums
-  double* endsum;      // [2][4] inlet / outlet column sums
-  double* colsum;      // [4][pitch] column sums of the last recorded state
-  double* strip;       // [nxt][4] (min C_l, argmin, sum (C_l - C_in), bad)
+  double* partials;    // [2][4][nrt][pitch] per row-tile column sums
+  double* endsum;      // [2][2][kMaxEnd][4] inlet / outlet column sums per end block
+  double* colsum;      // [4][pitch] column sums of the last reduced level
+  double* strip;       // [2][nxt][4] (min C_l, argmin, sum (C_l - C_in), bad)
   double* hist;        // [hist_cap][4] (t, CL, C~_l, x_min)
-  unsigned* counters;  // [nxt + 1] arrival counters (strips, then global)
   unsigned* status;    // [1] bit 0: non-finite or non-positive column density seen
   long long hist_cap;
+  long long part_stride;   // elements of one partials buffer: 4 * nrt * pitch
 };
 
 __device__ __forceinline__ long long pidx(const KParams& kp, int s, int i, int j, int x) {
   return (long long)(s * 9 + i) * kp.plane + (long long)j * kp.pitch + x;
 }
 
-// Pre-collision populations of node (x, j) at the new time level.
+// Population (s, i) at (j, x) of a state buffer as a wave-uniform plane base
+// plus a 32-bit byte offset inside the plane, so loads and stores address
+// through a scalar base register and one vector offset.
+template <typename S>
+__device__ __forceinline__ S* plane_at(const KParams& kp, S* base, int s, int i, int j, int x) {
+  const unsigned off = ((unsigned)j * (unsigned)kp.pitch + (unsigned)x) * (unsigned)sizeof(S);
+  char* pl = reinterpret_cast<char*>(base) + (size_t)(s * 9 + i) * (size_t)kp.plane * sizeof(S);
+  return reinterpret_cast<S*>(pl + off);
+}
+template <typename S>
+__device__ __forceinline__ const S* plane_at(const KParams& kp, const S* base, int s, int i, int j, int x) {
+  const unsigned off = ((unsigned)j * (unsigned)kp.pitch + (unsigned)x) * (unsigned)sizeof(S);
+  const char* pl = reinterpret_cast<const char*>(base) + (size_t)(s * 9 + i) * (size_t)kp.plane * sizeof(S);
+  return reinterpret_cast<const S*>(pl + off);
+}
+
+__device__ __forceinline__ double ref_rho(const KParams& kp, int s, int x) {
+  return kp.ref0[s] + kp.slope[s] * double(x);
+}
+
+template <typename T>
+__device__ __forceinline__ T sum9(const T f[9]) {
+  return ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+}
+
+// Pre-collision populations (deviations in the FP32/FP16 modes) of species s
+// at node (x, j) at the new time level.
 // PULL: streamed from the post-collision state in src, with DBB on wall rows.
 // !PULL: read in place (src already holds a pre-collision state).
-template <typename T, bool PULL>
-__device__ __forceinline__ void gather(const KParams& kp, const T* __restrict__ src, int x, int j, T fa[9],
-                                       T fb[9]) {
+// On the inlet/outlet columns the directions that would come from outside the
+// channel are loaded from the node itself (kept in range) and replaced by the
+// caller.
+template <class MD, bool PULL>
+__device__ __forceinline__ void gather1(const KParams& kp, const typename MD::St* __restrict__ src, int s, int x,
+                                        int j, typename MD::Ct f[9]) {
+  using C = typename MD::Ct;
   if (!PULL) {
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      fa[i] = src[pidx(kp, 0, i, j, x)];
-      fb[i] = src[pidx(kp, 1, i, j, x)];
-    }
+    for (int i = 0; i < 9; ++i) f[i] = C(*plane_at(kp, src, s, i, j, x));
     return;
   }
   int xm = x - 1, xp = x + 1, jm = j - 1, jp = j + 1;
   if (kp.flags & LBSEP_PERIODIC_X) {
     if (xm < 0) xm += kp.nx;
     if (xp >= kp.nx) xp -= kp.nx;
+  } else {
+    if (xm < 0) xm = 0;
+    if (xp >= kp.nx) xp = kp.nx - 1;
   }
   bool bot = false, top = false;
   if (kp.flags & LBSEP_PERIODIC_Y) {
@@ -110,137 +176,187 @@ __device__ __forceinline__ void gather(const KParams& kp, const T* __restrict__ 
   const int sy[9] = {j, j, jm, j, jp, jm, jm, jp, jp};
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
-    fa[i] = src[pidx(kp, 0, i, sy[i], sx[i])];
-    fb[i] = src[pidx(kp, 1, i, sy[i], sx[i])];
+    f[i] = C(*plane_at(kp, src, s, i, sy[i], sx[i]));
+    if (MD::kDev && (i == 1 || i == 3 || i >= 5)) f[i] += C(kp.corr[s][i]);
   }
   if (bot || top) {
     // Eqs. (bot)/(bot2): the populations that would come from outside the
     // channel are r f^eq(rho_w, u_w = 0) + (1 - r) f'_opposite at the same node;
     // rho_w makes the returned mass equal the leaving mass F, which puts the
     // shares 4/6, 1/6, 1/6 of F on the axis and the two diagonal directions.
-    const T r = T(kp.r);
-    const T q = T(1) - r;
+    // The rest equilibrium is a fixed point of this map, so deviations obey it too.
+    // (constant array indices in each branch keep f in registers)
+    const C r = C(kp.r);
+    const C q = C(1) - r;
     const int o0 = bot ? 4 : 2, o1 = bot ? 7 : 5, o2 = bot ? 8 : 6;  // leaving
-    const int u0 = bot ? 2 : 4, u1 = bot ? 5 : 7, u2 = bot ? 6 : 8;  // returning
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      T* f = s ? fb : fa;
-      const T l0 = src[pidx(kp, s, o0, j, x)];
-      const T l1 = src[pidx(kp, s, o1, j, x)];
-      const T l2 = src[pidx(kp, s, o2, j, x)];
-      const T F = l0 + l1 + l2;
-      f[u0] = r * (T(2.0 / 3.0) * F) + q * l0;
-      f[u1] = r * (F * T(1.0 / 6.0)) + q * l1;
-      f[u2] = r * (F * T(1.0 / 6.0)) + q * l2;
+    const C l0 = C(*plane_at(kp, src, s, o0, j, x));
+    const C l1 = C(*plane_at(kp, src, s, o1, j, x));
+    const C l2 = C(*plane_at(kp, src, s, o2, j, x));
+    const C F = (l0 + l1) + l2;
+    const C v0 = r * (C(2.0 / 3.0) * F) + q * l0;
+    const C v1 = r * (F * C(1.0 / 6.0)) + q * l1;
+    const C v2 = r * (F * C(1.0 / 6.0)) + q * l2;
+    if (bot) {  // returning 2, 5, 6
+      f[2] = v0;
+      f[5] = v1;
+      f[6] = v2;
+    } else {    // returning 4, 7, 8
+      f[4] = v0;
+      f[7] = v1;
+      f[8] = v2;
     }
   }
 }
 
-template <typename T>
-__device__ __forceinline__ T sum9(const T f[9]) {
-  return ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+// Rebuilt pre-collision node of species s on the inlet (e = 0) or outlet
+// (e = 1) column, Eqs. (rho1), (rho2): the populations entering from the
+// reservoir are extrapolated from the first and second inner layers, the node
+// is rescaled to kappa rho'(j) with rho' = 2 rho(l1, j) - rho(l2, j).
+// kap = kappa; km1 = kappa - 1 (used by the deviation modes).
+template <class MD>
+__device__ __forceinline__ void end_node(const KParams& kp, const typename MD::St* __restrict__ src, int e, int s,
+                                         int j, double kap, double km1, typename MD::Ct f[9]) {
+  using C = typename MD::Ct;
+  const int col = e ? kp.nx - 1 : 0;
+  const int l1 = e ? kp.nx - 2 : 1;
+  const int l2 = e ? kp.nx - 3 : 2;
+  C g1[9], g2[9];
+  gather1<MD, true>(kp, src, s, col, j, f);
+  gather1<MD, true>(kp, src, s, l1, j, g1);
+  gather1<MD, true>(kp, src, s, l2, j, g2);
+  if (e == 0) {  // entering at the inlet: c_x = +1
+    f[1] = C(2) * g1[1] - g2[1];
+    f[5] = C(2) * g1[5] - g2[5];
+    f[8] = C(2) * g1[8] - g2[8];
+  } else {       // entering at the outlet: c_x = -1
+    f[3] = C(2) * g1[3] - g2[3];
+    f[6] = C(2) * g1[6] - g2[6];
+    f[7] = C(2) * g1[7] - g2[7];
+  }
+  const C rp = C(2) * sum9(g1) - sum9(g2);  // rho' (deviation modes: rho' - rho0(col))
+  if (!MD::kDev) {
+    const C scale = (C(kap) * rp) / sum9(f);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) f[i] *= scale;
+  } else {
+    // f -> S f with S - 1 = ((kappa - 1) rho0 + kappa d rho' - d rho_node) / rho_node
+    const double r0d = ref_rho(kp, s, col);
+    const C r0 = C(r0d);
+    const C dn = sum9(f);
+    const C sm1 = (C(km1 * r0d) + C(kap) * rp - dn) / (r0 + dn);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) f[i] += sm1 * (f[i] + C(kp.wa[s][i] * r0d));
+  }
 }
 
 // Moments, relaxation times and (STEP) collision + store or (EVAL) output of
 // one node. acc receives (n_a, n_b, rho_a u_ax, rho_b u_bx) in double.
-template <typename T, bool EVAL>
-__device__ __forceinline__ void process_node(const KParams& kp, int x, int j, T fa[9], T fb[9],
-                                             T* __restrict__ dst, double* __restrict__ mom,
-                                             T* __restrict__ fout, double acc[4]) {
-  const T rho_a = sum9(fa);
-  const T rho_b = sum9(fb);
-  const T jxa = (fa[1] - fa[3]) + (fa[5] - fa[6]) + (fa[8] - fa[7]);
-  const T jya = (fa[2] - fa[4]) + (fa[5] + fa[6]) - (fa[7] + fa[8]);
-  const T jxb = (fb[1] - fb[3]) + (fb[5] - fb[6]) + (fb[8] - fb[7]);
-  const T jyb = (fb[2] - fb[4]) + (fb[5] + fb[6]) - (fb[7] + fb[8]);
-  const T rho = rho_a + rho_b;
-  const T inv_rho = T(1) / rho;
-  const T ux = (jxa + jxb) * inv_rho;
-  const T uy = (jya + jyb) * inv_rho;
-  T ts, td, tq;
-  relaxation_times<T>(kp.rc, j, rho_a, rho_b, ts, td, tq);
+template <class MD, bool EVAL>
+__device__ __forceinline__ void process_node(const KParams& kp, int x, int j, typename MD::Ct fa[9],
+                                             typename MD::Ct fb[9], typename MD::St* __restrict__ dst,
+                                             double* __restrict__ mom, typename MD::St* __restrict__ fraw,
+                                             double* __restrict__ ffull, double acc[4]) {
+  using C = typename MD::Ct;
+  const C ca = sum9(fa);  // rho_a, or rho_a - rho0_a(x)
+  const C cb = sum9(fb);
+  double ra_d, rb_d;      // species densities in double
+  C rho_a, rho_b;
+  if (MD::kDev) {
+    ra_d = ref_rho(kp, 0, x) + double(ca);
+    rb_d = ref_rho(kp, 1, x) + double(cb);
+    rho_a = C(ra_d);
+    rho_b = C(rb_d);
+  } else {
+    ra_d = double(ca);
+    rb_d = double(cb);
+    rho_a = ca;
+    rho_b = cb;
+  }
+  const C jxa = (fa[1] - fa[3]) + (fa[5] - fa[6]) + (fa[8] - fa[7]);
+  const C jya = (fa[2] - fa[4]) + (fa[5] + fa[6]) - (fa[7] + fa[8]);
+  const C jxb = (fb[1] - fb[3]) + (fb[5] - fb[6]) + (fb[8] - fb[7]);
+  const C jyb = (fb[2] - fb[4]) + (fb[5] + fb[6]) - (fb[7] + fb[8]);
+  const C rho = rho_a + rho_b;
+  const C inv_rho = E1Traits<C>::rcp(rho);
+  const C ux = (jxa + jxb) * inv_rho;
+  const C uy = (jya + jyb) * inv_rho;
+  C ts, td, tq;
+  relaxation_times<C>(kp.rc, j, rho_a, rho_b, ts, td, tq);
   // species momentum of Eq. (rhou): rho_s u_s = (1 - 1/(2 tau_d)) j_s + rho_s u / (2 tau_d)
-  const T h2 = T(0.5) / td;
-  const T g = T(1) - h2;
-  const T pxa = g * jxa + rho_a * ux * h2;
-  const T pxb = g * jxb + rho_b * ux * h2;
+  const C h2 = C(0.5) * E1Traits<C>::rcp(td);
+  const C g = C(1) - h2;
+  const C pxa = g * jxa + rho_a * ux * h2;
+  const C pxb = g * jxb + rho_b * ux * h2;
   if (EVAL) {
     const long long n = (long long)kp.nx * kp.ny;
     const long long o = (long long)j * kp.nx + x;
     if (mom) {
-      const T pya = g * jya + rho_a * uy * h2;
-      const T pyb = g * jyb + rho_b * uy * h2;
-      mom[o] = double(rho_a);
-      mom[n + o] = double(rho_b);
+      const C pya = g * jya + rho_a * uy * h2;
+      const C pyb = g * jyb + rho_b * uy * h2;
+      mom[o] = ra_d;
+      mom[n + o] = rb_d;
       mom[2 * n + o] = double(pxa / rho_a);
       mom[3 * n + o] = double(pya / rho_a);
       mom[4 * n + o] = double(pxb / rho_b);
       mom[5 * n + o] = double(pyb / rho_b);
     }
-    if (fout) {
+    if (fraw) {
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
-        fout[i * n + o] = fa[i];
-        fout[(9 + i) * n + o] = fb[i];
+        fraw[i * n + o] = typename MD::St(fa[i]);
+        fraw[(9 + i) * n + o] = typename MD::St(fb[i]);
+      }
+    }
+    if (ffull) {
+      const double r0a = MD::kDev ? ref_rho(kp, 0, x) : 0.0;
+      const double r0b = MD::kDev ? ref_rho(kp, 1, x) : 0.0;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        ffull[i * n + o] = double(fa[i]) + (MD::kDev ? kp.wa[0][i] * r0a : 0.0);
+        ffull[(9 + i) * n + o] = double(fb[i]) + (MD::kDev ? kp.wa[1][i] * r0b : 0.0);
       }
     }
     return;
   }
-  acc[0] += double(rho_a) * kp.rc.inv_m[0];
-  acc[1] += double(rho_b) * kp.rc.inv_m[1];
+  acc[0] += ra_d * kp.rc.inv_m[0];
+  acc[1] += rb_d * kp.rc.inv_m[1];
   acc[2] += double(pxa);
   acc[3] += double(pxb);
-  T we, weps;
+  C we, weps;
+  const C ws = E1Traits<C>::rcp(ts);
   if (kp.rc.bgk) {
-    we = weps = T(1) / ts;
+    we = weps = ws;
   } else {
-    we = T(1.0 / 1.1);     // tau_e = 1.1 (Sec. 3.3)
-    weps = T(1.0 / 1.2);   // tau_eps = 1.2
+    we = C(1.0 / 1.1);    // tau_e = 1.1 (Sec. 3.3)
+    weps = C(1.0 / 1.2);  // tau_eps = 1.2
   }
-  const T wd = T(1) / td, wq = T(1) / tq, ws = T(1) / ts;
-  collide_species<T>(fa, rho_a, ux, uy, T(kp.rc.s[0]), we, weps, wd, wq, ws);
-  collide_species<T>(fb, rho_b, ux, uy, T(kp.rc.s[1]), we, weps, wd, wq, ws);
+  const C wd = C(2) * h2, wq = E1Traits<C>::rcp(tq);
+  collide_species<C>(fa, ca, rho_a, ux, uy, C(kp.rc.s[0]), we, weps, wd, wq, ws);
+  collide_species<C>(fb, cb, rho_b, ux, uy, C(kp.rc.s[1]), we, weps, wd, wq, ws);
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
-    dst[pidx(kp, 0, i, j, x)] = fa[i];
-    dst[pidx(kp, 1, i, j, x)] = fb[i];
+    *plane_at(kp, dst, 0, i, j, x) = typename MD::St(fa[i]);
+    *plane_at(kp, dst, 1, i, j, x) = typename MD::St(fb[i]);
   }
 }
 
-// Last-arriver detection for the block-level reduction. Every thread fences
-// its own stores before the block's single arrival; the last block fences
-// again before it reads what the others wrote.
-__device__ __forceinline__ bool arrive_last(unsigned* counter, unsigned expected) {
-  __shared__ int last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned prev = atomicAdd(counter, 1u);
-    last = (prev == expected - 1u);
-  }
-  __syncthreads();
-  const bool is_last = last != 0;
-  if (is_last) __threadfence();
-  return is_last;
-}
-
-// Reduction of one column strip (64 columns) after all its row tiles (and the
-// inlet/outlet block that owns one of its columns) have stored their sums,
-// then, for the last strip, of all strips to CL and C~_l for level t.
-__device__ void finish_strip(const KParams& kp, const KBufs& kb, int bx, long long t,
+// Column sums of one strip (64 columns) of level `step`: add the row-tile
+// partials (the inlet/outlet columns come from their own blocks), store them,
+// and reduce the strip to (min C_l, its column, sum (C_l - C_in), bad flag).
+__device__ void strip_reduce(const KParams& kp, const KBufs& kb, int bx, long long step,
                              double (*red)[kTY][kTX]) {
   const int tx = threadIdx.x & (kTX - 1);
   const int q = threadIdx.x / kTX;  // which sum
   const int x = bx * kTX + tx;
+  const int par = int(step & 1);
   const bool px = kp.flags & LBSEP_PERIODIC_X;
   double v = 0.0;
   if (x < kp.nx) {
-    if (!px && x == 0) {
-      v = kb.endsum[0 * 4 + q];
-    } else if (!px && x == kp.nx - 1) {
-      v = kb.endsum[1 * 4 + q];
+    if (!px && (x == 0 || x == kp.nx - 1)) {
+      const int e = x == 0 ? 0 : 1;
+      for (int blk = 0; blk < kp.nend; ++blk) v += kb.endsum[((par * 2 + e) * kMaxEnd + blk) * 4 + q];
     } else {
-      const double* p = kb.partials + (long long)q * kp.nrt * kp.pitch + x;
+      const double* p = kb.partials + par * kb.part_stride + (long long)q * kp.nrt * kp.pitch + x;
       for (int by = 0; by < kp.nrt; ++by) v += p[(long long)by * kp.pitch];
     }
     kb.colsum[(long long)q * kp.pitch + x] = v;
@@ -275,49 +391,51 @@ __device__ void finish_strip(const KParams& kp, const KBufs& kb, int bx, long lo
       bad = fmax(bad, obad);
     }
     if (tx == 0) {
-      double* s = kb.strip + (long long)bx * 4;
-      s[0] = cl;
-      s[1] = arg;
-      s[2] = dev;
-      s[3] = bad;
-      kb.counters[bx] = 0u;  // all arrivals for this strip are in
+      double* st = kb.strip + ((long long)par * kp.nxt + bx) * 4;
+      st[0] = cl;
+      st[1] = arg;
+      st[2] = dev;
+      st[3] = bad;
     }
   }
-  if (!arrive_last(kb.counters + kp.nxt, (unsigned)kp.nxt)) return;
-  if (threadIdx.x < kTX) {
-    const int lane = threadIdx.x;
-    double cl = 1e300, arg = 1e300, dev = 0.0, bad = 0.0;
-    for (int k = lane; k < kp.nxt; k += kTX) {
-      const double* s = kb.strip + (long long)k * 4;
-      if (s[0] < cl || (s[0] == cl && s[1] < arg)) {
-        cl = s[0];
-        arg = s[1];
-      }
-      dev += s[2];
-      bad = fmax(bad, s[3]);
+}
+
+// Record of level `step` from its strip results: CL (Eq. (CL)), C~_l
+// (Eq. (Clline)) and the column of the smallest C_l. Wavefront 0 only.
+__device__ void global_reduce(const KParams& kp, const KBufs& kb, long long step) {
+  if (threadIdx.x >= kTX) return;
+  const int lane = threadIdx.x;
+  const int par = int(step & 1);
+  double cl = 1e300, arg = 1e300, dev = 0.0, bad = 0.0;
+  for (int k = lane; k < kp.nxt; k += kTX) {
+    const double* st = kb.strip + ((long long)par * kp.nxt + k) * 4;
+    if (st[0] < cl || (st[0] == cl && st[1] < arg)) {
+      cl = st[0];
+      arg = st[1];
     }
+    dev += st[2];
+    bad = fmax(bad, st[3]);
+  }
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-      const double ocl = __shfl_xor(cl, off);
-      const double oarg = __shfl_xor(arg, off);
-      const double odev = __shfl_xor(dev, off);
-      const double obad = __shfl_xor(bad, off);
-      if (ocl < cl || (ocl == cl && oarg < arg)) {
-        cl = ocl;
-        arg = oarg;
-      }
-      dev += odev;
-      bad = fmax(bad, obad);
+  for (int off = 32; off >= 1; off >>= 1) {
+    const double ocl = __shfl_xor(cl, off);
+    const double oarg = __shfl_xor(arg, off);
+    const double odev = __shfl_xor(dev, off);
+    const double obad = __shfl_xor(bad, off);
+    if (ocl < cl || (ocl == cl && oarg < arg)) {
+      cl = ocl;
+      arg = oarg;
     }
-    if (lane == 0) {
-      double* h = kb.hist + (t % kb.hist_cap) * 4;
-      h[0] = double(t);
-      h[1] = (kp.cl_in - cl) / kp.cl_in;                 // Eq. (CL)
-      h[2] = dev / (double(kp.nx) * kp.cl_in);           // Eq. (Clline)
-      h[3] = arg;
-      if (bad != 0.0) atomicOr(kb.status, 1u);
-      kb.counters[kp.nxt] = 0u;
-    }
+    dev += odev;
+    bad = fmax(bad, obad);
+  }
+  if (lane == 0) {
+    double* h = kb.hist + (step % kb.hist_cap) * 4;
+    h[0] = double(step);
+    h[1] = (kp.cl_in - cl) / kp.cl_in;        // Eq. (CL)
+    h[2] = dev / (double(kp.nx) * kp.cl_in);  // Eq. (Clline)
+    h[3] = arg;
+    if (bad != 0.0) kb.status[0] |= 1u;       // single writer per launch
   }
 }
 
@@ -340,65 +458,91 @@ __device__ void block_sum(double (*red)[kTY][kTX], const double* v, int nv) {
   __syncthreads();
 }
 
-template <typename T, bool PULL, bool EVAL>
-__global__ __launch_bounds__(kThreads) void k_sweep(KParams kp, KBufs kb, const T* __restrict__ src,
-                                                    T* __restrict__ dst, double* __restrict__ mom,
-                                                    T* __restrict__ fout, long long t) {
+template <class MD, bool PULL, bool EVAL>
+__global__ __launch_bounds__(kThreads) void k_sweep(KParams kp, KBufs kb, const typename MD::St* __restrict__ src,
+                                                    typename MD::St* __restrict__ dst, double* __restrict__ mom,
+                                                    typename MD::St* __restrict__ fraw,
+                                                    double* __restrict__ ffull, long long t,
+                                                    long long t_first) {
+  using C = typename MD::Ct;
   __shared__ double red[4][kTY][kTX];
   const int b = blockIdx.x;
   const bool px = kp.flags & LBSEP_PERIODIC_X;
-  if (b < kLeadBlocks) {
-    // ---- inlet (b = 0) / outlet (b = 1) column ---------------------------
-    if (px || b >= 2) return;
-    const int e = b;
+  if (b < kp.lead) {
+    if (b >= 2 * kp.nend) {
+      // ---- pipelined reductions of the two previous levels --------------------
+      if (EVAL) return;
+      const int r = b - 2 * kp.nend;
+      if (r < kp.nxt) {
+        if (t - 1 >= t_first) strip_reduce(kp, kb, r, t - 1, red);
+      } else if (r == kp.nxt) {
+        if (t - 2 >= t_first) global_reduce(kp, kb, t - 2);
+      }
+      return;
+    }
+    // ---- inlet (e = 0) / outlet (e = 1) column, rows [128 blk, 128 blk + 128) ----
+    if (px) return;
+    const int e = b / kp.nend;
+    const int blk = b - e * kp.nend;
     const int col = e ? kp.nx - 1 : 0;
     const int l1 = e ? kp.nx - 2 : 1;
-    const int l2 = e ? kp.nx - 3 : 2;
-    T kap[2] = {T(1), T(1)};
+    const int l2 = e ? kp.nx - 3 : 2;  // first and second inner layers
+    double kap[2] = {1.0, 1.0}, km1[2] = {0.0, 0.0};
     if (PULL) {
-      // Eq. (rho1): rho'(col, j) = 2 rho(l1, j) - rho(l2, j); Eq. (rho2): kappa
+      // Eq. (rho1): rho'(col, j) = 2 rho(l1, j) - rho(l2, j), summed over the
+      // whole column by every end block; Eq. (rho2): kappa. Items (j, s, layer).
       double sums[2] = {0.0, 0.0};
-      for (int j = threadIdx.x; j < kp.ny; j += kThreads) {
-        T fa[9], fb[9], ga[9], gb[9];
-        gather<T, true>(kp, src, l1, j, fa, fb);
-        gather<T, true>(kp, src, l2, j, ga, gb);
-        sums[0] += double(T(2) * sum9(fa) - sum9(ga));
-        sums[1] += double(T(2) * sum9(fb) - sum9(gb));
+      for (int it = threadIdx.x; it < 4 * kp.ny; it += kThreads) {
+        const int j = it >> 2, s = (it >> 1) & 1, layer = it & 1;
+        C g[9];
+        gather1<MD, true>(kp, src, s, layer ? l2 : l1, j, g);
+        const double rho_l = double(sum9(g));
+        const double v = layer ? -rho_l : 2.0 * rho_l;
+        if (s) sums[1] += v; else sums[0] += v;
       }
       block_sum(red, sums, 2);
-      kap[0] = T(double(kp.ny) * kp.rho_bc[e][0] / red[0][0][0]);
-      kap[1] = T(double(kp.ny) * kp.rho_bc[e][1] / red[1][0][0]);
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const double n = double(kp.ny), sum = red[s][0][0];
+        if (MD::kDev) {
+          // sum_j rho' = n rho0(col) + sum (deviation sums)
+          const double r0 = ref_rho(kp, s, col);
+          km1[s] = (n * (kp.rho_bc[e][s] - r0) - sum) / (n * r0 + sum);
+          kap[s] = 1.0 + km1[s];
+        } else {
+          kap[s] = n * kp.rho_bc[e][s] / sum;
+          km1[s] = kap[s] - 1.0;
+        }
+      }
       __syncthreads();
     }
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int j = threadIdx.x; j < kp.ny; j += kThreads) {
-      T fa[9], fb[9];
-      if (PULL) {
-        T ga[9], gb[9];
-        gather<T, true>(kp, src, l1, j, fa, fb);
-        gather<T, true>(kp, src, l2, j, ga, gb);
+    // items (j, s) on adjacent lanes: each lane rebuilds one species, the pair
+    // swaps populations and the even lane collides the node
+    const int it = blk * kThreads + (int)threadIdx.x;
+    const int j = it >> 1, s = it & 1;
+    const bool active = j < kp.ny;
+    C f[9];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) {
-          fa[i] = kap[0] * (T(2) * fa[i] - ga[i]);
-          fb[i] = kap[1] * (T(2) * fb[i] - gb[i]);
-        }
-      } else {
-        gather<T, false>(kp, src, col, j, fa, fb);
-      }
-      process_node<T, EVAL>(kp, col, j, fa, fb, dst, mom, fout, acc);
+    for (int i = 0; i < 9; ++i) f[i] = C(0);
+    if (active) {
+      if (PULL)
+        end_node<MD>(kp, src, e, s, j, kap[s], km1[s], f);
+      else
+        gather1<MD, false>(kp, src, s, col, j, f);
     }
+    C g[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) g[i] = __shfl_xor(f[i], 1);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (active && s == 0) process_node<MD, EVAL>(kp, col, j, f, g, dst, mom, fraw, ffull, acc);
     if (EVAL) return;
     block_sum(red, acc, 4);
-    if (threadIdx.x < 4) kb.endsum[e * 4 + threadIdx.x] = red[threadIdx.x][0][0];
-    __syncthreads();
-    const int bx = e ? kp.nxt - 1 : 0;
-    const unsigned expected = (unsigned)kp.nrt + 1u + ((kp.nxt == 1) ? 1u : 0u);
-    if (arrive_last(kb.counters + bx, expected)) finish_strip(kp, kb, bx, t, red);
+    if (threadIdx.x < 4) kb.endsum[(((t & 1) * 2 + e) * kMaxEnd + blk) * 4 + threadIdx.x] = red[threadIdx.x][0][0];
     return;
   }
   // ---- interior tile ---------------------------------------------------------
   const int xcd = b & 7;
-  const int k = (b >> 3) - 1;
+  const int k = (b - kp.lead) >> 3;
   const int lin = xcd * kp.chunk + k;
   if (lin >= kp.tiles) return;
   const int bx = lin / kp.nrt;
@@ -411,9 +555,10 @@ __global__ __launch_bounds__(kThreads) void k_sweep(KParams kp, KBufs kb, const 
   for (int r = 0; r < kp.rpt; ++r) {
     const int j = by * (kTY * kp.rpt) + r * kTY + ty;
     if (xin && j < kp.ny) {
-      T fa[9], fb[9];
-      gather<T, PULL>(kp, src, x, j, fa, fb);
-      process_node<T, EVAL>(kp, x, j, fa, fb, dst, mom, fout, acc);
+      C fa[9], fb[9];
+      gather1<MD, PULL>(kp, src, 0, x, j, fa);
+      gather1<MD, PULL>(kp, src, 1, x, j, fb);
+      process_node<MD, EVAL>(kp, x, j, fa, fb, dst, mom, fraw, ffull, acc);
     }
   }
   if (EVAL) return;
@@ -423,18 +568,33 @@ __global__ __launch_bounds__(kThreads) void k_sweep(KParams kp, KBufs kb, const 
   __syncthreads();
   if (x < kp.nx) {
     const double s = ((red[ty][0][tx] + red[ty][1][tx]) + red[ty][2][tx]) + red[ty][3][tx];
-    kb.partials[((long long)ty * kp.nrt + by) * kp.pitch + x] = s;
+    kb.partials[(t & 1) * kb.part_stride + ((long long)ty * kp.nrt + by) * kp.pitch + x] = s;
   }
-  const unsigned expected =
-      (unsigned)kp.nrt + ((!px && bx == 0) ? 1u : 0u) + ((!px && bx == kp.nxt - 1) ? 1u : 0u);
-  if (arrive_last(kb.counters + bx, expected)) finish_strip(kp, kb, bx, t, red);
+}
+
+// Completes the records of levels t - 1 and t (reads after the last sweep):
+// phase 0 reduces the strips of level t (blocks 0 .. nxt-1) and finishes level
+// t - 1 (block nxt); phase 1 finishes level t.
+__global__ __launch_bounds__(kThreads) void k_finalize(KParams kp, KBufs kb, long long t, long long t_first,
+                                                       int phase) {
+  __shared__ double red[4][kTY][kTX];
+  const int b = blockIdx.x;
+  if (phase == 0) {
+    if (b < kp.nxt)
+      strip_reduce(kp, kb, b, t, red);
+    else if (t - 1 >= t_first)
+      global_reduce(kp, kb, t - 1);
+  } else {
+    global_reduce(kp, kb, t);
+  }
 }
 
 // Initial state: f = f^eq(rho_s(x), u = 0) (Eq. (feq) at rest), pressure and
-// C_l linear in x from (P_in, C_in) to (P_out, C_out).
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_init(KParams kp, T* __restrict__ f, double p_in, double p_out,
-                                                   double c_in, double c_out) {
+// C_l linear in x from (P_in, C_in) to (P_out, C_out); deviation modes store
+// f - f0(x).
+template <class MD>
+__global__ __launch_bounds__(kThreads) void k_init(KParams kp, typename MD::St* __restrict__ f, double p_in,
+                                                   double p_out, double c_in, double c_out) {
   const long long n = (long long)kp.ny * kp.pitch;
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n;
        e += (long long)gridDim.x * blockDim.x) {
@@ -449,12 +609,27 @@ __global__ __launch_bounds__(kThreads) void k_init(KParams kp, T* __restrict__ f
     for (int s = 0; s < 2; ++s) {
       const double sv = kp.rc.s[s];
       const double a0 = (9.0 - 5.0 * sv) / 4.0;
-      f[pidx(kp, s, 0, j, x)] = T(4.0 / 9.0 * rho[s] * a0);
+      double fi[9];
+      fi[0] = 4.0 / 9.0 * rho[s] * a0;
+      for (int i = 1; i < 5; ++i) fi[i] = 1.0 / 9.0 * rho[s] * sv;
+      for (int i = 5; i < 9; ++i) fi[i] = 1.0 / 36.0 * rho[s] * sv;
+      const double r0 = ref_rho(kp, s, x);
 #pragma unroll
-      for (int i = 1; i < 5; ++i) f[pidx(kp, s, i, j, x)] = T(1.0 / 9.0 * rho[s] * sv);
-#pragma unroll
-      for (int i = 5; i < 9; ++i) f[pidx(kp, s, i, j, x)] = T(1.0 / 36.0 * rho[s] * sv);
+      for (int i = 0; i < 9; ++i)
+        f[pidx(kp, s, i, j, x)] = typename MD::St(MD::kDev ? fi[i] - kp.wa[s][i] * r0 : fi[i]);
     }
+  }
+}
+
+// psi(alpha) and psi'(alpha)/2 of the device wall function, element-wise.
+template <typename T>
+__global__ void k_wall_function(const double* __restrict__ a, double* __restrict__ psi, double* __restrict__ h,
+                                long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    T p, hh;
+    wall_psi<T>(T(a[i]), p, hh);
+    psi[i] = double(p);
+    if (h) h[i] = double(hh);
   }
 }
 
@@ -463,15 +638,30 @@ __global__ void k_zero_u32(unsigned* p, int n) {
   if (i < n) p[i] = 0u;
 }
 
-// Dense [2*9*ny][nx] <-> pitched state copy.
-template <typename T>
-__global__ void k_copy_in(KParams kp, const T* __restrict__ dense, T* __restrict__ f) {
+// Dense [2*9*ny][nx] raw state -> pitched buffer.
+template <typename S>
+__global__ void k_copy_in(KParams kp, const S* __restrict__ dense, S* __restrict__ f) {
   const long long n = 18LL * kp.ny * kp.nx;
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n;
        e += (long long)gridDim.x * blockDim.x) {
     const long long row = e / kp.nx;
     const int x = int(e - row * kp.nx);
     f[row * kp.pitch + x] = dense[e];
+  }
+}
+
+// Dense [2][9][ny][nx] FP64 populations -> pitched storage representation.
+template <class MD>
+__global__ void k_set_pop(KParams kp, const double* __restrict__ dense, typename MD::St* __restrict__ f) {
+  const long long n = 18LL * kp.ny * kp.nx;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long row = e / kp.nx;
+    const int x = int(e - row * kp.nx);
+    const int si = int(row / kp.ny);  // s * 9 + i
+    const int s = si / 9, i = si - 9 * s;
+    const double v = MD::kDev ? dense[e] - kp.wa[s][i] * ref_rho(kp, s, x) : dense[e];
+    f[row * kp.pitch + x] = typename MD::St(v);
   }
 }
 
@@ -487,9 +677,11 @@ int fail(int code, const std::string& msg) {
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+size_t elem_bytes(int dtype) { return dtype == LBSEP_F64 ? 8 : dtype == LBSEP_F32 ? 4 : 2; }
+
 struct Layout {
-  int pitch, nxt, nrt, rpt, tiles, chunk;
-  size_t elem, state_buf, f0, f1, partials, endsum, colsum, strip, hist, counters, mom, total;
+  int pitch, nxt, nrt, rpt, tiles, chunk, lead, nend;
+  size_t elem, state_buf, f0, f1, partials, endsum, colsum, strip, hist, status, mom, total;
 };
 
 bool validate(const lbsep_params* p, std::string& why) {
@@ -500,6 +692,7 @@ bool validate(const lbsep_params* p, std::string& why) {
   if (p->nx < (px ? 1 : 6)) return why = "nx must be >= 6 (>= 1 with LBSEP_PERIODIC_X)", false;
   if (p->ny < 2) return why = "ny must be >= 2", false;
   if ((long long)p->nx * p->ny > (1LL << 31)) return why = "nx * ny too large", false;
+  if (p->ny > 128 * kMaxEnd) return why = "ny must be <= " + std::to_string(128 * kMaxEnd), false;
   if (!(p->m_a > 0) || !(p->m_b >= p->m_a) || !std::isfinite(p->m_b))
     return why = "need 0 < m_a <= m_b (species a is the light one)", false;
   if (!(p->cl_in > 0 && p->cl_in < 1) || !(p->cl_out > 0 && p->cl_out < 1))
@@ -511,14 +704,15 @@ bool validate(const lbsep_params* p, std::string& why) {
   if ((p->flags & LBSEP_BGK_TEST) && !(p->tau_bgk > 0.5 && std::isfinite(p->tau_bgk)))
     return why = "tau_bgk must be > 0.5 with LBSEP_BGK_TEST", false;
   if (py && !(p->flags & LBSEP_MFP_OFF)) return why = "LBSEP_PERIODIC_Y requires LBSEP_MFP_OFF", false;
-  if (p->dtype != LBSEP_F64 && p->dtype != LBSEP_F32) return why = "dtype must be LBSEP_F64 or LBSEP_F32", false;
+  if (p->dtype != LBSEP_F64 && p->dtype != LBSEP_F32 && p->dtype != LBSEP_F16)
+    return why = "dtype must be LBSEP_F64, LBSEP_F32 or LBSEP_F16", false;
   if (p->hist_cap < 1) return why = "hist_cap must be >= 1", false;
   return true;
 }
 
 Layout make_layout(const lbsep_params* p) {
   Layout L{};
-  L.elem = p->dtype == LBSEP_F64 ? sizeof(double) : sizeof(float);
+  L.elem = elem_bytes(p->dtype);
   L.pitch = (int)align_up((size_t)p->nx, kTX);
   L.nxt = (p->nx + kTX - 1) / kTX;
   // rows per thread: the largest of 4, 2, 1 that still gives >= 1024 tiles
@@ -533,17 +727,28 @@ Layout make_layout(const lbsep_params* p) {
   L.nrt = (p->ny + kTY * L.rpt - 1) / (kTY * L.rpt);
   L.tiles = L.nxt * L.nrt;
   L.chunk = (L.tiles + 7) / 8;
+  L.nend = (p->ny + 127) / 128;
+  L.lead = (int)align_up((size_t)(2 * L.nend + L.nxt + 1), 8);
   L.state_buf = align_up(18ull * p->ny * L.pitch * L.elem, 256);
   size_t off = 0;
-  L.f0 = off; off += L.state_buf;
-  L.f1 = off; off += L.state_buf;
-  L.partials = off; off += align_up(4ull * L.nrt * L.pitch * sizeof(double), 256);
-  L.endsum = off; off += 256;
-  L.colsum = off; off += align_up(4ull * L.pitch * sizeof(double), 256);
-  L.strip = off; off += align_up(4ull * L.nxt * sizeof(double), 256);
-  L.hist = off; off += align_up(4ull * p->hist_cap * sizeof(double), 256);
-  L.counters = off; off += align_up((L.nxt + 2ull) * sizeof(unsigned), 256);
-  L.mom = off; off += align_up(6ull * p->ny * p->nx * sizeof(double), 256);
+  L.f0 = off;
+  off += L.state_buf;
+  L.f1 = off;
+  off += L.state_buf;
+  L.partials = off;
+  off += align_up(2ull * 4 * L.nrt * L.pitch * sizeof(double), 256);
+  L.endsum = off;
+  off += align_up(2ull * 2 * kMaxEnd * 4 * sizeof(double), 256);
+  L.colsum = off;
+  off += align_up(4ull * L.pitch * sizeof(double), 256);
+  L.strip = off;
+  off += align_up(2ull * 4 * L.nxt * sizeof(double), 256);
+  L.hist = off;
+  off += align_up(4ull * p->hist_cap * sizeof(double), 256);
+  L.status = off;
+  off += 256;
+  L.mom = off;
+  off += align_up(6ull * p->ny * p->nx * sizeof(double), 256);
   L.total = off;
   return L;
 }
@@ -562,10 +767,11 @@ struct lbsep_channel {
   char* ws;
   void* f[2];
   double* mom;
-  int cur;        // buffer holding f'(t)
-  bool prev_pre;  // the other buffer holds the pre-collision f(t) (after init / set_state)
+  int cur;          // buffer holding f'(t)
+  bool prev_pre;    // the other buffer holds the pre-collision f(t) (after init / set_state)
   int64_t t;
   int64_t t_first;  // first level with a history record
+  bool finalized;   // records of levels t-1 and t are complete
 };
 
 namespace {
@@ -575,39 +781,74 @@ int check_hip(hipError_t e, const char* what) {
   return LBSEP_OK;
 }
 
-template <typename T, bool PULL, bool EVAL>
-void launch_sweep(lbsep_channel* h, const void* src, void* dst, double* mom, void* fout, long long t) {
-  const int grid = kLeadBlocks + 8 * h->L.chunk;
-  hipLaunchKernelGGL((k_sweep<T, PULL, EVAL>), dim3(grid), dim3(kThreads), 0, h->stream, h->kp, h->kb,
-                     static_cast<const T*>(src), static_cast<T*>(dst), mom, static_cast<T*>(fout), t);
+template <class MD, bool PULL, bool EVAL>
+void launch_sweep(lbsep_channel* h, const void* src, void* dst, double* mom, void* fraw, double* ffull,
+                  long long t) {
+  using S = typename MD::St;
+  const int grid = h->L.lead + 8 * h->L.chunk;
+  hipLaunchKernelGGL((k_sweep<MD, PULL, EVAL>), dim3(grid), dim3(kThreads), 0, h->stream, h->kp, h->kb,
+                     static_cast<const S*>(src), static_cast<S*>(dst), mom, static_cast<S*>(fraw), ffull, t,
+                     (long long)h->t_first);
 }
 
 template <bool PULL, bool EVAL>
-void sweep_any(lbsep_channel* h, const void* src, void* dst, double* mom, void* fout, long long t) {
-  if (h->p.dtype == LBSEP_F64)
-    launch_sweep<double, PULL, EVAL>(h, src, dst, mom, fout, t);
-  else
-    launch_sweep<float, PULL, EVAL>(h, src, dst, mom, fout, t);
+void sweep_any(lbsep_channel* h, const void* src, void* dst, double* mom, void* fraw, double* ffull, long long t) {
+  switch (h->p.dtype) {
+    case LBSEP_F64:
+      launch_sweep<ModeF64, PULL, EVAL>(h, src, dst, mom, fraw, ffull, t);
+      break;
+    case LBSEP_F32:
+      launch_sweep<ModeF32, PULL, EVAL>(h, src, dst, mom, fraw, ffull, t);
+      break;
+    default:
+      launch_sweep<ModeF16, PULL, EVAL>(h, src, dst, mom, fraw, ffull, t);
+      break;
+  }
 }
 
 // Collide the pre-collision state held in f[0] into f[1] at level t.
 int collide_loaded(lbsep_channel* h, int64_t t) {
-  sweep_any<false, false>(h, h->f[0], h->f[1], nullptr, nullptr, t);
+  h->t_first = t;
+  sweep_any<false, false>(h, h->f[0], h->f[1], nullptr, nullptr, nullptr, t);
   h->cur = 1;
   h->prev_pre = true;
   h->t = t;
-  h->t_first = t;
+  h->finalized = false;
   return check_hip(hipGetLastError(), "collide launch");
 }
 
-// EVAL sweep of the current state into mom and/or fout.
-int eval_state(lbsep_channel* h, double* mom, void* fout) {
+// Complete the records of the last two levels (idempotent).
+int finalize(lbsep_channel* h) {
+  if (h->finalized) return LBSEP_OK;
+  hipLaunchKernelGGL(k_finalize, dim3(h->L.nxt + 1), dim3(kThreads), 0, h->stream, h->kp, h->kb,
+                     (long long)h->t, (long long)h->t_first, 0);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, h->stream, h->kp, h->kb, (long long)h->t,
+                     (long long)h->t_first, 1);
+  h->finalized = true;
+  return check_hip(hipGetLastError(), "finalize launch");
+}
+
+// EVAL sweep of the current state into mom, fraw and/or ffull.
+int eval_state(lbsep_channel* h, double* mom, void* fraw, double* ffull) {
   const void* prev = h->f[1 - h->cur];
   if (h->prev_pre)
-    sweep_any<false, true>(h, prev, nullptr, mom, fout, h->t);
+    sweep_any<false, true>(h, prev, nullptr, mom, fraw, ffull, h->t);
   else
-    sweep_any<true, true>(h, prev, nullptr, mom, fout, h->t);
+    sweep_any<true, true>(h, prev, nullptr, mom, fraw, ffull, h->t);
   return check_hip(hipGetLastError(), "eval launch");
+}
+
+template <class MD>
+void launch_init(lbsep_channel* h, double p_in, double p_out) {
+  const int igrid = (int)std::min<long long>(4096, ((long long)h->p.ny * h->L.pitch + 255) / 256);
+  hipLaunchKernelGGL(k_init<MD>, dim3(igrid), dim3(kThreads), 0, h->stream, h->kp,
+                     static_cast<typename MD::St*>(h->f[0]), p_in, p_out, h->p.cl_in, h->p.cl_out);
+}
+
+template <class MD>
+void launch_set_pop(lbsep_channel* h, const double* src) {
+  hipLaunchKernelGGL(k_set_pop<MD>, dim3(2048), dim3(256), 0, h->stream, h->kp, src,
+                     static_cast<typename MD::St*>(h->f[0]));
 }
 
 }  // namespace
@@ -631,7 +872,7 @@ size_t lbsep_state_bytes(const lbsep_params* p) {
     fail(LBSEP_EINVAL, why);
     return 0;
   }
-  return 18ull * p->ny * p->nx * (p->dtype == LBSEP_F64 ? sizeof(double) : sizeof(float));
+  return 18ull * p->ny * p->nx * elem_bytes(p->dtype);
 }
 
 double lbsep_dbb_r_from_cm(double c_m, double m_a, double m_b, double cl) {
@@ -650,8 +891,7 @@ int lbsep_init(const lbsep_params* p, void* dev_ws, size_t ws_bytes, void* hip_s
   if (!dev_ws || (reinterpret_cast<uintptr_t>(dev_ws) & 255u))
     return fail(LBSEP_EINVAL, "dev_ws must be a non-NULL 256-byte aligned device pointer");
   const Layout L = make_layout(p);
-  if (ws_bytes < L.total)
-    return fail(LBSEP_ESIZE, "workspace too small: need " + std::to_string(L.total) + " bytes");
+  if (ws_bytes < L.total) return fail(LBSEP_ESIZE, "workspace too small: need " + std::to_string(L.total) + " bytes");
   lbsep_channel* h = new (std::nothrow) lbsep_channel();
   if (!h) return fail(LBSEP_EDEVICE, "out of host memory");
   h->p = *p;
@@ -663,6 +903,7 @@ int lbsep_init(const lbsep_params* p, void* dev_ws, size_t ws_bytes, void* hip_s
   h->mom = reinterpret_cast<double*>(h->ws + L.mom);
 
   KParams& kp = h->kp;
+  const bool px = p->flags & LBSEP_PERIODIC_X;
   const double m_min = p->m_a;  // validated: m_a <= m_b
   const double cs2 = 1.0 / 3.0, p_out = cs2, p_in = p->theta * cs2;
   kp.nx = p->nx;
@@ -673,6 +914,8 @@ int lbsep_init(const lbsep_params* p, void* dev_ws, size_t ws_bytes, void* hip_s
   kp.rpt = L.rpt;
   kp.tiles = L.tiles;
   kp.chunk = L.chunk;
+  kp.lead = L.lead;
+  kp.nend = L.nend;
   kp.plane = (long long)p->ny * L.pitch;
   kp.flags = p->flags;
   kp.r = p->dbb_r;
@@ -683,6 +926,7 @@ int lbsep_init(const lbsep_params* p, void* dev_ws, size_t ws_bytes, void* hip_s
   rc.s[0] = m_min / p->m_a;
   rc.s[1] = m_min / p->m_b;
   rc.lam_p = p->kn_out * double(p->ny) * p_out;
+  rc.inv_lam_p = 1.0 / rc.lam_p;
   rc.kpref = std::sqrt(6.0 * m_min / M_PI);
   rc.dpref = 1.5 * std::sqrt(3.0 * (p->m_a + p->m_b) * p->m_a * p->m_b / m_min);
   const double a1 = (2.0 - p->accom) / p->accom * (1.0 - 0.1817 * p->accom);  // Eq. (A12)
@@ -699,6 +943,17 @@ int lbsep_init(const lbsep_params* p, void* dev_ws, size_t ws_bytes, void* hip_s
   kp.rho_bc[0][1] = (1.0 - p->cl_in) * p_in / (rc.s[1] * cs2);
   kp.rho_bc[1][0] = p->cl_out * p_out / (rc.s[0] * cs2);
   kp.rho_bc[1][1] = (1.0 - p->cl_out) * p_out / (rc.s[1] * cs2);
+  // reference density of the deviation modes and the lattice weights w_i alpha_si
+  static const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+  static const int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+  for (int s = 0; s < 2; ++s) {
+    kp.ref0[s] = kp.rho_bc[0][s];
+    kp.slope[s] = px ? 0.0 : (kp.rho_bc[1][s] - kp.rho_bc[0][s]) / double(p->nx - 1);
+    for (int i = 0; i < 9; ++i) {
+      kp.wa[s][i] = w[i] * (i == 0 ? (9.0 - 5.0 * rc.s[s]) / 4.0 : rc.s[s]);
+      kp.corr[s][i] = -double(cx[i]) * kp.wa[s][i] * kp.slope[s];
+    }
+  }
 
   KBufs& kb = h->kb;
   kb.partials = reinterpret_cast<double*>(h->ws + L.partials);
@@ -706,18 +961,22 @@ int lbsep_init(const lbsep_params* p, void* dev_ws, size_t ws_bytes, void* hip_s
   kb.colsum = reinterpret_cast<double*>(h->ws + L.colsum);
   kb.strip = reinterpret_cast<double*>(h->ws + L.strip);
   kb.hist = reinterpret_cast<double*>(h->ws + L.hist);
-  kb.counters = reinterpret_cast<unsigned*>(h->ws + L.counters);
-  kb.status = kb.counters + (L.nxt + 1);
+  kb.status = reinterpret_cast<unsigned*>(h->ws + L.status);
   kb.hist_cap = p->hist_cap;
+  kb.part_stride = 4LL * L.nrt * L.pitch;
 
-  hipLaunchKernelGGL(k_zero_u32, dim3((L.nxt + 2 + 255) / 256), dim3(256), 0, h->stream, kb.counters, L.nxt + 2);
-  const int igrid = (int)std::min<long long>(4096, ((long long)p->ny * L.pitch + 255) / 256);
-  if (p->dtype == LBSEP_F64)
-    hipLaunchKernelGGL(k_init<double>, dim3(igrid), dim3(kThreads), 0, h->stream, kp,
-                       static_cast<double*>(h->f[0]), p_in, p_out, p->cl_in, p->cl_out);
-  else
-    hipLaunchKernelGGL(k_init<float>, dim3(igrid), dim3(kThreads), 0, h->stream, kp,
-                       static_cast<float*>(h->f[0]), p_in, p_out, p->cl_in, p->cl_out);
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(256), 0, h->stream, kb.status, 1);
+  switch (p->dtype) {
+    case LBSEP_F64:
+      launch_init<ModeF64>(h, p_in, p_out);
+      break;
+    case LBSEP_F32:
+      launch_init<ModeF32>(h, p_in, p_out);
+      break;
+    default:
+      launch_init<ModeF16>(h, p_in, p_out);
+      break;
+  }
   int rc_ = check_hip(hipGetLastError(), "init launch");
   if (rc_ == LBSEP_OK) rc_ = collide_loaded(h, 0);
   if (rc_ != LBSEP_OK) {
@@ -733,10 +992,11 @@ int lbsep_step(lbsep_channel* h, int64_t nsteps) {
   if (nsteps < 0) return fail(LBSEP_EINVAL, "nsteps must be >= 0");
   for (int64_t n = 0; n < nsteps; ++n) {
     const int nxt_buf = 1 - h->cur;
-    sweep_any<true, false>(h, h->f[h->cur], h->f[nxt_buf], nullptr, nullptr, (long long)(h->t + 1));
+    sweep_any<true, false>(h, h->f[h->cur], h->f[nxt_buf], nullptr, nullptr, nullptr, (long long)(h->t + 1));
     h->cur = nxt_buf;
     h->prev_pre = false;
     h->t += 1;
+    h->finalized = false;
   }
   return check_hip(hipGetLastError(), "step launch");
 }
@@ -745,6 +1005,7 @@ int64_t lbsep_time(const lbsep_channel* h) { return h ? h->t : -1; }
 
 int lbsep_read_cl(lbsep_channel* h, double* cl, double* cl_tilde, int32_t* x_min, double* profile) {
   if (!h) return fail(LBSEP_EINVAL, "channel is NULL");
+  if (int e = finalize(h)) return e;
   double rec[4];
   unsigned status = 0;
   const double* src = h->kb.hist + (h->t % h->kb.hist_cap) * 4;
@@ -775,6 +1036,7 @@ int lbsep_read_cl(lbsep_channel* h, double* cl, double* cl_tilde, int32_t* x_min
 
 int lbsep_read_column_sums(lbsep_channel* h, double* host) {
   if (!h || !host) return fail(LBSEP_EINVAL, "NULL argument");
+  if (int e = finalize(h)) return e;
   int rc = check_hip(hipMemcpy2DAsync(host, h->p.nx * sizeof(double), h->kb.colsum, h->L.pitch * sizeof(double),
                                       h->p.nx * sizeof(double), 4, hipMemcpyDeviceToHost, h->stream),
                      "column sums copy");
@@ -785,6 +1047,7 @@ int lbsep_read_column_sums(lbsep_channel* h, double* host) {
 int lbsep_read_history(lbsep_channel* h, int64_t t0, int64_t count, double* host) {
   if (!h || (!host && count > 0) || count < 0) return fail(LBSEP_EINVAL, "bad argument");
   if (count == 0) return LBSEP_OK;
+  if (int e = finalize(h)) return e;
   const int64_t oldest = std::max<int64_t>(h->t_first, h->t - h->kb.hist_cap + 1);
   if (t0 < oldest || t0 + count - 1 > h->t)
     return fail(LBSEP_ERANGE, "history levels kept: " + std::to_string(oldest) + ".." + std::to_string(h->t));
@@ -803,7 +1066,7 @@ int lbsep_read_history(lbsep_channel* h, int64_t t0, int64_t count, double* host
 
 int lbsep_read_moments(lbsep_channel* h, double* host) {
   if (!h || !host) return fail(LBSEP_EINVAL, "NULL argument");
-  int rc = eval_state(h, h->mom, nullptr);
+  int rc = eval_state(h, h->mom, nullptr, nullptr);
   if (rc) return rc;
   rc = check_hip(hipMemcpyAsync(host, h->mom, 6ull * h->p.ny * h->p.nx * sizeof(double), hipMemcpyDeviceToHost,
                                 h->stream),
@@ -814,23 +1077,69 @@ int lbsep_read_moments(lbsep_channel* h, double* host) {
 
 int lbsep_get_state(lbsep_channel* h, void* dev_dst) {
   if (!h || !dev_dst) return fail(LBSEP_EINVAL, "NULL argument");
-  return eval_state(h, nullptr, dev_dst);
+  return eval_state(h, nullptr, dev_dst, nullptr);
+}
+
+int lbsep_get_populations(lbsep_channel* h, double* dev_dst) {
+  if (!h || !dev_dst) return fail(LBSEP_EINVAL, "NULL argument");
+  return eval_state(h, nullptr, nullptr, dev_dst);
 }
 
 int lbsep_set_state(lbsep_channel* h, const void* dev_src, int64_t t) {
   if (!h || !dev_src) return fail(LBSEP_EINVAL, "NULL argument");
   if (t < 0) return fail(LBSEP_EINVAL, "t must be >= 0");
-  const int grid = 2048;
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(256), 0, h->stream, h->kb.status, 1);
-  if (h->p.dtype == LBSEP_F64)
-    hipLaunchKernelGGL(k_copy_in<double>, dim3(grid), dim3(256), 0, h->stream, h->kp,
-                       static_cast<const double*>(dev_src), static_cast<double*>(h->f[0]));
-  else
-    hipLaunchKernelGGL(k_copy_in<float>, dim3(grid), dim3(256), 0, h->stream, h->kp,
-                       static_cast<const float*>(dev_src), static_cast<float*>(h->f[0]));
+  switch (h->p.dtype) {
+    case LBSEP_F64:
+      hipLaunchKernelGGL(k_copy_in<double>, dim3(2048), dim3(256), 0, h->stream, h->kp,
+                         static_cast<const double*>(dev_src), static_cast<double*>(h->f[0]));
+      break;
+    case LBSEP_F32:
+      hipLaunchKernelGGL(k_copy_in<float>, dim3(2048), dim3(256), 0, h->stream, h->kp,
+                         static_cast<const float*>(dev_src), static_cast<float*>(h->f[0]));
+      break;
+    default:
+      hipLaunchKernelGGL(k_copy_in<_Float16>, dim3(2048), dim3(256), 0, h->stream, h->kp,
+                         static_cast<const _Float16*>(dev_src), static_cast<_Float16*>(h->f[0]));
+      break;
+  }
   int rc = check_hip(hipGetLastError(), "set_state copy");
   if (rc) return rc;
   return collide_loaded(h, t);
+}
+
+int lbsep_set_populations(lbsep_channel* h, const double* dev_src, int64_t t) {
+  if (!h || !dev_src) return fail(LBSEP_EINVAL, "NULL argument");
+  if (t < 0) return fail(LBSEP_EINVAL, "t must be >= 0");
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(256), 0, h->stream, h->kb.status, 1);
+  switch (h->p.dtype) {
+    case LBSEP_F64:
+      launch_set_pop<ModeF64>(h, dev_src);
+      break;
+    case LBSEP_F32:
+      launch_set_pop<ModeF32>(h, dev_src);
+      break;
+    default:
+      launch_set_pop<ModeF16>(h, dev_src);
+      break;
+  }
+  int rc = check_hip(hipGetLastError(), "set_populations");
+  if (rc) return rc;
+  return collide_loaded(h, t);
+}
+
+int lbsep_wall_function(const double* dev_alpha, double* dev_psi, double* dev_h, int64_t n, int32_t dtype,
+                        void* hip_stream) {
+  if (n < 0 || (n > 0 && (!dev_alpha || !dev_psi))) return fail(LBSEP_EINVAL, "bad argument");
+  if (dtype != LBSEP_F64 && dtype != LBSEP_F32 && dtype != LBSEP_F16) return fail(LBSEP_EINVAL, "bad dtype");
+  if (n == 0) return LBSEP_OK;
+  const int grid = (int)std::min<int64_t>(1024, (n + 255) / 256);
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  if (dtype == LBSEP_F64)
+    hipLaunchKernelGGL(k_wall_function<double>, dim3(grid), dim3(256), 0, st, dev_alpha, dev_psi, dev_h, (long long)n);
+  else
+    hipLaunchKernelGGL(k_wall_function<float>, dim3(grid), dim3(256), 0, st, dev_alpha, dev_psi, dev_h, (long long)n);
+  return check_hip(hipGetLastError(), "wall function launch");
 }
 
 void lbsep_destroy(lbsep_channel* h) { delete h; }

@@ -11,38 +11,47 @@
 
 namespace lbsep {
 
-// Precision traits: table, cut-off and math entry points per storage type.
+// Precision traits: table, cut-off and math entry points per arithmetic type.
+// double: IEEE-exact library exp / log / sqrt and division (the FP64 path is
+// the reference precision). float: the hardware exp2 / log2 / reciprocal /
+// reciprocal square root (about 1 ulp), enough for the FP32 paths' 1e-5 bound.
 template <typename T> struct E1Traits;
 
 template <> struct E1Traits<double> {
   static constexpr int kSeg = LBSEP_E1_F64_NSEG;
   static constexpr int kDeg = LBSEP_E1_F64_DEG;
   static constexpr int kSer = LBSEP_E1_F64_NSER;
-  __device__ static double ser(int k) { return lbsep_e1_series_f64[k]; }
+  __device__ static double pa(int k) { return lbsep_psi_a_f64[k]; }
+  __device__ static double pb(int k) { return lbsep_psi_b_f64[k]; }
   __device__ static double cheb(int s, int k) { return lbsep_e1_cheb_f64[s][k]; }
   __device__ static double ex(double a) { return exp(a); }
   __device__ static double ln(double a) { return log(a); }
   __device__ static double rsq(double a) { return 1.0 / sqrt(a); }
+  __device__ static double rcp(double a) { return 1.0 / a; }
 };
 
 template <> struct E1Traits<float> {
   static constexpr int kSeg = LBSEP_E1_F32_NSEG;
   static constexpr int kDeg = LBSEP_E1_F32_DEG;
   static constexpr int kSer = LBSEP_E1_F32_NSER;
-  __device__ static float ser(int k) { return lbsep_e1_series_f32[k]; }
+  __device__ static float pa(int k) { return lbsep_psi_a_f32[k]; }
+  __device__ static float pb(int k) { return lbsep_psi_b_f32[k]; }
   __device__ static float cheb(int s, int k) { return lbsep_e1_cheb_f32[s][k]; }
-  __device__ static float ex(float a) { return expf(a); }
-  __device__ static float ln(float a) { return logf(a); }
-  __device__ static float rsq(float a) { return 1.0f / sqrtf(a); }
+  __device__ static float ex(float a) { return __builtin_amdgcn_exp2f(a * 1.4426950408889634f); }
+  __device__ static float ln(float a) { return __builtin_amdgcn_logf(a) * 0.6931471805599453f; }
+  __device__ static float rsq(float a) { return __builtin_amdgcn_rsqf(a); }
+  __device__ static float rcp(float a) { return __builtin_amdgcn_rcpf(a); }
 };
 
-// psi(a) = 1 + (a - 1) e^-a - a^2 E1(a) (wall function of Sec. 3.1) and
-// h(a) = e^-a - a E1(a) = psi'(a) / 2.
-//   a <= 1      : E1 = -gamma - ln a + S(a), S the entire series (Horner).
+// psi(a) = 1 + (a - 1) e^-a - a^2 E1(a) (wall function of Sec. 3.1) and, when
+// WANT_H, h(a) = e^-a - a E1(a) = psi'(a) / 2.
+//   a <= 1      : psi = A(a) + a^2 ln a, h = B(a) + a ln a, with A and B entire
+//                 power series (Horner); one logarithm, no exponential.
 //   1 < a < 2^n : E1 = e^-a G(a) / a with G(a) = a e^a E1(a) from the octave's
-//                 Chebyshev interpolant (Clenshaw), so psi = 1 + e^-a (a - 1 - a G).
-//   beyond      : psi = 1 and h = 0 to the storage precision.
-template <typename T>
+//                 Chebyshev interpolant (Clenshaw), so psi = 1 + e^-a (a - 1 - a G)
+//                 and h = e^-a (1 - G).
+//   beyond      : psi = 1 and h = 0 to the arithmetic's precision.
+template <typename T, bool WANT_H>
 __device__ __forceinline__ void wall_psi(T a, T& psi, T& h) {
   using E = E1Traits<T>;
   if (!(a > T(0))) {
@@ -51,14 +60,17 @@ __device__ __forceinline__ void wall_psi(T a, T& psi, T& h) {
     return;
   }
   if (a <= T(1)) {
-    T s = E::ser(E::kSer - 1);
+    const T la = E::ln(a);
+    T A = E::pa(E::kSer - 1);
 #pragma unroll
-    for (int k = E::kSer - 2; k >= 0; --k) s = s * a + E::ser(k);
-    s *= a;
-    const T e1 = -T(LBSEP_EULER_GAMMA) - E::ln(a) + s;
-    const T ea = E::ex(-a);
-    psi = T(1) + (a - T(1)) * ea - a * a * e1;
-    h = ea - a * e1;
+    for (int k = E::kSer - 2; k >= 1; --k) A = A * a + E::pa(k);
+    psi = A * a + a * a * la;  // alpha_0 = 0
+    if (WANT_H) {
+      T B = E::pb(E::kSer - 1);
+#pragma unroll
+      for (int k = E::kSer - 2; k >= 0; --k) B = B * a + E::pb(k);
+      h = B + a * la;
+    }
     return;
   }
   const int seg = ilogb(a);
@@ -67,26 +79,39 @@ __device__ __forceinline__ void wall_psi(T a, T& psi, T& h) {
     h = T(0);
     return;
   }
-  // t = (2a - 3 * 2^seg) / 2^seg, exact
-  const T t = ldexp(a, 1 - seg) - T(3);
-  const T t2 = t + t;
-  T b1 = T(0), b2 = T(0);
+  // Clenshaw on the octave's Chebyshev series, one octave at a time over a
+  // wave-uniform loop: the coefficients are then scalar loads shared by the
+  // wave (a wave's arguments usually span one or two octaves).
+  T g = T(0);
+  for (int sg = 0; sg < E::kSeg; ++sg) {
+    if (!__any(seg == sg)) continue;
+    // t = (2a - 3 * 2^sg) / 2^sg, exact for the lanes of this octave
+    const T t = ldexp(a, 1 - sg) - T(3);
+    const T t2 = t + t;
+    T b1 = T(0), b2 = T(0);
 #pragma unroll
-  for (int k = E::kDeg; k >= 1; --k) {
-    const T b0 = E::cheb(seg, k) + t2 * b1 - b2;
-    b2 = b1;
-    b1 = b0;
+    for (int k = E::kDeg; k >= 1; --k) {
+      const T b0 = E::cheb(sg, k) + t2 * b1 - b2;
+      b2 = b1;
+      b1 = b0;
+    }
+    const T gs = E::cheb(sg, 0) + t * b1 - b2;
+    if (seg == sg) g = gs;
   }
-  const T g = E::cheb(seg, 0) + t * b1 - b2;
   const T ea = E::ex(-a);
   psi = T(1) + ea * (a - T(1) - a * g);
-  h = ea * (T(1) - g);
+  if (WANT_H) h = ea * (T(1) - g);
+}
+
+template <typename T>
+__device__ __forceinline__ void wall_psi(T a, T& psi, T& h) {
+  wall_psi<T, true>(a, psi, h);
 }
 
 template <typename T>
 __device__ __forceinline__ T wall_psi_only(T a) {
   T p, h;
-  wall_psi(a, p, h);
+  wall_psi<T, false>(a, p, h);
   return p;
 }
 
@@ -95,6 +120,7 @@ struct RelaxConsts {
   double inv_m[2];  // 1 / m_sigma
   double s[2];      // s_sigma = m_min / m_sigma
   double lam_p;     // lambda * P = Kn_out * H * P_out (mean free path at pressure P is lam_p / P)
+  double inv_lam_p; // 1 / lam_p
   double kpref;     // sqrt(6 m_min / pi): k = kpref / sqrt(m_x) in Eq. (taos)
   double dpref;     // (3/2) sqrt(3 m_0 m_a m_b / m_min): Eq. (EQFrsp) prefactor times m_x
   double tq_a;      // 24 varsigma^2 A2 (= 4 pi A2), Eq. (taoq)
@@ -117,12 +143,13 @@ __device__ __forceinline__ void relaxation_times(const RelaxConsts& c, int j, T 
   }
   const T na = rho_a * T(c.inv_m[0]);
   const T nb = rho_b * T(c.inv_m[1]);
-  const T inv_n = T(1) / (na + nb);
+  const T inv_n = E::rcp(na + nb);
   const T xa = na * inv_n;
   const T xb = nb * inv_n;
   const T mx = (rho_a + rho_b) * inv_n;                                  // m_x = rho / n
   const T pres = T(1.0 / 3.0) * (T(c.s[0]) * rho_a + T(c.s[1]) * rho_b);  // P = n k_B T
-  const T lam = T(c.lam_p) / pres;                                       // mean free path at P
+  const T il = pres * T(c.inv_lam_p);                                    // 1 / lambda
+  const T lam = T(c.lam_p) * E::rcp(pres);                               // mean free path at P
   const T k = T(c.kpref) * E::rsq(mx);                                   // sqrt(6 m_min / (pi m_x))
   T psi_m, psi_a, psi_b, tt0, dtt0;
   if (c.mfp_off) {
@@ -130,7 +157,6 @@ __device__ __forceinline__ void relaxation_times(const RelaxConsts& c, int j, T 
     tt0 = k * lam;
     dtt0 = T(0);
   } else {
-    const T il = pres / T(c.lam_p);                                      // 1 / lambda
     const T y = T(j) + T(0.5);
     const T yb = T(c.height) - y;
     const T ay = y * il, ab = yb * il;
@@ -147,9 +173,10 @@ __device__ __forceinline__ void relaxation_times(const RelaxConsts& c, int j, T 
   }
   tau_s = T(0.5) + lam * psi_m * k;                                      // Eq. (taos)
   const T sa = E::rsq(psi_a) + E::rsq(psi_b);
-  tau_d = T(0.5) + T(c.dpref) * lam / (mx * sa * sa);                     // Eq. (EQFrsp)
-  tau_q = T(0.5) + (T(3) + T(c.tq_a) * tt0 * tt0) / (T(16) * tt0) +
-          dtt0 * (T(12) + T(c.tq_b) * tt0) / (T(16) * tt0 * tt0);         // Eq. (taoq)
+  tau_d = T(0.5) + T(c.dpref) * lam * E::rcp(mx * sa * sa);               // Eq. (EQFrsp)
+  const T r0 = E::rcp(tt0);
+  tau_q = T(0.5) + (T(3) * r0 + T(c.tq_a) * tt0) * T(1.0 / 16.0) +
+          dtt0 * (T(12) * r0 * r0 + T(c.tq_b) * r0) * T(1.0 / 16.0);      // Eq. (taoq)
 }
 
 // MRT collision of one species in the moment space of Eq. (m):
@@ -158,24 +185,31 @@ __device__ __forceinline__ void relaxation_times(const RelaxConsts& c, int j, T 
 // (rho, rho(2s-4) + 3 rho|u|^2, rho(4-3s) - 3 rho|u|^2, rho ux, -rho ux,
 //  rho uy, -rho uy, rho(ux^2 - uy^2), rho ux uy).
 // M^-1 = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4).
+//
+// The populations may be deviations d = f - f0 from the rest equilibrium
+// f0 = w_i alpha_i rho0 of a reference density rho0: M f0 is
+// (rho0, rho0(2s-4), rho0(4-3s), 0, ..., 0), so the same update holds for d
+// with the conserved part rho_c = rho - rho0 in place of rho in the terms
+// linear in the density (first three moments), while the velocity terms keep
+// the full density rho. For plain populations rho_c = rho.
 template <typename T>
-__device__ __forceinline__ void collide_species(T f[9], T rho, T ux, T uy, T s, T w_e, T w_eps, T w_d, T w_q,
-                                                T w_s) {
-  const T sa = f[1] + f[2] + f[3] + f[4];
-  const T sd = f[5] + f[6] + f[7] + f[8];
+__device__ __forceinline__ void collide_species(T f[9], T rho_c, T rho, T ux, T uy, T s, T w_e, T w_eps, T w_d,
+                                                T w_q, T w_s) {
+  const T sa = (f[1] + f[2]) + (f[3] + f[4]);
+  const T sd = (f[5] + f[6]) + (f[7] + f[8]);
   T e = T(-4) * f[0] - sa + T(2) * sd;
   T eps = T(4) * f[0] - T(2) * sa + sd;
-  T jx = f[1] - f[3] + f[5] - f[6] - f[7] + f[8];
-  T qx = T(-2) * (f[1] - f[3]) + f[5] - f[6] - f[7] + f[8];
-  T jy = f[2] - f[4] + f[5] + f[6] - f[7] - f[8];
-  T qy = T(-2) * (f[2] - f[4]) + f[5] + f[6] - f[7] - f[8];
-  T pxx = f[1] - f[2] + f[3] - f[4];
-  T pxy = f[5] - f[6] + f[7] - f[8];
+  T jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+  T qx = T(-2) * (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+  T jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+  T qy = T(-2) * (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+  T pxx = (f[1] - f[2]) + (f[3] - f[4]);
+  T pxy = (f[5] - f[6]) + (f[7] - f[8]);
 
   const T u2 = ux * ux + uy * uy;
   const T jxe = rho * ux, jye = rho * uy;
-  e -= w_e * (e - (rho * (T(2) * s - T(4)) + T(3) * rho * u2));
-  eps -= w_eps * (eps - (rho * (T(4) - T(3) * s) - T(3) * rho * u2));
+  e -= w_e * (e - (rho_c * (T(2) * s - T(4)) + T(3) * rho * u2));
+  eps -= w_eps * (eps - (rho_c * (T(4) - T(3) * s) - T(3) * rho * u2));
   jx -= w_d * (jx - jxe);
   qx -= w_q * (qx + jxe);
   jy -= w_d * (jy - jye);
@@ -183,7 +217,7 @@ __device__ __forceinline__ void collide_species(T f[9], T rho, T ux, T uy, T s, 
   pxx -= w_s * (pxx - rho * (ux * ux - uy * uy));
   pxy -= w_s * (pxy - rho * ux * uy);
 
-  const T a0 = rho * T(1.0 / 9.0);
+  const T a0 = rho_c * T(1.0 / 9.0);
   const T a1 = e * T(1.0 / 36.0);
   const T a2 = eps * T(1.0 / 36.0);
   const T a3 = jx * T(1.0 / 6.0);

@@ -19,9 +19,9 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblbsep.so
 
 OK, EINVAL, ESIZE, EDEVICE, ENONFINITE, ERANGE = 0, -1, -2, -3, -4, -5
 PERIODIC_X, PERIODIC_Y, MFP_OFF, BGK_TEST = 0x1, 0x2, 0x4, 0x8
-F64, F32 = 0, 1
-_DTYPES = {"f64": F64, "f32": F32}
-_TORCH = {F64: torch.float64, F32: torch.float32}
+F64, F32, F16 = 0, 1, 2
+_DTYPES = {"f64": F64, "f32": F32, "f16": F16}
+_TORCH = {F64: torch.float64, F32: torch.float32, F16: torch.float16}
 
 
 class LbsepError(RuntimeError):
@@ -67,7 +67,10 @@ def load():
         "lbsep_read_moments": (c_int, [c_void_p, POINTER(c_double)]),
         "lbsep_get_state": (c_int, [c_void_p, c_void_p]),
         "lbsep_set_state": (c_int, [c_void_p, c_void_p, c_int64]),
+        "lbsep_get_populations": (c_int, [c_void_p, c_void_p]),
+        "lbsep_set_populations": (c_int, [c_void_p, c_void_p, c_int64]),
         "lbsep_dbb_r_from_cm": (c_double, [c_double, c_double, c_double, c_double]),
+        "lbsep_wall_function": (c_int, [c_void_p, c_void_p, c_void_p, c_int64, c_int32, c_void_p]),
         "lbsep_destroy": (None, [c_void_p]),
         "lbsep_last_error": (c_char_p, []),
     }
@@ -104,6 +107,19 @@ def workspace_bytes(params: Params) -> int:
 
 def dbb_r_from_cm(c_m: float, m_a: float, m_b: float, cl: float) -> float:
     return load().lbsep_dbb_r_from_cm(c_m, m_a, m_b, cl)
+
+
+def wall_function(alpha: torch.Tensor, dtype="f64"):
+    """(psi, psi'/2) of the device wall function for a float64 cuda tensor."""
+    if alpha.dtype != torch.float64 or alpha.device.type != "cuda":
+        raise ValueError("alpha must be a float64 cuda tensor")
+    a = alpha.contiguous()
+    psi = torch.empty_like(a)
+    h = torch.empty_like(a)
+    code = _DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
+    _check(load().lbsep_wall_function(c_void_p(a.data_ptr()), c_void_p(psi.data_ptr()), c_void_p(h.data_ptr()),
+                                      a.numel(), code, c_void_p(torch.cuda.current_stream().cuda_stream)))
+    return psi, h
 
 
 def _dptr(a: np.ndarray):
@@ -177,6 +193,7 @@ class Channel:
         return out
 
     def get_state(self) -> torch.Tensor:
+        """Raw state in the storage type (f for f64, deviations for f32/f16)."""
         out = torch.empty((2, 9, self.ny, self.nx), dtype=self.dtype, device=self.device)
         _check(load().lbsep_get_state(self._h, c_void_p(out.data_ptr())))
         return out
@@ -187,6 +204,19 @@ class Channel:
         f = f.contiguous()
         _check(load().lbsep_set_state(self._h, c_void_p(f.data_ptr()), int(t)))
         self._keep = f  # keep the source alive until the stream has consumed it
+
+    def get_populations(self) -> torch.Tensor:
+        """Pre-collision populations f in float64, whatever the storage type."""
+        out = torch.empty((2, 9, self.ny, self.nx), dtype=torch.float64, device=self.device)
+        _check(load().lbsep_get_populations(self._h, c_void_p(out.data_ptr())))
+        return out
+
+    def set_populations(self, f: torch.Tensor, t: int = 0):
+        if f.shape != (2, 9, self.ny, self.nx) or f.dtype != torch.float64 or f.device.type != "cuda":
+            raise ValueError(f"populations must be a float64 cuda tensor of shape (2, 9, {self.ny}, {self.nx})")
+        f = f.contiguous()
+        _check(load().lbsep_set_populations(self._h, c_void_p(f.data_ptr()), int(t)))
+        self._keep = f
 
     def synchronize(self):
         self.stream.synchronize()

@@ -91,4 +91,4 @@ def random_state(ny: int, nx: int, seed: int, scale=(1.0, 8.0), spread: float = 
     f = 1.0 + spread * rng.uniform(-1.0, 1.0, size=shape)
     f[0] *= scale[0] / 9.0
     f[1] *= scale[1] / 9.0
-    return np.ascontiguousarray(np.broadcast_to(f, (2, 9, ny, nx)))
+    return np.array(np.broadcast_to(f, (2, 9, ny, nx)), dtype=np.float64, copy=True)

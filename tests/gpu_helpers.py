@@ -32,13 +32,35 @@ def r_of(w):
 
 
 def field_errors(got, ref):
-    """Normwise relative error per moment field: max|got - ref| / max|ref|."""
-    return [float(np.max(np.abs(got[k] - ref[k])) / max(np.max(np.abs(ref[k])), 1e-300)) for k in range(len(ref))]
+    """Normwise relative errors of the species moment vectors (rho_s, rho_s u_s):
+    max|d rho_s| / max|rho_s| and max|d (rho_s u_s)| / max|rho_s| (both velocity
+    components). The momentum is a sum of O(rho) populations, so its rounding
+    error scales with the density, not with the (possibly tiny) velocity; it is
+    measured on that scale."""
+    errs = []
+    for k in (0, 1):
+        errs.append(float(np.max(np.abs(got[k] - ref[k])) / max(np.max(np.abs(ref[k])), 1e-300)))
+    for k, r in ((2, 0), (4, 1)):
+        scale = max(np.max(np.abs(ref[r])), 1e-300)
+        dj = max(np.max(np.abs(got[r] * got[k] - ref[r] * ref[k])),
+                 np.max(np.abs(got[r] * got[k + 1] - ref[r] * ref[k + 1])))
+        errs.append(float(dj / scale))
+    return errs
+
+
+def velocity_errors(got, ref):
+    """max|d u_s| / max|u_s| per species (both components): reported, not the
+    pass criterion, since it is ill-conditioned where the flow is slow."""
+    out = []
+    for k in (2, 4):
+        scale = max(np.max(np.abs(ref[k])), np.max(np.abs(ref[k + 1])), 1e-300)
+        out.append(float(max(np.max(np.abs(got[k] - ref[k])), np.max(np.abs(got[k + 1] - ref[k + 1]))) / scale))
+    return out
 
 
 def assert_moments(got, ref, tol, what=""):
     errs = field_errors(got, ref)
-    names = ["rho_a", "rho_b", "u_ax", "u_ay", "u_bx", "u_by"]
+    names = ["rho_a", "rho_b", "j_a", "j_b"]
     bad = {names[k]: e for k, e in enumerate(errs) if not e <= tol}
     assert not bad, f"{what}: moment fields beyond {tol:g}: {bad}"
     return max(errs)
@@ -46,3 +68,11 @@ def assert_moments(got, ref, tol, what=""):
 
 def assert_cl(got, ref, rel, abs_):
     assert abs(got - ref) <= rel * abs(ref) + abs_, (got, ref)
+
+
+def assert_argmin(got_x, profile_ref, margin=1e-11):
+    """The column of the smallest C_l must match where the minimum is unique by
+    more than round-off; within the margin any of the tied columns is valid."""
+    m = profile_ref.min()
+    tied = np.flatnonzero(profile_ref <= m + margin)
+    assert got_x in tied, (got_x, tied[:10])

@@ -86,9 +86,13 @@ def _single_species_step(f, ny, nx, kn, r, rho_in, rho_out, accom=1.0):
         out = fp[lev[0], row] + fp[lev[1], row] + fp[lev[2], row]
         for iu, il, share in zip(unk, lev, (4 / 6, 1 / 6, 1 / 6)):
             fn[iu, row] = r * share * out + (1 - r) * fp[il, row]
-    for col, c1, c2, rb in ((0, 1, 2, rho_in), (nx - 1, nx - 2, nx - 3, rho_out)):
-        ext = 2 * fn[:, :, c1] - fn[:, :, c2]
-        fn[:, :, col] = ext * (ny * rb / ext.sum())
+    # ends: directions entering from the reservoir are extrapolated, then the
+    # node is rescaled to the corrected extrapolated density
+    for col, c1, c2, rb, enter in ((0, 1, 2, rho_in, (1, 5, 8)), (nx - 1, nx - 2, nx - 3, rho_out, (3, 6, 7))):
+        fn[list(enter), :, col] = 2 * fn[list(enter), :, c1] - fn[list(enter), :, c2]
+        target = 2 * fn[:, :, c1].sum(0) - fn[:, :, c2].sum(0)
+        target = target * (ny * rb / target.sum())
+        fn[:, :, col] = fn[:, :, col] * (target / fn[:, :, col].sum(0))
     return fn
 
 

@@ -302,20 +302,39 @@ def test_species_mass_conserved_with_walls(r):
 
 # --- Inlet/outlet (Eqs. (rho1), (rho2)), P8 -------------------------------------------
 def test_inlet_outlet_impose_mean_density_and_mole_fraction():
+    """Eq. (rho2): the boundary column's mean species density is rho_bc exactly
+    and its density profile is proportional to the extrapolated profile
+    2 rho(1, j) - rho(2, j) of Eq. (rho1); hence C_l(0) = C_in, C_l(nx-1) = C_out.
+    The populations leaving the channel through the boundary node keep the
+    direction split they streamed in with (only the density is corrected)."""
     rng = _rng(10)
     p = O.Params(nx=10, ny=6, m_a=4, m_b=40, cl_in=0.7, cl_out=0.3, theta=2.5, kn_out=0.2, dbb_r=1.1)
     fpost = O.initial_state(p) * (1 + 0.03 * rng.standard_normal((2, 9, 6, 10)))
     fnew = O.stream(fpost, p)
     rin, rout = O.boundary_densities(p)
     for sig in range(2):
-        assert abs(fnew[sig, :, :, 0].sum() / 6 - rin[sig]) < 1e-13 * rin[sig]
-        assert abs(fnew[sig, :, :, -1].sum() / 6 - rout[sig]) < 1e-13 * rout[sig]
-        # the column is a multiple of the linear extrapolation of the inner layers
-        ext = 2 * fnew[sig, :, :, 1] - fnew[sig, :, :, 2]
-        ratio = fnew[sig, :, :, 0] / ext
-        assert np.allclose(ratio, ratio.flat[0], rtol=1e-13)
+        for col, l1, l2, rbc in ((0, 1, 2, rin[sig]), (9, 8, 7, rout[sig])):
+            rho_col = fnew[sig, :, :, col].sum(0)
+            assert abs(rho_col.mean() - rbc) < 1e-13 * rbc
+            ext = 2 * fnew[sig, :, :, l1].sum(0) - fnew[sig, :, :, l2].sum(0)
+            assert np.allclose(rho_col / ext, (rho_col / ext)[0], rtol=1e-13)
+        # inlet node, interior row: direction 3 streams in from column 1 (c_x = -1)
+        # and direction 0 stays; their ratio is untouched by the correction
+        assert abs(fnew[sig, 3, 2, 0] / fnew[sig, 0, 2, 0] - fpost[sig, 3, 2, 1] / fpost[sig, 0, 2, 0]) < 1e-13
     d = O.diagnostics(fnew, p)
     assert abs(d.cl_profile[0] - 0.7) < 1e-14 and abs(d.cl_profile[-1] - 0.3) < 1e-14
+
+
+def test_end_closure_is_linearly_stable_where_extrapolating_every_population_is_not():
+    """R14 evidence: with the unknown-population closure a 1e-12 perturbation
+    of the He-Ar H = 8, Kn_out = 0.1 channel does not grow over 1500 steps."""
+    p = O.Params(nx=80, ny=8, m_a=4, m_b=40, cl_in=0.5, cl_out=0.5, theta=2, kn_out=0.1,
+                 dbb_r=O.dbb_r_from_cm(0.8183, 4, 40, 0.5))
+    f = O.initial_state(p)
+    g = f * (1 + 1e-12 * _rng(5).standard_normal(f.shape))
+    for _ in range(1500):
+        f, g = O.step(f, p), O.step(g, p)
+    assert np.abs(f - g).max() / np.abs(f).max() < 1e-12
 
 
 def test_initial_state_has_zero_separation():
