@@ -73,6 +73,11 @@ extern "C" {
 #define LBSEP_F32 1 /* deviations from the rest equilibrium stored and collided in float     */
 #define LBSEP_F16 2 /* deviations stored as IEEE binary16, collided in float                 */
 
+/* ---- tile shape of the sweep (lbsep_params.tile_mode) ----------------- */
+#define LBSEP_TILE_AUTO 0  /* chosen from the channel size                                */
+#define LBSEP_TILE_SPLIT 1 /* two lanes per node, one per species (latency-bound channels) */
+#define LBSEP_TILE_NODE 2  /* one lane per node (channels that fill the GPU many times)   */
+
 /* Problem statement (Sec. 2) plus the DBB inputs of Sec. 3.2. */
 typedef struct lbsep_params {
   int32_t nx;       /* columns along the flow (channel length L): >= 6, or >= 1 with PERIODIC_X */
@@ -89,6 +94,7 @@ typedef struct lbsep_params {
   uint32_t flags;   /* LBSEP_PERIODIC_X | LBSEP_PERIODIC_Y | LBSEP_MFP_OFF | LBSEP_BGK_TEST      */
   int32_t dtype;    /* LBSEP_F64, LBSEP_F32 or LBSEP_F16                                         */
   int32_t hist_cap; /* per-step diagnostic records kept on the device (ring), >= 1               */
+  int32_t tile_mode; /* LBSEP_TILE_AUTO / _SPLIT / _NODE: how nodes map to lanes (same results)  */
 } lbsep_params;
 
 typedef struct lbsep_channel lbsep_channel;

@@ -38,7 +38,9 @@
 // state f'(t), the other the previous post-collision state f'(t-1) (or, right
 // after init / set_state, the pre-collision state f(t)).
 //
-// Work decomposition: a block is 4 wavefronts = 64 columns x (4 * rpt) rows.
+// Work decomposition: a node is a lane pair, one lane per species. A tile
+// block is 4 wavefronts = 32 columns x (4 * rpt) rows; in each wavefront lanes
+// 0-31 hold species a and lanes 32-63 species b of the same 32 columns.
 // Lead blocks come first: 2 nend blocks own the inlet and outlet columns,
 // 128 rows each (they need whole-column sums of the inner layers before they
 // can rebuild the boundary nodes, so each end block sums the full column);
@@ -80,7 +82,8 @@ using ModeF16 = Mode<_Float16, float, true>;
 struct KParams {
   RelaxConsts rc;
   int nx, ny, pitch;
-  int nxt, nrt, rpt;    // column strips, row tiles, rows per thread
+  int nxt, nrt, rpt;    // 64-column reduction strips, row tiles, rows per thread
+  int ntx;              // 32-column tile strips
   int tiles, chunk;     // nxt * nrt, ceil(tiles / 8)
   int lead;             // lead blocks (multiple of 8) before the first tile
   int nend;             // blocks per inlet/outlet column (128 rows each)
@@ -250,40 +253,34 @@ __device__ __forceinline__ void end_node(const KParams& kp, const typename MD::S
 }
 
 // Moments, relaxation times and (STEP) collision + store or (EVAL) output of
-// one node. acc receives (n_a, n_b, rho_a u_ax, rho_b u_bx) in double.
+// one node by one lane holding both species (fa, fb: populations, deviations
+// in the FP32/FP16 modes). acc receives (n_a, n_b, rho_a u_ax, rho_b u_bx).
 template <class MD, bool EVAL>
 __device__ __forceinline__ void process_node(const KParams& kp, int x, int j, typename MD::Ct fa[9],
                                              typename MD::Ct fb[9], typename MD::St* __restrict__ dst,
                                              double* __restrict__ mom, typename MD::St* __restrict__ fraw,
                                              double* __restrict__ ffull, double acc[4]) {
   using C = typename MD::Ct;
+  using E = E1Traits<C>;
   const C ca = sum9(fa);  // rho_a, or rho_a - rho0_a(x)
   const C cb = sum9(fb);
-  double ra_d, rb_d;      // species densities in double
-  C rho_a, rho_b;
-  if (MD::kDev) {
-    ra_d = ref_rho(kp, 0, x) + double(ca);
-    rb_d = ref_rho(kp, 1, x) + double(cb);
-    rho_a = C(ra_d);
-    rho_b = C(rb_d);
-  } else {
-    ra_d = double(ca);
-    rb_d = double(cb);
-    rho_a = ca;
-    rho_b = cb;
-  }
+  const double r0a = MD::kDev ? ref_rho(kp, 0, x) : 0.0;
+  const double r0b = MD::kDev ? ref_rho(kp, 1, x) : 0.0;
+  const double ra_d = MD::kDev ? r0a + double(ca) : double(ca);
+  const double rb_d = MD::kDev ? r0b + double(cb) : double(cb);
+  const C rho_a = MD::kDev ? C(ra_d) : ca;
+  const C rho_b = MD::kDev ? C(rb_d) : cb;
   const C jxa = (fa[1] - fa[3]) + (fa[5] - fa[6]) + (fa[8] - fa[7]);
   const C jya = (fa[2] - fa[4]) + (fa[5] + fa[6]) - (fa[7] + fa[8]);
   const C jxb = (fb[1] - fb[3]) + (fb[5] - fb[6]) + (fb[8] - fb[7]);
   const C jyb = (fb[2] - fb[4]) + (fb[5] + fb[6]) - (fb[7] + fb[8]);
-  const C rho = rho_a + rho_b;
-  const C inv_rho = E1Traits<C>::rcp(rho);
-  const C ux = (jxa + jxb) * inv_rho;
+  const C inv_rho = E::rcp(rho_a + rho_b);
+  const C ux = (jxa + jxb) * inv_rho;  // mixture velocity, Eq. (rhou)
   const C uy = (jya + jyb) * inv_rho;
   C ts, td, tq;
   relaxation_times<C>(kp.rc, j, rho_a, rho_b, ts, td, tq);
   // species momentum of Eq. (rhou): rho_s u_s = (1 - 1/(2 tau_d)) j_s + rho_s u / (2 tau_d)
-  const C h2 = C(0.5) * E1Traits<C>::rcp(td);
+  const C h2 = C(0.5) * E::rcp(td);
   const C g = C(1) - h2;
   const C pxa = g * jxa + rho_a * ux * h2;
   const C pxb = g * jxb + rho_b * ux * h2;
@@ -308,8 +305,6 @@ __device__ __forceinline__ void process_node(const KParams& kp, int x, int j, ty
       }
     }
     if (ffull) {
-      const double r0a = MD::kDev ? ref_rho(kp, 0, x) : 0.0;
-      const double r0b = MD::kDev ? ref_rho(kp, 1, x) : 0.0;
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
         ffull[i * n + o] = double(fa[i]) + (MD::kDev ? kp.wa[0][i] * r0a : 0.0);
@@ -323,14 +318,14 @@ __device__ __forceinline__ void process_node(const KParams& kp, int x, int j, ty
   acc[2] += double(pxa);
   acc[3] += double(pxb);
   C we, weps;
-  const C ws = E1Traits<C>::rcp(ts);
+  const C ws = E::rcp(ts);
   if (kp.rc.bgk) {
     we = weps = ws;
   } else {
     we = C(1.0 / 1.1);    // tau_e = 1.1 (Sec. 3.3)
     weps = C(1.0 / 1.2);  // tau_eps = 1.2
   }
-  const C wd = C(2) * h2, wq = E1Traits<C>::rcp(tq);
+  const C wd = C(2) * h2, wq = E::rcp(tq);
   collide_species<C>(fa, ca, rho_a, ux, uy, C(kp.rc.s[0]), we, weps, wd, wq, ws);
   collide_species<C>(fb, cb, rho_b, ux, uy, C(kp.rc.s[1]), we, weps, wd, wq, ws);
 #pragma unroll
@@ -338,6 +333,82 @@ __device__ __forceinline__ void process_node(const KParams& kp, int x, int j, ty
     *plane_at(kp, dst, 0, i, j, x) = typename MD::St(fa[i]);
     *plane_at(kp, dst, 1, i, j, x) = typename MD::St(fb[i]);
   }
+}
+
+// Moments, relaxation times and (STEP) collision + store or (EVAL) output of
+// one node by a lane pair: this lane holds species s (f: its 9 populations,
+// deviations in the FP32/FP16 modes), the partner lane (lane ^ XOR) the other
+// species. Every lane of the wave must call this (it swaps values across the
+// pair); lanes with active == false only feed the swaps. acc receives this
+// species' (n_s, rho_s u_sx) in double.
+template <class MD, bool EVAL, int XOR>
+__device__ __forceinline__ void process_pair(const KParams& kp, int x, int j, int s, bool active,
+                                             typename MD::Ct f[9], typename MD::St* __restrict__ dst,
+                                             double* __restrict__ mom, typename MD::St* __restrict__ fraw,
+                                             double* __restrict__ ffull, double acc[2]) {
+  using C = typename MD::Ct;
+  using E = E1Traits<C>;
+  if (!active) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) f[i] = MD::kDev ? C(0) : C(0.1);  // finite filler for the swaps
+  }
+  const C c_own = sum9(f);  // rho_s, or rho_s - rho0_s(x)
+  const double r0 = MD::kDev ? ref_rho(kp, s, x) : 0.0;
+  const double r_own = MD::kDev ? r0 + double(c_own) : double(c_own);
+  const C rho_own = MD::kDev ? C(r_own) : c_own;
+  const C jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+  const C jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+  const C rho_oth = __shfl_xor(rho_own, XOR);
+  const C jx_oth = __shfl_xor(jx, XOR);
+  const C jy_oth = __shfl_xor(jy, XOR);
+  const C rho_a = s ? rho_oth : rho_own;
+  const C rho_b = s ? rho_own : rho_oth;
+  const C jxa = s ? jx_oth : jx, jxb = s ? jx : jx_oth;
+  const C jya = s ? jy_oth : jy, jyb = s ? jy : jy_oth;
+  const C inv_rho = E::rcp(rho_a + rho_b);
+  const C ux = (jxa + jxb) * inv_rho;  // mixture velocity, Eq. (rhou)
+  const C uy = (jya + jyb) * inv_rho;
+  C ts, td, tq;
+  relaxation_times_pair<C, XOR>(kp.rc, j, s, rho_a, rho_b, ts, td, tq);
+  // species momentum of Eq. (rhou): rho_s u_s = (1 - 1/(2 tau_d)) j_s + rho_s u / (2 tau_d)
+  const C h2 = C(0.5) * E::rcp(td);
+  const C g = C(1) - h2;
+  const C px = g * jx + rho_own * ux * h2;
+  if (EVAL) {
+    if (!active) return;
+    const long long n = (long long)kp.nx * kp.ny;
+    const long long o = (long long)j * kp.nx + x;
+    if (mom) {
+      const C py = g * jy + rho_own * uy * h2;
+      mom[s * n + o] = r_own;
+      mom[(2 + 2 * s) * n + o] = double(px / rho_own);
+      mom[(3 + 2 * s) * n + o] = double(py / rho_own);
+    }
+    if (fraw) {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) fraw[(9 * s + i) * n + o] = typename MD::St(f[i]);
+    }
+    if (ffull) {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) ffull[(9 * s + i) * n + o] = double(f[i]) + (MD::kDev ? kp.wa[s][i] * r0 : 0.0);
+    }
+    return;
+  }
+  C we, weps;
+  const C ws = E::rcp(ts);
+  if (kp.rc.bgk) {
+    we = weps = ws;
+  } else {
+    we = C(1.0 / 1.1);    // tau_e = 1.1 (Sec. 3.3)
+    weps = C(1.0 / 1.2);  // tau_eps = 1.2
+  }
+  const C wd = C(2) * h2, wq = E::rcp(tq);
+  collide_species<C>(f, c_own, rho_own, ux, uy, C(kp.rc.s[s]), we, weps, wd, wq, ws);
+  if (!active) return;
+  acc[0] += r_own * kp.rc.inv_m[s];
+  acc[1] += double(px);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) *plane_at(kp, dst, s, i, j, x) = typename MD::St(f[i]);
 }
 
 // Column sums of one strip (64 columns) of level `step`: add the row-tile
@@ -458,7 +529,7 @@ __device__ void block_sum(double (*red)[kTY][kTX], const double* v, int nv) {
   __syncthreads();
 }
 
-template <class MD, bool PULL, bool EVAL>
+template <class MD, bool PULL, bool EVAL, bool SPLIT>
 __global__ __launch_bounds__(kThreads) void k_sweep(KParams kp, KBufs kb, const typename MD::St* __restrict__ src,
                                                     typename MD::St* __restrict__ dst, double* __restrict__ mom,
                                                     typename MD::St* __restrict__ fraw,
@@ -530,45 +601,76 @@ __global__ __launch_bounds__(kThreads) void k_sweep(KParams kp, KBufs kb, const 
       else
         gather1<MD, false>(kp, src, s, col, j, f);
     }
-    C g[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) g[i] = __shfl_xor(f[i], 1);
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    if (active && s == 0) process_node<MD, EVAL>(kp, col, j, f, g, dst, mom, fraw, ffull, acc);
+    double acc2[2] = {0.0, 0.0};
+    process_pair<MD, EVAL, 1>(kp, col, j, s, active, f, dst, mom, fraw, ffull, acc2);
     if (EVAL) return;
+    const double acc[4] = {s ? 0.0 : acc2[0], s ? acc2[0] : 0.0, s ? 0.0 : acc2[1], s ? acc2[1] : 0.0};
     block_sum(red, acc, 4);
     if (threadIdx.x < 4) kb.endsum[(((t & 1) * 2 + e) * kMaxEnd + blk) * 4 + threadIdx.x] = red[threadIdx.x][0][0];
     return;
   }
-  // ---- interior tile ---------------------------------------------------------
+  // ---- interior tile --------------------------------------------------------------
   const int xcd = b & 7;
   const int k = (b - kp.lead) >> 3;
   const int lin = xcd * kp.chunk + k;
   if (lin >= kp.tiles) return;
   const int bx = lin / kp.nrt;
   const int by = lin - bx * kp.nrt;
-  const int tx = threadIdx.x & (kTX - 1);
+  const int lane = threadIdx.x & (kTX - 1);
   const int ty = threadIdx.x / kTX;
-  const int x = bx * kTX + tx;
-  const bool xin = (x < kp.nx) && (px || (x > 0 && x < kp.nx - 1));
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int r = 0; r < kp.rpt; ++r) {
-    const int j = by * (kTY * kp.rpt) + r * kTY + ty;
-    if (xin && j < kp.ny) {
-      C fa[9], fb[9];
-      gather1<MD, PULL>(kp, src, 0, x, j, fa);
-      gather1<MD, PULL>(kp, src, 1, x, j, fb);
-      process_node<MD, EVAL>(kp, x, j, fa, fb, dst, mom, fraw, ffull, acc);
+  if (SPLIT) {
+    // 32 columns x (4 rpt) rows; lanes 0-31 hold species a, 32-63 species b
+    const int s = lane >> 5;
+    const int cx = lane & 31;
+    const int x = bx * 32 + cx;
+    const bool xin = (x < kp.nx) && (px || (x > 0 && x < kp.nx - 1));
+    double acc[2] = {0.0, 0.0};
+#pragma unroll 1
+    for (int r = 0; r < kp.rpt; ++r) {
+      const int j = by * (kTY * kp.rpt) + r * kTY + ty;
+      if (j < kp.ny) {  // wave-uniform
+        C f[9];
+        if (xin) gather1<MD, PULL>(kp, src, s, x, j, f);
+        process_pair<MD, EVAL, 32>(kp, x, j, s, xin, f, dst, mom, fraw, ffull, acc);
+      }
     }
-  }
-  if (EVAL) return;
-  // per-column sums of this row tile (4 wavefronts -> 1), quantity q = ty
+    if (EVAL) return;
+    // per-column sums of this row tile: quantity q = s (n_s) and 2 + s (rho_s u_sx)
+    red[s][ty][cx] = acc[0];
+    red[2 + s][ty][cx] = acc[1];
+    __syncthreads();
+    if (threadIdx.x < 128) {
+      const int q = threadIdx.x >> 5, c = threadIdx.x & 31;
+      const int xc = bx * 32 + c;
+      if (xc < kp.nx) {
+        const double v = ((red[q][0][c] + red[q][1][c]) + red[q][2][c]) + red[q][3][c];
+        kb.partials[(t & 1) * kb.part_stride + ((long long)q * kp.nrt + by) * kp.pitch + xc] = v;
+      }
+    }
+  } else {
+    // 64 columns x (4 rpt) rows, one lane per node
+    const int x = bx * kTX + lane;
+    const bool xin = (x < kp.nx) && (px || (x > 0 && x < kp.nx - 1));
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+    for (int r = 0; r < kp.rpt; ++r) {
+      const int j = by * (kTY * kp.rpt) + r * kTY + ty;
+      if (xin && j < kp.ny) {
+        C fa[9], fb[9];
+        gather1<MD, PULL>(kp, src, 0, x, j, fa);
+        gather1<MD, PULL>(kp, src, 1, x, j, fb);
+        process_node<MD, EVAL>(kp, x, j, fa, fb, dst, mom, fraw, ffull, acc);
+      }
+    }
+    if (EVAL) return;
+    // per-column sums of this row tile (4 wavefronts -> 1), quantity q = ty
 #pragma unroll
-  for (int q = 0; q < 4; ++q) red[q][ty][tx] = acc[q];
-  __syncthreads();
-  if (x < kp.nx) {
-    const double s = ((red[ty][0][tx] + red[ty][1][tx]) + red[ty][2][tx]) + red[ty][3][tx];
-    kb.partials[(t & 1) * kb.part_stride + ((long long)ty * kp.nrt + by) * kp.pitch + x] = s;
+    for (int q = 0; q < 4; ++q) red[q][ty][lane] = acc[q];
+    __syncthreads();
+    if (x < kp.nx) {
+      const double v = ((red[ty][0][lane] + red[ty][1][lane]) + red[ty][2][lane]) + red[ty][3][lane];
+      kb.partials[(t & 1) * kb.part_stride + ((long long)ty * kp.nrt + by) * kp.pitch + x] = v;
+    }
   }
 }
 
@@ -680,7 +782,8 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 size_t elem_bytes(int dtype) { return dtype == LBSEP_F64 ? 8 : dtype == LBSEP_F32 ? 4 : 2; }
 
 struct Layout {
-  int pitch, nxt, nrt, rpt, tiles, chunk, lead, nend;
+  int pitch, nxt, ntx, nrt, rpt, tiles, chunk, lead, nend;
+  bool split;
   size_t elem, state_buf, f0, f1, partials, endsum, colsum, strip, hist, status, mom, total;
 };
 
@@ -707,6 +810,7 @@ bool validate(const lbsep_params* p, std::string& why) {
   if (p->dtype != LBSEP_F64 && p->dtype != LBSEP_F32 && p->dtype != LBSEP_F16)
     return why = "dtype must be LBSEP_F64, LBSEP_F32 or LBSEP_F16", false;
   if (p->hist_cap < 1) return why = "hist_cap must be >= 1", false;
+  if (p->tile_mode < LBSEP_TILE_AUTO || p->tile_mode > LBSEP_TILE_NODE) return why = "bad tile_mode", false;
   return true;
 }
 
@@ -715,17 +819,29 @@ Layout make_layout(const lbsep_params* p) {
   L.elem = elem_bytes(p->dtype);
   L.pitch = (int)align_up((size_t)p->nx, kTX);
   L.nxt = (p->nx + kTX - 1) / kTX;
-  // rows per thread: the largest of 4, 2, 1 that still gives >= 1024 tiles
+  // Tile shape: a lane pair per node (species split) halves each lane's chain,
+  // which pays where one wave per SIMD or less is available (latency-bound
+  // small channels); one lane per node does less work per node, which pays
+  // when the channel fills the GPU many times over.
+  if (p->tile_mode == LBSEP_TILE_SPLIT)
+    L.split = true;
+  else if (p->tile_mode == LBSEP_TILE_NODE)
+    L.split = false;
+  else
+    L.split = (long long)p->nx * p->ny <= (1LL << 19);
+  const int cols = L.split ? 32 : 64;
+  L.ntx = (p->nx + cols - 1) / cols;
+  // rows per thread: the largest of 4, 2, 1 that still gives >= 2048 tiles
   L.rpt = 1;
   for (int r : {4, 2}) {
     const int nrt = (p->ny + kTY * r - 1) / (kTY * r);
-    if ((long long)L.nxt * nrt >= 1024) {
+    if ((long long)L.ntx * nrt >= 2048) {
       L.rpt = r;
       break;
     }
   }
   L.nrt = (p->ny + kTY * L.rpt - 1) / (kTY * L.rpt);
-  L.tiles = L.nxt * L.nrt;
+  L.tiles = L.ntx * L.nrt;
   L.chunk = (L.tiles + 7) / 8;
   L.nend = (p->ny + 127) / 128;
   L.lead = (int)align_up((size_t)(2 * L.nend + L.nxt + 1), 8);
@@ -786,9 +902,14 @@ void launch_sweep(lbsep_channel* h, const void* src, void* dst, double* mom, voi
                   long long t) {
   using S = typename MD::St;
   const int grid = h->L.lead + 8 * h->L.chunk;
-  hipLaunchKernelGGL((k_sweep<MD, PULL, EVAL>), dim3(grid), dim3(kThreads), 0, h->stream, h->kp, h->kb,
-                     static_cast<const S*>(src), static_cast<S*>(dst), mom, static_cast<S*>(fraw), ffull, t,
-                     (long long)h->t_first);
+  if (h->L.split)
+    hipLaunchKernelGGL((k_sweep<MD, PULL, EVAL, true>), dim3(grid), dim3(kThreads), 0, h->stream, h->kp, h->kb,
+                       static_cast<const S*>(src), static_cast<S*>(dst), mom, static_cast<S*>(fraw), ffull, t,
+                       (long long)h->t_first);
+  else
+    hipLaunchKernelGGL((k_sweep<MD, PULL, EVAL, false>), dim3(grid), dim3(kThreads), 0, h->stream, h->kp, h->kb,
+                       static_cast<const S*>(src), static_cast<S*>(dst), mom, static_cast<S*>(fraw), ffull, t,
+                       (long long)h->t_first);
 }
 
 template <bool PULL, bool EVAL>
@@ -911,6 +1032,7 @@ int lbsep_init(const lbsep_params* p, void* dev_ws, size_t ws_bytes, void* hip_s
   kp.pitch = L.pitch;
   kp.nxt = L.nxt;
   kp.nrt = L.nrt;
+  kp.ntx = L.ntx;
   kp.rpt = L.rpt;
   kp.tiles = L.tiles;
   kp.chunk = L.chunk;

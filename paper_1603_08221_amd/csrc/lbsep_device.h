@@ -83,6 +83,7 @@ __device__ __forceinline__ void wall_psi(T a, T& psi, T& h) {
   // wave-uniform loop: the coefficients are then scalar loads shared by the
   // wave (a wave's arguments usually span one or two octaves).
   T g = T(0);
+#pragma unroll 1
   for (int sg = 0; sg < E::kSeg; ++sg) {
     if (!__any(seg == sg)) continue;
     // t = (2a - 3 * 2^sg) / 2^sg, exact for the lanes of this octave
@@ -131,52 +132,108 @@ struct RelaxConsts {
   int bgk;
 };
 
-// Relaxation times of one node from its species densities (recomputed every
-// step from the pre-collision state).
+// Relaxation times of one node, recomputed every step from its pre-collision
+// state. The common part (mixture quantities and mean free path) and the final
+// formulas are shared; the seven wall-function evaluations are either done by
+// one lane (relaxation_times) or split over a lane pair (relaxation_times_pair).
+template <typename T>
+struct NodeGas {
+  T xa, xb, mx, il, lam, k;
+};
+
+template <typename T>
+__device__ __forceinline__ NodeGas<T> node_gas(const RelaxConsts& c, T rho_a, T rho_b) {
+  using E = E1Traits<T>;
+  NodeGas<T> g;
+  const T na = rho_a * T(c.inv_m[0]);
+  const T nb = rho_b * T(c.inv_m[1]);
+  const T inv_n = E::rcp(na + nb);
+  g.xa = na * inv_n;
+  g.xb = nb * inv_n;
+  g.mx = (rho_a + rho_b) * inv_n;                                        // m_x = rho / n
+  const T pres = T(1.0 / 3.0) * (T(c.s[0]) * rho_a + T(c.s[1]) * rho_b);  // P = n k_B T
+  g.il = pres * T(c.inv_lam_p);                                          // 1 / lambda (R5)
+  g.lam = T(c.lam_p) * E::rcp(pres);                                     // mean free path at P
+  g.k = T(c.kpref) * E::rsq(g.mx);                                       // sqrt(6 m_min / (pi m_x))
+  return g;
+}
+
+// tau_s (Eq. (taos)), tau_d (Eq. (EQFrsp)), tau_q (Eq. (taoq)) from the wall
+// function values Psi(y; lambda), Psi(y; lambda_a), Psi(y; lambda_b) and the wall
+// values tau~_s(0), tau~'_s(0).
+template <typename T>
+__device__ __forceinline__ void taus_from_psi(const RelaxConsts& c, const NodeGas<T>& g, T psi_m, T psi_a, T psi_b,
+                                              T tt0, T dtt0, T& tau_s, T& tau_d, T& tau_q) {
+  using E = E1Traits<T>;
+  tau_s = T(0.5) + g.lam * psi_m * g.k;
+  const T sa = E::rsq(psi_a) + E::rsq(psi_b);
+  tau_d = T(0.5) + T(c.dpref) * g.lam * E::rcp(g.mx * sa * sa);
+  const T r0 = E::rcp(tt0);
+  tau_q = T(0.5) + (T(3) * r0 + T(c.tq_a) * tt0) * T(1.0 / 16.0) +
+          dtt0 * (T(12) * r0 * r0 + T(c.tq_b) * r0) * T(1.0 / 16.0);
+}
+
+// One lane per node: all seven wall-function evaluations here.
 template <typename T>
 __device__ __forceinline__ void relaxation_times(const RelaxConsts& c, int j, T rho_a, T rho_b, T& tau_s,
                                                  T& tau_d, T& tau_q) {
-  using E = E1Traits<T>;
   if (c.bgk) {
     tau_s = tau_d = tau_q = T(c.tau_bgk);
     return;
   }
-  const T na = rho_a * T(c.inv_m[0]);
-  const T nb = rho_b * T(c.inv_m[1]);
-  const T inv_n = E::rcp(na + nb);
-  const T xa = na * inv_n;
-  const T xb = nb * inv_n;
-  const T mx = (rho_a + rho_b) * inv_n;                                  // m_x = rho / n
-  const T pres = T(1.0 / 3.0) * (T(c.s[0]) * rho_a + T(c.s[1]) * rho_b);  // P = n k_B T
-  const T il = pres * T(c.inv_lam_p);                                    // 1 / lambda
-  const T lam = T(c.lam_p) * E::rcp(pres);                               // mean free path at P
-  const T k = T(c.kpref) * E::rsq(mx);                                   // sqrt(6 m_min / (pi m_x))
-  T psi_m, psi_a, psi_b, tt0, dtt0;
+  const NodeGas<T> g = node_gas<T>(c, rho_a, rho_b);
   if (c.mfp_off) {
-    psi_m = psi_a = psi_b = T(1);
-    tt0 = k * lam;
-    dtt0 = T(0);
-  } else {
-    const T y = T(j) + T(0.5);
-    const T yb = T(c.height) - y;
-    const T ay = y * il, ab = yb * il;
-    psi_m = T(0.5) * (wall_psi_only(ay) + wall_psi_only(ab));
-    // lambda_sigma = lambda / x_sigma  ->  y / lambda_sigma = x_sigma y / lambda
-    psi_a = T(0.5) * (wall_psi_only(xa * ay) + wall_psi_only(xa * ab));
-    psi_b = T(0.5) * (wall_psi_only(xb * ay) + wall_psi_only(xb * ab));
-    // wall values for Eq. (taoq): tau~_s(0) = k lam psi(H/lam) / 2 and
-    // tau~'_s(0) = (k/2) (psi'(0) - psi'(H/lam)) = k (1 - h(H/lam))
-    T pw, hw;
-    wall_psi(T(c.height) * il, pw, hw);
-    tt0 = T(0.5) * k * lam * pw;
-    dtt0 = k * (T(1) - hw);
+    taus_from_psi<T>(c, g, T(1), T(1), T(1), g.k * g.lam, T(0), tau_s, tau_d, tau_q);
+    return;
   }
-  tau_s = T(0.5) + lam * psi_m * k;                                      // Eq. (taos)
-  const T sa = E::rsq(psi_a) + E::rsq(psi_b);
-  tau_d = T(0.5) + T(c.dpref) * lam * E::rcp(mx * sa * sa);               // Eq. (EQFrsp)
-  const T r0 = E::rcp(tt0);
-  tau_q = T(0.5) + (T(3) * r0 + T(c.tq_a) * tt0) * T(1.0 / 16.0) +
-          dtt0 * (T(12) * r0 * r0 + T(c.tq_b) * r0) * T(1.0 / 16.0);      // Eq. (taoq)
+  const T y = T(j) + T(0.5);
+  const T ay = y * g.il, ab = (T(c.height) - y) * g.il;
+  const T psi_m = T(0.5) * (wall_psi_only(ay) + wall_psi_only(ab));
+  // lambda_sigma = lambda / x_sigma  ->  y / lambda_sigma = x_sigma y / lambda (R6)
+  const T psi_a = T(0.5) * (wall_psi_only(g.xa * ay) + wall_psi_only(g.xa * ab));
+  const T psi_b = T(0.5) * (wall_psi_only(g.xb * ay) + wall_psi_only(g.xb * ab));
+  // wall values (R8): tau~_s(0) = k lam psi(H/lam) / 2, tau~'_s(0) = k (1 - h(H/lam))
+  T pw, hw;
+  wall_psi(T(c.height) * g.il, pw, hw);
+  taus_from_psi<T>(c, g, psi_m, psi_a, psi_b, T(0.5) * g.k * g.lam * pw, g.k * (T(1) - hw), tau_s, tau_d,
+                   tau_q);
+}
+
+// A lane pair per node (one lane per species, partner at lane ^ XOR): both
+// lanes hold the node's species densities; the seven evaluations are split
+// four / three between the lanes and the results swapped, so both lanes end
+// with identical tau values.
+template <typename T, int XOR>
+__device__ __forceinline__ void relaxation_times_pair(const RelaxConsts& c, int j, int s, T rho_a, T rho_b,
+                                                      T& tau_s, T& tau_d, T& tau_q) {
+  if (c.bgk) {
+    tau_s = tau_d = tau_q = T(c.tau_bgk);
+    return;
+  }
+  const NodeGas<T> g = node_gas<T>(c, rho_a, rho_b);
+  if (c.mfp_off) {
+    taus_from_psi<T>(c, g, T(1), T(1), T(1), g.k * g.lam, T(0), tau_s, tau_d, tau_q);
+    return;
+  }
+  const T y = T(j) + T(0.5);
+  const T ay = y * g.il, ab = (T(c.height) - y) * g.il;
+  // lane a: psi(y/l), psi((H-y)/l), psi(x_a y/l), psi(x_a (H-y)/l)
+  // lane b: psi(x_b y/l), psi(x_b (H-y)/l), psi and h of H/l
+  const T p0 = wall_psi_only(s ? g.xb * ay : ay);
+  const T p1 = wall_psi_only(s ? g.xb * ab : ab);
+  T p2, h2;
+  wall_psi<T, true>(s ? T(c.height) * g.il : g.xa * ay, p2, h2);
+  T p3 = T(0);
+  if (s == 0) p3 = wall_psi_only(g.xa * ab);
+  const T X = T(0.5) * (p0 + p1);           // lane a: Psi(y; l), lane b: Psi(y; l_b)
+  const T Y = s ? p2 : T(0.5) * (p2 + p3);  // lane a: Psi(y; l_a), lane b: psi(H/l)
+  const T Xo = __shfl_xor(X, XOR);
+  const T Yo = __shfl_xor(Y, XOR);
+  const T Zo = __shfl_xor(h2, XOR);
+  const T pw = s ? Y : Yo;
+  const T hw = s ? h2 : Zo;
+  taus_from_psi<T>(c, g, s ? Xo : X, s ? Yo : Y, s ? X : Xo, T(0.5) * g.k * g.lam * pw, g.k * (T(1) - hw), tau_s,
+                   tau_d, tau_q);
 }
 
 // MRT collision of one species in the moment space of Eq. (m):

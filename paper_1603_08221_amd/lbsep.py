@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblbsep.so
 
 OK, EINVAL, ESIZE, EDEVICE, ENONFINITE, ERANGE = 0, -1, -2, -3, -4, -5
 PERIODIC_X, PERIODIC_Y, MFP_OFF, BGK_TEST = 0x1, 0x2, 0x4, 0x8
+TILE_AUTO, TILE_SPLIT, TILE_NODE = 0, 1, 2
 F64, F32, F16 = 0, 1, 2
 _DTYPES = {"f64": F64, "f32": F32, "f16": F16}
 _TORCH = {F64: torch.float64, F32: torch.float32, F16: torch.float16}
@@ -38,7 +39,7 @@ class Params(ctypes.Structure):
         ("cl_in", c_double), ("cl_out", c_double),
         ("theta", c_double), ("kn_out", c_double),
         ("dbb_r", c_double), ("accom", c_double), ("tau_bgk", c_double),
-        ("flags", c_uint32), ("dtype", c_int32), ("hist_cap", c_int32),
+        ("flags", c_uint32), ("dtype", c_int32), ("hist_cap", c_int32), ("tile_mode", c_int32),
     ]
 
 
@@ -92,10 +93,10 @@ def _check(rc: int):
 
 
 def make_params(nx, ny, m_a, m_b, cl_in, cl_out, theta, kn_out, dbb_r, accom=1.0, tau_bgk=0.0,
-                flags=0, dtype="f64", hist_cap=4096) -> Params:
+                flags=0, dtype="f64", hist_cap=4096, tile_mode=TILE_AUTO) -> Params:
     return Params(int(nx), int(ny), float(m_a), float(m_b), float(cl_in), float(cl_out), float(theta),
                   float(kn_out), float(dbb_r), float(accom), float(tau_bgk), int(flags),
-                  _DTYPES[dtype] if isinstance(dtype, str) else int(dtype), int(hist_cap))
+                  _DTYPES[dtype] if isinstance(dtype, str) else int(dtype), int(hist_cap), int(tile_mode))
 
 
 def workspace_bytes(params: Params) -> int:
