@@ -126,6 +126,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 reference leg (profiling runs)")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the leg on the 512 x 10240 channel (above the last-level cache)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device copy of this size (PMC calibration)")
     args = ap.parse_args()
@@ -205,6 +207,20 @@ def main():
         out["cl_err_vs_fp64"] = abs(cl32["cl"] - cl64["cl"])
         out["cl_ok"] = out["cl_err_vs_fp64"] <= 1e-5
         del ch64
+    if not args.no_large and w.name != "he_ar_512x10240":
+        wl = CONFIGS["he_ar_512x10240"]
+        chl, _ = make_channel(lbsep, wl, args.dtype, hist_cap=64)
+        chl.step(20)
+        nl = 200
+        wall_l, ev_l = time_steps(torch, chl, nl)
+        bl = wl.nodes * 36 * BYTES_PER_POP[args.dtype]
+        gbs = bl / (ev_l / 1e3 / nl) / 1e9
+        tr = measured_traffic(wl.name, args.dtype)
+        out["large_channel"] = {"workload": wl.name, "steps": nl, "mlups": round(wl.nodes * nl / wall_l / 1e6, 1),
+                                "us_per_step": round(ev_l * 1e3 / nl, 2), "gbps_algorithmic": round(gbs, 1),
+                                "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+                                "traffic": None if tr is None else round(tr), "cl": chl.read_cl()["cl"]}
+        del chl
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, r, args.cpu_seconds)
         out["fp64_vs_oracle"] = oracle_parity(lbsep, w, r, 100)
