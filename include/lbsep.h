@@ -81,7 +81,7 @@ extern "C" {
 /* Problem statement (Sec. 2) plus the DBB inputs of Sec. 3.2. */
 typedef struct lbsep_params {
   int32_t nx;       /* columns along the flow (channel length L): >= 6, or >= 1 with PERIODIC_X */
-  int32_t ny;       /* rows across the channel (H = ny lattice units, the N of Eq. (taoq)): >= 2  */
+  int32_t ny;       /* rows across the channel (H = ny lattice units, the N of Eq. (taoq)): 2..2048 */
   double m_a;       /* molecular mass of the light species, > 0                                   */
   double m_b;       /* molecular mass of the heavy species, >= m_a (only ratios matter)          */
   double cl_in;     /* light-species mole fraction at the inlet, in (0, 1)                        */

@@ -42,7 +42,7 @@
 // block is 4 wavefronts = 32 columns x (4 * rpt) rows; in each wavefront lanes
 // 0-31 hold species a and lanes 32-63 species b of the same 32 columns.
 // Lead blocks come first: 2 nend blocks own the inlet and outlet columns,
-// 128 rows each (they need whole-column sums of the inner layers before they
+// 64 rows each (they need whole-column sums of the inner layers before they
 // can rebuild the boundary nodes, so each end block sums the full column);
 // then nxt blocks reduce one column strip each of the previous step and one
 // block finishes the step before that; the lead count is rounded up to a
@@ -67,7 +67,7 @@ namespace {
 constexpr int kTX = 64;         // columns per block (one wavefront across x)
 constexpr int kTY = 4;          // wavefronts per block
 constexpr int kThreads = kTX * kTY;
-constexpr int kMaxEnd = 32;     // end blocks per inlet/outlet column: ny <= 128 * kMaxEnd
+constexpr int kMaxEnd = 32;     // end blocks per inlet/outlet column: ny <= 64 * kMaxEnd
 
 template <typename S, typename C, bool DEV>
 struct Mode {
@@ -86,7 +86,7 @@ struct KParams {
   int ntx;              // 32-column tile strips
   int tiles, chunk;     // nxt * nrt, ceil(tiles / 8)
   int lead;             // lead blocks (multiple of 8) before the first tile
-  int nend;             // blocks per inlet/outlet column (128 rows each)
+  int nend;             // blocks per inlet/outlet column (64 rows each)
   long long plane;      // ny * pitch
   unsigned flags;
   double r;             // DBB coefficient
@@ -212,21 +212,16 @@ __device__ __forceinline__ void gather1(const KParams& kp, const typename MD::St
 }
 
 // Rebuilt pre-collision node of species s on the inlet (e = 0) or outlet
-// (e = 1) column, Eqs. (rho1), (rho2): the populations entering from the
-// reservoir are extrapolated from the first and second inner layers, the node
-// is rescaled to kappa rho'(j) with rho' = 2 rho(l1, j) - rho(l2, j).
+// (e = 1) column, Eqs. (rho1), (rho2): f holds the node's pulled populations,
+// g1 / g2 those of the first / second inner layer. The populations entering
+// from the reservoir are extrapolated, then the node is rescaled to
+// kappa rho'(j) with rho' = 2 rho(l1, j) - rho(l2, j).
 // kap = kappa; km1 = kappa - 1 (used by the deviation modes).
 template <class MD>
-__device__ __forceinline__ void end_node(const KParams& kp, const typename MD::St* __restrict__ src, int e, int s,
-                                         int j, double kap, double km1, typename MD::Ct f[9]) {
+__device__ __forceinline__ void end_rebuild(const KParams& kp, int e, int s, int col, double kap, double km1,
+                                            const typename MD::Ct g1[9], const typename MD::Ct g2[9],
+                                            typename MD::Ct f[9]) {
   using C = typename MD::Ct;
-  const int col = e ? kp.nx - 1 : 0;
-  const int l1 = e ? kp.nx - 2 : 1;
-  const int l2 = e ? kp.nx - 3 : 2;
-  C g1[9], g2[9];
-  gather1<MD, true>(kp, src, s, col, j, f);
-  gather1<MD, true>(kp, src, s, l1, j, g1);
-  gather1<MD, true>(kp, src, s, l2, j, g2);
   if (e == 0) {  // entering at the inlet: c_x = +1
     f[1] = C(2) * g1[1] - g2[1];
     f[5] = C(2) * g1[5] - g2[5];
@@ -551,58 +546,72 @@ __global__ __launch_bounds__(kThreads) void k_sweep(KParams kp, KBufs kb, const 
       }
       return;
     }
-    // ---- inlet (e = 0) / outlet (e = 1) column, rows [128 blk, 128 blk + 128) ----
+    // ---- inlet (e = 0) / outlet (e = 1) column, rows [64 blk, 64 blk + 64) ----
+    // Lane L = 4 j' + 2 s + layer holds, for row j = 64 blk + j' and species s,
+    // the pulled populations of the first (layer 0) or second (layer 1) inner
+    // layer; layer-0 lanes also pull the boundary node itself. All these loads
+    // are in flight together; Eq. (rho2) then needs the whole column's sum of
+    // rho' (Eq. (rho1)) for kappa, after which the layer-0 lanes rebuild the
+    // node from their own and their layer-1 neighbour's values and collide it
+    // in species pairs (lanes L and L ^ 2).
     if (px) return;
     const int e = b / kp.nend;
     const int blk = b - e * kp.nend;
     const int col = e ? kp.nx - 1 : 0;
     const int l1 = e ? kp.nx - 2 : 1;
     const int l2 = e ? kp.nx - 3 : 2;  // first and second inner layers
-    double kap[2] = {1.0, 1.0}, km1[2] = {0.0, 0.0};
+    const int L = threadIdx.x;
+    const int layer = L & 1;
+    const int s = (L >> 1) & 1;
+    const int j = blk * 64 + (L >> 2);
+    const bool active = j < kp.ny;
+    C g[9], f[9];
+    double kap = 1.0, km1 = 0.0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) g[i] = f[i] = C(0);
     if (PULL) {
-      // Eq. (rho1): rho'(col, j) = 2 rho(l1, j) - rho(l2, j), summed over the
-      // whole column by every end block; Eq. (rho2): kappa. Items (j, s, layer).
-      double sums[2] = {0.0, 0.0};
-      for (int it = threadIdx.x; it < 4 * kp.ny; it += kThreads) {
-        const int j = it >> 2, s = (it >> 1) & 1, layer = it & 1;
-        C g[9];
+      if (active) {
         gather1<MD, true>(kp, src, s, layer ? l2 : l1, j, g);
-        const double rho_l = double(sum9(g));
-        const double v = layer ? -rho_l : 2.0 * rho_l;
-        if (s) sums[1] += v; else sums[0] += v;
+        if (layer == 0) gather1<MD, true>(kp, src, s, col, j, f);
+      }
+      // kappa needs sum_j rho'(col, j) over the whole column: own rows from the
+      // registers, the other end blocks' rows pulled again (sum only)
+      double sums[2] = {0.0, 0.0};
+      if (active) {
+        const double v = double(sum9(g));
+        if (s) sums[1] += layer ? -v : 2.0 * v; else sums[0] += layer ? -v : 2.0 * v;
+      }
+      for (int it = L; it < 4 * kp.ny; it += kThreads) {
+        const int jj = it >> 2;
+        if ((jj >> 6) == blk) continue;
+        const int ss = (it >> 1) & 1, ll = it & 1;
+        C h[9];
+        gather1<MD, true>(kp, src, ss, ll ? l2 : l1, jj, h);
+        const double v = double(sum9(h));
+        if (ss) sums[1] += ll ? -v : 2.0 * v; else sums[0] += ll ? -v : 2.0 * v;
       }
       block_sum(red, sums, 2);
-#pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        const double n = double(kp.ny), sum = red[s][0][0];
-        if (MD::kDev) {
-          // sum_j rho' = n rho0(col) + sum (deviation sums)
-          const double r0 = ref_rho(kp, s, col);
-          km1[s] = (n * (kp.rho_bc[e][s] - r0) - sum) / (n * r0 + sum);
-          kap[s] = 1.0 + km1[s];
-        } else {
-          kap[s] = n * kp.rho_bc[e][s] / sum;
-          km1[s] = kap[s] - 1.0;
-        }
+      const double n = double(kp.ny), sum = red[s][0][0];
+      __syncthreads();  // red is reused by the block sum below
+      if (MD::kDev) {
+        // sum_j rho' = n rho0(col) + sum (deviation sums)
+        const double r0 = ref_rho(kp, s, col);
+        km1 = (n * (kp.rho_bc[e][s] - r0) - sum) / (n * r0 + sum);
+        kap = 1.0 + km1;
+      } else {
+        kap = n * kp.rho_bc[e][s] / sum;
+        km1 = kap - 1.0;
       }
-      __syncthreads();
-    }
-    // items (j, s) on adjacent lanes: each lane rebuilds one species, the pair
-    // swaps populations and the even lane collides the node
-    const int it = blk * kThreads + (int)threadIdx.x;
-    const int j = it >> 1, s = it & 1;
-    const bool active = j < kp.ny;
-    C f[9];
+      // layer-1 values to the layer-0 lane of the same (row, species)
+      C g2[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) f[i] = C(0);
-    if (active) {
-      if (PULL)
-        end_node<MD>(kp, src, e, s, j, kap[s], km1[s], f);
-      else
-        gather1<MD, false>(kp, src, s, col, j, f);
+      for (int i = 0; i < 9; ++i) g2[i] = __shfl_xor(g[i], 1);
+      if (active && layer == 0) end_rebuild<MD>(kp, e, s, col, kap, km1, g, g2, f);
+    } else {
+      if (active && layer == 0) gather1<MD, false>(kp, src, s, col, j, f);
     }
     double acc2[2] = {0.0, 0.0};
-    process_pair<MD, EVAL, 1>(kp, col, j, s, active, f, dst, mom, fraw, ffull, acc2);
+    process_pair<MD, EVAL, 2>(kp, col, j, s, active && layer == 0, f, dst, mom, fraw, ffull, acc2);
     if (EVAL) return;
     const double acc[4] = {s ? 0.0 : acc2[0], s ? acc2[0] : 0.0, s ? 0.0 : acc2[1], s ? acc2[1] : 0.0};
     block_sum(red, acc, 4);
@@ -795,7 +804,7 @@ bool validate(const lbsep_params* p, std::string& why) {
   if (p->nx < (px ? 1 : 6)) return why = "nx must be >= 6 (>= 1 with LBSEP_PERIODIC_X)", false;
   if (p->ny < 2) return why = "ny must be >= 2", false;
   if ((long long)p->nx * p->ny > (1LL << 31)) return why = "nx * ny too large", false;
-  if (p->ny > 128 * kMaxEnd) return why = "ny must be <= " + std::to_string(128 * kMaxEnd), false;
+  if (p->ny > 64 * kMaxEnd) return why = "ny must be <= " + std::to_string(64 * kMaxEnd), false;
   if (!(p->m_a > 0) || !(p->m_b >= p->m_a) || !std::isfinite(p->m_b))
     return why = "need 0 < m_a <= m_b (species a is the light one)", false;
   if (!(p->cl_in > 0 && p->cl_in < 1) || !(p->cl_out > 0 && p->cl_out < 1))
@@ -843,7 +852,7 @@ Layout make_layout(const lbsep_params* p) {
   L.nrt = (p->ny + kTY * L.rpt - 1) / (kTY * L.rpt);
   L.tiles = L.ntx * L.nrt;
   L.chunk = (L.tiles + 7) / 8;
-  L.nend = (p->ny + 127) / 128;
+  L.nend = (p->ny + 63) / 64;
   L.lead = (int)align_up((size_t)(2 * L.nend + L.nxt + 1), 8);
   L.state_buf = align_up(18ull * p->ny * L.pitch * L.elem, 256);
   size_t off = 0;
