@@ -15,16 +15,25 @@ Method (our own, from the mathematics; no vendor constants):
   Neither needs an exponential, and psi ~ 2a carries no cancellation at small a.
   The table holds alpha_n and beta_n rounded to the target precision (checked
   here against mpmath).
-* 1 < a < 2^NSEG: G(a) = a e^a E1(a) is smooth and bounded in (0.59, 1). On each
+* FP64, 1 < a < 2^NSEG: G(a) = a e^a E1(a) is smooth and bounded in (0.59, 1). On each
   octave [2^s, 2^(s+1)) it is replaced by a Chebyshev interpolant in
   t = (2a - 3 * 2^s) / 2^s, evaluated by Clenshaw's recurrence. Coefficients
   are computed here with mpmath at 50 digits from Chebyshev-node samples of
   the exact G (mpmath.e1), and truncated where the remaining terms are below
   the target tolerance (padded to one uniform degree per precision so the
   device loop has no divergent trip count).
-* a >= 2^NSEG: the wall function is 1 to the target precision (its deficit is
+* FP64, a >= 2^NSEG: the wall function is 1 to the target precision (its deficit is
   about 2 e^-a / a) and the device code does not evaluate E1 there.
+* FP32 only, a > 1: one rational function replaces the octaves,
+  G(a) ~ P(u) / Q(u) with u = 1/a in (0, 1], degrees (5, 5), Q(0) = 1. Fitted
+  here by linearised least squares (Sanathanan-Koerner iteration: minimise
+  |G Q - P| / Q_previous on Chebyshev-distributed samples of u), followed by
+  Lawson reweighting towards the minimax error; checked against mpmath on
+  [1, 10^4] with the coefficients rounded to float. With positive coefficients the FP32 Horner evaluation stays within
+  a few ulp, and e^-a underflows to 0 long before the fit loses accuracy, so
+  no cut-off branch is needed.
 """
+import numpy as np
 import os
 
 import mpmath as mp
@@ -113,6 +122,43 @@ def check(segs, nseg):
     return worst
 
 
+def rational_fit(m=5, n=5, nsamp=4000, sk_iters=30, lawson_iters=60):
+    """P (degree m) and Q (degree n, Q(0) = 1) with G(1/u) ~ P(u) / Q(u) on [0, 1]."""
+    uu = 0.5 - 0.5 * np.cos(np.pi * (np.arange(nsamp) + 0.5) / nsamp)
+    gg = np.array([float(g_exact(1 / mp.mpf(u))) for u in uu])
+    vp = np.vander(uu, m + 1, increasing=True)
+    vq = np.vander(uu, n + 1, increasing=True)[:, 1:]
+    qprev = np.ones_like(uu)
+    w = np.ones_like(uu)
+    for it in range(sk_iters + lawson_iters):
+        A = np.hstack([vp, -gg[:, None] * vq]) / qprev[:, None] * np.sqrt(w)[:, None]
+        b = gg / qprev * np.sqrt(w)
+        c = np.linalg.lstsq(A, b, rcond=None)[0]
+        p, q = c[:m + 1], np.concatenate([[1.0], c[m + 1:]])
+        qprev = np.polyval(q[::-1], uu)
+        r = np.polyval(p[::-1], uu) / qprev - gg
+        if it >= sk_iters:
+            w = w * np.abs(r)
+            w /= w.sum()
+    return p, q
+
+
+def check_rational(p, q, tol):
+    """The rational in exact arithmetic (coefficients rounded to float) against G."""
+    p32 = [mp.mpf(float(np.float32(c))) for c in p]
+    q32 = [mp.mpf(float(np.float32(c))) for c in q]
+    worst = mp.mpf(0)
+    pts = [1 + mp.mpf(k) / 50 for k in range(951)] + [mp.mpf(20) * mp.mpf(500) ** (mp.mpf(k) / 100) for k in range(101)]
+    for a in pts:
+        u = 1 / a
+        P = mp.fsum(c * u ** k for k, c in enumerate(p32))
+        Q = mp.fsum(c * u ** k for k, c in enumerate(q32))
+        worst = max(worst, abs(P / Q - g_exact(a)))
+    assert worst < tol, worst
+    assert all(c > 0 for c in p) and all(c > 0 for c in q)
+    return worst
+
+
 def fmt(x, single):
     if single:
         return mp.nstr(x, 12, min_fixed=-1, max_fixed=-1) + "f"
@@ -123,7 +169,7 @@ def main():
     cfg = {
         # precision: (number of octaves, Chebyshev tolerance, series terms)
         "double": (6, mp.mpf("2e-18"), 21),
-        "float": (4, mp.mpf("1e-9"), 12),
+        "float": (0, mp.mpf("1e-9"), 12),
     }
     lines = [
         "// Generated by gen_e1_table.py -- do not edit.",
@@ -137,26 +183,39 @@ def main():
     ]
     for name, (nseg, tol, nser) in cfg.items():
         single = name == "float"
-        segs, deg = build(nseg, tol)
-        worst = check(segs, nseg)
+        segs, deg = build(nseg, tol) if not single else ([], 0)
+        worst = check(segs, nseg) if not single else mp.mpf(0)
         small = check_small(nser, mp.mpf("1e-18") if not single else mp.mpf("1e-9"))
         al, be = alpha_coeffs(nser), beta_coeffs(nser)
         tag = "F32" if single else "F64"
         lines.append("")
-        lines.append(f"// {name}: {nseg} octaves, degree {deg}, max |G error| = {mp.nstr(worst, 3)}; "
-                     f"{nser}-term A, B series, max error {mp.nstr(small, 3)}")
-        lines.append(f"#define LBSEP_E1_{tag}_NSEG {nseg}")
-        lines.append(f"#define LBSEP_E1_{tag}_DEG {deg}")
+        if single:
+            lines.append(f"// {name}: {nser}-term A, B series, max error {mp.nstr(small, 3)}")
+        else:
+            lines.append(f"// {name}: {nseg} octaves, degree {deg}, max |G error| = {mp.nstr(worst, 3)}; "
+                         f"{nser}-term A, B series, max error {mp.nstr(small, 3)}")
+        if not single:
+            lines.append(f"#define LBSEP_E1_{tag}_NSEG {nseg}")
+            lines.append(f"#define LBSEP_E1_{tag}_DEG {deg}")
         lines.append(f"#define LBSEP_E1_{tag}_NSER {nser}")
         lines.append(f"__constant__ {name} lbsep_psi_a_{tag.lower()}[{nser}] = {{")
         lines.append("    " + ", ".join(fmt(c, single) for c in al) + "};")
         lines.append(f"__constant__ {name} lbsep_psi_b_{tag.lower()}[{nser}] = {{")
         lines.append("    " + ", ".join(fmt(c, single) for c in be) + "};")
-        lines.append(f"__constant__ {name} lbsep_e1_cheb_{tag.lower()}[{nseg}][{deg + 1}] = {{")
-        for seg in segs:
-            lines.append("    {" + ", ".join(fmt(c, single) for c in seg) + "},")
-        lines.append("};")
+        if not single:  # FP32 uses the rational below for a > 1
+            lines.append(f"__constant__ {name} lbsep_e1_cheb_{tag.lower()}[{nseg}][{deg + 1}] = {{")
+            for seg in segs:
+                lines.append("    {" + ", ".join(fmt(c, single) for c in seg) + "},")
+            lines.append("};")
         print(name, "deg", deg, "worst", mp.nstr(worst, 3), "small-argument series", mp.nstr(small, 3))
+    p, q = rational_fit()
+    worst = check_rational(p, q, mp.mpf("2e-8"))
+    lines.append("")
+    lines.append(f"// float, a > 1: G(a) ~ P(1/a) / Q(1/a), degrees (5, 5), max |G error| = {mp.nstr(worst, 3)}")
+    lines.append("#define LBSEP_E1_F32_RAT_DEG 5")
+    lines.append("constexpr float lbsep_e1_rat_p_f32[6] = {" + ", ".join(fmt(mp.mpf(float(c)), True) for c in p) + "};")
+    lines.append("constexpr float lbsep_e1_rat_q_f32[6] = {" + ", ".join(fmt(mp.mpf(float(c)), True) for c in q) + "};")
+    print("float rational worst", mp.nstr(worst, 3))
     with open(os.path.join(HERE, "e1_table.h"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
 

@@ -18,6 +18,7 @@ namespace lbsep {
 template <typename T> struct E1Traits;
 
 template <> struct E1Traits<double> {
+  static constexpr bool kRational = false;  // octave Chebyshev interpolants for a > 1
   static constexpr int kSeg = LBSEP_E1_F64_NSEG;
   static constexpr int kDeg = LBSEP_E1_F64_DEG;
   static constexpr int kSer = LBSEP_E1_F64_NSER;
@@ -31,12 +32,13 @@ template <> struct E1Traits<double> {
 };
 
 template <> struct E1Traits<float> {
-  static constexpr int kSeg = LBSEP_E1_F32_NSEG;
-  static constexpr int kDeg = LBSEP_E1_F32_DEG;
+  static constexpr bool kRational = true;  // one rational in 1/a for a > 1
+  static constexpr int kSeg = 0;
+  static constexpr int kDeg = 0;
   static constexpr int kSer = LBSEP_E1_F32_NSER;
   __device__ static float pa(int k) { return lbsep_psi_a_f32[k]; }
   __device__ static float pb(int k) { return lbsep_psi_b_f32[k]; }
-  __device__ static float cheb(int s, int k) { return lbsep_e1_cheb_f32[s][k]; }
+  __device__ static float cheb(int, int) { return 0.0f; }
   __device__ static float ex(float a) { return __builtin_amdgcn_exp2f(a * 1.4426950408889634f); }
   __device__ static float ln(float a) { return __builtin_amdgcn_logf(a) * 0.6931471805599453f; }
   __device__ static float rsq(float a) { return __builtin_amdgcn_rsqf(a); }
@@ -47,10 +49,12 @@ template <> struct E1Traits<float> {
 // WANT_H, h(a) = e^-a - a E1(a) = psi'(a) / 2.
 //   a <= 1      : psi = A(a) + a^2 ln a, h = B(a) + a ln a, with A and B entire
 //                 power series (Horner); one logarithm, no exponential.
-//   1 < a < 2^n : E1 = e^-a G(a) / a with G(a) = a e^a E1(a) from the octave's
-//                 Chebyshev interpolant (Clenshaw), so psi = 1 + e^-a (a - 1 - a G)
-//                 and h = e^-a (1 - G).
-//   beyond      : psi = 1 and h = 0 to the arithmetic's precision.
+//   1 < a       : E1 = e^-a G(a) / a with G(a) = a e^a E1(a), so
+//                 psi = 1 + e^-a (a - 1 - a G) and h = e^-a (1 - G).
+//                 FP64: G from the octave's Chebyshev interpolant (Clenshaw) for
+//                 a < 2^n, beyond that psi = 1 and h = 0 to FP64 precision.
+//                 FP32: G = P(1/a) / Q(1/a), one (5, 5) rational on all of
+//                 (1, inf); e^-a underflows where psi rounds to 1.
 template <typename T, bool WANT_H>
 __device__ __forceinline__ void wall_psi(T a, T& psi, T& h) {
   using E = E1Traits<T>;
@@ -71,6 +75,21 @@ __device__ __forceinline__ void wall_psi(T a, T& psi, T& h) {
       for (int k = E::kSer - 2; k >= 0; --k) B = B * a + E::pb(k);
       h = B + a * la;
     }
+    return;
+  }
+  if constexpr (E::kRational) {
+    const T u = E::rcp(a);
+    T P = T(lbsep_e1_rat_p_f32[LBSEP_E1_F32_RAT_DEG]);
+    T Q = T(lbsep_e1_rat_q_f32[LBSEP_E1_F32_RAT_DEG]);
+#pragma unroll
+    for (int k = LBSEP_E1_F32_RAT_DEG - 1; k >= 0; --k) {
+      P = P * u + T(lbsep_e1_rat_p_f32[k]);
+      Q = Q * u + T(lbsep_e1_rat_q_f32[k]);
+    }
+    const T g = P * E::rcp(Q);
+    const T ea = E::ex(-a);
+    psi = T(1) + ea * (a - T(1) - a * g);
+    if (WANT_H) h = ea * (T(1) - g);
     return;
   }
   const int seg = ilogb(a);

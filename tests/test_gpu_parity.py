@@ -316,11 +316,13 @@ def test_device_wall_function_against_mpmath(dtype, tol):
     assert np.max(np.abs(psi[small] - ref_psi[small]) / ref_psi[small]) < (1e-14 if dtype == "f64" else 1e-6)
 
 
+@pytest.mark.parametrize("shape", [(150, 13), (517, 24)])
 @pytest.mark.parametrize("dtype", ["f64", "f32", "f16"])
-def test_tile_shapes_give_identical_results(dtype):
+def test_tile_shapes_give_identical_results(dtype, shape):
     """A lane pair per node and one lane per node run the same arithmetic on the
-    same inputs: the FP64 and FP32 states agree bitwise."""
-    w = Workload("shape", 150, 13, *NE_AR, 0.3, 0.7, 3.0, 0.05, 300)
+    same inputs: the FP64 and FP32 states agree bitwise (517 columns: a ragged
+    last tile in both shapes)."""
+    w = Workload("shape", shape[0], shape[1], *NE_AR, 0.3, 0.7, 3.0, 0.05, 300)
     r = r_of(w)
     out = []
     for mode in (lbsep.TILE_SPLIT, lbsep.TILE_NODE):
