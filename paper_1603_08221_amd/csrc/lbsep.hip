@@ -68,6 +68,7 @@ constexpr int kTX = 64;         // columns per block (one wavefront across x)
 constexpr int kTY = 4;          // wavefronts per block
 constexpr int kThreads = kTX * kTY;
 constexpr int kMaxEnd = 32;     // end blocks per inlet/outlet column: ny <= 64 * kMaxEnd
+constexpr unsigned kRowMajorTiles = 1u << 16;  // KParams::flags bit above the ABI flags
 
 template <typename S, typename C, bool DEV>
 struct Mode {
@@ -250,7 +251,7 @@ __device__ __forceinline__ void end_rebuild(const KParams& kp, int e, int s, int
 // Moments, relaxation times and (STEP) collision + store or (EVAL) output of
 // one node by one lane holding both species (fa, fb: populations, deviations
 // in the FP32/FP16 modes). acc receives (n_a, n_b, rho_a u_ax, rho_b u_bx).
-template <class MD, bool EVAL>
+template <class MD, bool EVAL, bool NT = false>
 __device__ __forceinline__ void process_node(const KParams& kp, int x, int j, typename MD::Ct fa[9],
                                              typename MD::Ct fb[9], typename MD::St* __restrict__ dst,
                                              double* __restrict__ mom, typename MD::St* __restrict__ fraw,
@@ -325,8 +326,13 @@ __device__ __forceinline__ void process_node(const KParams& kp, int x, int j, ty
   collide_species<C>(fb, cb, rho_b, ux, uy, C(kp.rc.s[1]), we, weps, wd, wq, ws);
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
-    *plane_at(kp, dst, 0, i, j, x) = typename MD::St(fa[i]);
-    *plane_at(kp, dst, 1, i, j, x) = typename MD::St(fb[i]);
+    if (NT) {  // the next read of these lines is a whole sweep away: bypass the caches
+      __builtin_nontemporal_store(typename MD::St(fa[i]), plane_at(kp, dst, 0, i, j, x));
+      __builtin_nontemporal_store(typename MD::St(fb[i]), plane_at(kp, dst, 1, i, j, x));
+    } else {
+      *plane_at(kp, dst, 0, i, j, x) = typename MD::St(fa[i]);
+      *plane_at(kp, dst, 1, i, j, x) = typename MD::St(fb[i]);
+    }
   }
 }
 
@@ -524,7 +530,7 @@ __device__ void block_sum(double (*red)[kTY][kTX], const double* v, int nv) {
   __syncthreads();
 }
 
-template <class MD, bool PULL, bool EVAL, bool SPLIT>
+template <class MD, bool PULL, bool EVAL, bool SPLIT, bool NT>
 __global__ __launch_bounds__(kThreads) void k_sweep(KParams kp, KBufs kb, const typename MD::St* __restrict__ src,
                                                     typename MD::St* __restrict__ dst, double* __restrict__ mom,
                                                     typename MD::St* __restrict__ fraw,
@@ -623,8 +629,17 @@ __global__ __launch_bounds__(kThreads) void k_sweep(KParams kp, KBufs kb, const 
   const int k = (b - kp.lead) >> 3;
   const int lin = xcd * kp.chunk + k;
   if (lin >= kp.tiles) return;
-  const int bx = lin / kp.nrt;
-  const int by = lin - bx * kp.nrt;
+  // consecutive tiles of an XCD run down a column strip (small channels: the
+  // strip's rows stay together) or along a row band (large channels: the
+  // concurrently open rows of every plane stay few and long)
+  int bx, by;
+  if (kp.flags & kRowMajorTiles) {
+    by = lin / kp.ntx;
+    bx = lin - by * kp.ntx;
+  } else {
+    bx = lin / kp.nrt;
+    by = lin - bx * kp.nrt;
+  }
   const int lane = threadIdx.x & (kTX - 1);
   const int ty = threadIdx.x / kTX;
   if (SPLIT) {
@@ -668,7 +683,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep(KParams kp, KBufs kb, const 
         C fa[9], fb[9];
         gather1<MD, PULL>(kp, src, 0, x, j, fa);
         gather1<MD, PULL>(kp, src, 1, x, j, fb);
-        process_node<MD, EVAL>(kp, x, j, fa, fb, dst, mom, fraw, ffull, acc);
+        process_node<MD, EVAL, NT>(kp, x, j, fa, fb, dst, mom, fraw, ffull, acc);
       }
     }
     if (EVAL) return;
@@ -793,6 +808,7 @@ size_t elem_bytes(int dtype) { return dtype == LBSEP_F64 ? 8 : dtype == LBSEP_F3
 struct Layout {
   int pitch, nxt, ntx, nrt, rpt, tiles, chunk, lead, nend;
   bool split;
+  bool big;  // a state buffer exceeds half the last-level cache: row-major tiles, non-temporal stores
   size_t elem, state_buf, f0, f1, partials, endsum, colsum, strip, hist, status, mom, total;
 };
 
@@ -855,6 +871,7 @@ Layout make_layout(const lbsep_params* p) {
   L.nend = (p->ny + 63) / 64;
   L.lead = (int)align_up((size_t)(2 * L.nend + L.nxt + 1), 8);
   L.state_buf = align_up(18ull * p->ny * L.pitch * L.elem, 256);
+  L.big = !L.split && L.state_buf > (128ull << 20);
   size_t off = 0;
   L.f0 = off;
   off += L.state_buf;
@@ -912,12 +929,16 @@ void launch_sweep(lbsep_channel* h, const void* src, void* dst, double* mom, voi
   using S = typename MD::St;
   const int grid = h->L.lead + 8 * h->L.chunk;
   if (h->L.split)
-    hipLaunchKernelGGL((k_sweep<MD, PULL, EVAL, true>), dim3(grid), dim3(kThreads), 0, h->stream, h->kp, h->kb,
-                       static_cast<const S*>(src), static_cast<S*>(dst), mom, static_cast<S*>(fraw), ffull, t,
+    hipLaunchKernelGGL((k_sweep<MD, PULL, EVAL, true, false>), dim3(grid), dim3(kThreads), 0, h->stream, h->kp,
+                       h->kb, static_cast<const S*>(src), static_cast<S*>(dst), mom, static_cast<S*>(fraw), ffull, t,
+                       (long long)h->t_first);
+  else if (h->L.big && !EVAL)
+    hipLaunchKernelGGL((k_sweep<MD, PULL, EVAL, false, true>), dim3(grid), dim3(kThreads), 0, h->stream, h->kp,
+                       h->kb, static_cast<const S*>(src), static_cast<S*>(dst), mom, static_cast<S*>(fraw), ffull, t,
                        (long long)h->t_first);
   else
-    hipLaunchKernelGGL((k_sweep<MD, PULL, EVAL, false>), dim3(grid), dim3(kThreads), 0, h->stream, h->kp, h->kb,
-                       static_cast<const S*>(src), static_cast<S*>(dst), mom, static_cast<S*>(fraw), ffull, t,
+    hipLaunchKernelGGL((k_sweep<MD, PULL, EVAL, false, false>), dim3(grid), dim3(kThreads), 0, h->stream, h->kp,
+                       h->kb, static_cast<const S*>(src), static_cast<S*>(dst), mom, static_cast<S*>(fraw), ffull, t,
                        (long long)h->t_first);
 }
 
@@ -1048,7 +1069,7 @@ int lbsep_init(const lbsep_params* p, void* dev_ws, size_t ws_bytes, void* hip_s
   kp.lead = L.lead;
   kp.nend = L.nend;
   kp.plane = (long long)p->ny * L.pitch;
-  kp.flags = p->flags;
+  kp.flags = p->flags | (h->L.split ? 0u : kRowMajorTiles);
   kp.r = p->dbb_r;
   kp.cl_in = p->cl_in;
   RelaxConsts& rc = kp.rc;
