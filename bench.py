@@ -75,6 +75,53 @@ def time_steps(torch, ch, steps):
     return wall, start.elapsed_time(end)
 
 
+def batch_leg(torch, lbsep, dtype: str, steps: int):
+    """The seeded 64-channel parametric sweep (uneven H in {16..128}, L = 20 H)
+    as one launch per step: tile shapes from the autotuner, the step loop as a
+    captured HIP graph of 100 steps, `steps` steps timed with HIP events."""
+    from paper_1603_08221_amd import autotune
+    from paper_1603_08221_amd.workloads import batch_instances
+
+    ws = batch_instances()
+    ps = [lbsep.make_params(w.nx, w.ny, w.m_a, w.m_b, w.cl_in, w.cl_out, w.theta, w.kn_out,
+                            lbsep.dbb_r_from_cm(w.c_m, w.m_a, w.m_b, w.cl_in), dtype=dtype, hist_cap=64)
+          for w in ws]
+    tuned = autotune.tune(ps)
+    stream = torch.cuda.Stream()
+    chans = []
+    for p, m in zip(ps, tuned["modes"]):
+        p.tile_mode = m
+        chans.append(lbsep.Channel(p, device="cuda:0", stream=stream))
+    b = lbsep.Batch(chans)
+    b.capture(100)
+    b.step(100)
+    stream.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    start.record(stream)
+    b.step(steps)
+    end.record(stream)
+    end.synchronize()
+    wall = time.perf_counter() - t0
+    nodes = sum(w.nx * w.ny for w in ws)
+    per = start.elapsed_time(end) / 1e3 / steps
+    alg = nodes * 36 * BYTES_PER_POP[dtype]
+    diverged = 0
+    for c in chans:
+        try:
+            c.read_cl()
+        except lbsep.LbsepError:
+            diverged += 1
+    return {"workload": "sweep_table_64 (seed 160308221, H in {16..128}, L = 20 H)", "instances": len(ws),
+            "nodes": nodes, "steps": steps, "mlups": round(nodes * steps / wall / 1e6, 1),
+            "us_per_step": round(per * 1e6, 2), "gbps_algorithmic": round(alg / per / 1e9, 1),
+            "frac_of_hbm_peak": round(alg / per / 1e9 / HBM_PEAK_GBS, 4), "tiles": tuned["name"],
+            "tuning_ms_per_step": {k: round(v, 4) for k, v in tuned["timings"].items()},
+            "graph_steps": 100, "diverged_members": diverged,
+            "t_final": chans[0].t}
+
+
 def cpu_baseline(w, r, seconds: float):
     """The CPU oracle as it stands, on the same workload, for a bounded number
     of steps (about `seconds` of CPU work), single BLAS thread."""
@@ -128,6 +175,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 reference leg (profiling runs)")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the leg on the 512 x 10240 channel (above the last-level cache)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-channel batched sweep leg")
+    ap.add_argument("--batch-steps", type=int, default=1000)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device copy of this size (PMC calibration)")
     args = ap.parse_args()
@@ -221,6 +270,8 @@ def main():
                                 "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
                                 "traffic": None if tr is None else round(tr), "cl": chl.read_cl()["cl"]}
         del chl
+    if not args.no_batch:
+        out["batch"] = batch_leg(torch, lbsep, args.dtype, args.batch_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, r, args.cpu_seconds)
         out["fp64_vs_oracle"] = oracle_parity(lbsep, w, r, 100)

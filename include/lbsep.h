@@ -190,6 +190,41 @@ void lbsep_destroy(lbsep_channel* ch);
 /* Message of the last failure on this thread ("" if none). */
 const char* lbsep_last_error(void);
 
+/* ---- batches: the parametric sweeps of Table 1 / Sec. 4 as one launch ------
+ * A batch advances several independent channels (uneven sizes, any parameters
+ * of Table 1's kind) by one sweep kernel per step: every channel keeps its own
+ * workspace, reductions and CL history, and its results are bitwise those of
+ * stepping it alone. The member channels stay usable through the channel API
+ * (read_cl, read_moments, get_state ...) between batch steps; stepping or
+ * resetting a member on its own invalidates the batch (its next step fails
+ * with LBSEP_EINVAL). Members must outlive the batch. */
+typedef struct lbsep_batch lbsep_batch;
+
+/* Device workspace bytes for a batch of the n channels chans[0..n-1] (one
+ * dtype, one stream, no channel twice); 0 on invalid input. */
+size_t lbsep_batch_workspace_bytes(lbsep_channel* const* chans, int32_t n);
+
+/* Build the batch's instance table in dev_ws (caller-owned, 256-byte aligned,
+ * >= lbsep_batch_workspace_bytes) from the members' current states.
+ * Synchronises the stream once. */
+int lbsep_batch_create(lbsep_channel* const* chans, int32_t n, void* dev_ws, size_t ws_bytes, lbsep_batch** out);
+
+/* Advance every member by nsteps levels: replays of the captured step graph
+ * while at least its length remains, single launches for the rest. Enqueues
+ * only. */
+int lbsep_batch_step(lbsep_batch* b, int64_t nsteps);
+
+/* Capture `steps` batch steps (1 .. 100000) into a HIP graph replayed by
+ * lbsep_batch_step; 0 drops the graph. Needs a non-default stream. */
+int lbsep_batch_capture(lbsep_batch* b, int64_t steps);
+
+/* Number of member channels; -1 for NULL. */
+int32_t lbsep_batch_size(const lbsep_batch* b);
+
+/* Release the batch's host handle and graph (members and workspace stay the
+ * caller's). NULL is a no-op. */
+void lbsep_batch_destroy(lbsep_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

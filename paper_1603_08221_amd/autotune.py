@@ -1,0 +1,99 @@
+"""Autotuner for the tile shape of batched and single-channel sweeps.
+
+The sweep kernel maps nodes to lanes either as a lane pair per node (species
+split; shortest chain per lane, pays when a channel leaves the GPU mostly idle)
+or as one lane per node (fewest instructions per node, pays when the work
+fills the GPU several times). Which one is faster depends on the whole launch:
+a small channel alone wants the lane pair, the same channel inside a batch that
+fills the GPU wants one lane per node. The tuner times candidate assignments on
+scratch channels (fresh workspaces, same shapes and parameters, so the caller's
+states are never touched) and returns the fastest. Results are bitwise
+independent of the choice, so the choice is purely a speed decision.
+
+Choices can be cached in a JSON file keyed by the device name, the dtype and
+the member shapes.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+
+import torch
+
+from . import lbsep
+
+SPLIT, NODE = lbsep.TILE_SPLIT, lbsep.TILE_NODE
+
+
+def _key(params_list, device) -> str:
+    h = hashlib.sha256()
+    h.update(torch.cuda.get_device_name(device).encode())
+    for p in params_list:
+        h.update(f"{p.nx},{p.ny},{p.dtype},{p.flags}".encode())
+    return h.hexdigest()[:20]
+
+
+def candidates(params_list):
+    """Tile-mode assignments to try: all lane pairs, all one-lane-per-node, and
+    size thresholds in between (lane pairs for members up to T nodes)."""
+    sizes = [p.nx * p.ny for p in params_list]
+    out = {"split": [SPLIT] * len(sizes), "node": [NODE] * len(sizes)}
+    for t in (1 << 14, 1 << 16, 1 << 18):
+        a = [SPLIT if n <= t else NODE for n in sizes]
+        if a not in out.values():
+            out[f"split<={t}"] = a
+    return out
+
+
+def _with_mode(p, mode):
+    q = lbsep.Params.from_buffer_copy(p)
+    q.tile_mode = mode
+    q.hist_cap = 16
+    return q
+
+
+def _time_batch(params_list, modes, device, trial_steps, warmup):
+    stream = torch.cuda.Stream(device)
+    chans = [lbsep.Channel(_with_mode(p, m), device=device, stream=stream) for p, m in zip(params_list, modes)]
+    b = lbsep.Batch(chans) if len(chans) > 1 else None
+    step = b.step if b is not None else chans[0].step
+    step(warmup)
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    stream.synchronize()
+    start.record(stream)
+    step(trial_steps)
+    end.record(stream)
+    end.synchronize()
+    ms = start.elapsed_time(end) / trial_steps
+    if b is not None:
+        b.close()
+    for c in chans:
+        c.close()
+    return ms
+
+
+def tune(params_list, device="cuda:0", trial_steps=40, warmup=10, cache_file=None):
+    """Fastest tile-mode assignment for sweeping `params_list` together (one
+    channel: alone). Returns {"name", "modes", "ms_per_step", "timings"}."""
+    params_list = list(params_list)
+    key = _key(params_list, device)
+    cache = {}
+    if cache_file and os.path.exists(cache_file):
+        with open(cache_file) as fh:
+            cache = json.load(fh)
+        if key in cache:
+            return cache[key]
+    timings = {}
+    for name, modes in candidates(params_list).items():
+        timings[name] = _time_batch(params_list, modes, device, trial_steps, warmup)
+    best = min(timings, key=timings.get)
+    out = {"name": best, "modes": candidates(params_list)[best], "ms_per_step": timings[best], "timings": timings}
+    if cache_file:
+        cache[key] = out
+        tmp = cache_file + ".tmp"
+        with open(tmp, "w") as fh:
+            json.dump(cache, fh, indent=1)
+        os.replace(tmp, cache_file)
+    return out

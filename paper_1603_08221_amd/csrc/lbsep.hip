@@ -57,6 +57,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "lbsep.h"
 #include "lbsep_device.h"
@@ -530,15 +531,15 @@ __device__ void block_sum(double (*red)[kTY][kTX], const double* v, int nv) {
   __syncthreads();
 }
 
+// One block of the fused sweep of a channel, block index b of the channel's
+// own grid (lead blocks, then XCD-interleaved tiles).
 template <class MD, bool PULL, bool EVAL, bool SPLIT, bool NT>
-__global__ __launch_bounds__(kThreads) void k_sweep(KParams kp, KBufs kb, const typename MD::St* __restrict__ src,
-                                                    typename MD::St* __restrict__ dst, double* __restrict__ mom,
-                                                    typename MD::St* __restrict__ fraw,
-                                                    double* __restrict__ ffull, long long t,
-                                                    long long t_first) {
+__device__ __forceinline__ void sweep_block(const KParams& kp, const KBufs& kb,
+                                            const typename MD::St* __restrict__ src, typename MD::St* __restrict__ dst,
+                                            double* __restrict__ mom, typename MD::St* __restrict__ fraw,
+                                            double* __restrict__ ffull, long long t, long long t_first, int b,
+                                            double (*red)[kTY][kTX]) {
   using C = typename MD::Ct;
-  __shared__ double red[4][kTY][kTX];
-  const int b = blockIdx.x;
   const bool px = kp.flags & LBSEP_PERIODIC_X;
   if (b < kp.lead) {
     if (b >= 2 * kp.nend) {
@@ -696,6 +697,58 @@ __global__ __launch_bounds__(kThreads) void k_sweep(KParams kp, KBufs kb, const 
       kb.partials[(t & 1) * kb.part_stride + ((long long)ty * kp.nrt + by) * kp.pitch + x] = v;
     }
   }
+}
+
+template <class MD, bool PULL, bool EVAL, bool SPLIT, bool NT>
+__global__ __launch_bounds__(kThreads) void k_sweep(KParams kp, KBufs kb, const typename MD::St* __restrict__ src,
+                                                    typename MD::St* __restrict__ dst, double* __restrict__ mom,
+                                                    typename MD::St* __restrict__ fraw,
+                                                    double* __restrict__ ffull, long long t,
+                                                    long long t_first) {
+  __shared__ double red[4][kTY][kTX];
+  sweep_block<MD, PULL, EVAL, SPLIT, NT>(kp, kb, src, dst, mom, fraw, ffull, t, t_first, (int)blockIdx.x, red);
+}
+
+// A batch of channels swept by one launch: entry i holds channel i's constants,
+// reduction buffers and state buffers; its blocks are the contiguous range
+// [first_block, first_block + lead + 8 chunk) of the batch grid (a multiple of
+// 8 blocks each, so the XCD interleave of the tiles is kept).
+struct BatchEntry {
+  KParams kp;
+  KBufs kb;
+  void* f[2];          // the channel's two state buffers
+  long long t0;        // channel level when the batch's step counter was 0
+  long long t_first;   // first level with a history record
+  int cur0;            // buffer holding the post-collision state at counter 0
+  int first_block;
+  int split;           // tile kind: lane pair per node (1) or one lane per node (0)
+  int pad;
+};
+
+// Batch step k = *counter + k_local: every channel advances by one level.
+template <class MD, bool NT>
+__global__ __launch_bounds__(kThreads) void k_sweep_batch(const BatchEntry* __restrict__ tab,
+                                                          const int* __restrict__ blk_inst,
+                                                          const long long* __restrict__ counter, int k_local) {
+  __shared__ double red[4][kTY][kTX];
+  using S = typename MD::St;
+  const int inst = blk_inst[blockIdx.x];
+  const BatchEntry& e = tab[inst];
+  const long long k = *counter + k_local;
+  const int c = (e.cur0 + (int)(k & 1)) & 1;
+  const S* src = static_cast<const S*>(e.f[c]);
+  S* dst = static_cast<S*>(e.f[c ^ 1]);
+  const int b = (int)blockIdx.x - e.first_block;
+  if (e.split)
+    sweep_block<MD, true, false, true, false>(e.kp, e.kb, src, dst, nullptr, nullptr, nullptr, e.t0 + k + 1,
+                                              e.t_first, b, red);
+  else
+    sweep_block<MD, true, false, false, NT>(e.kp, e.kb, src, dst, nullptr, nullptr, nullptr, e.t0 + k + 1,
+                                            e.t_first, b, red);
+}
+
+__global__ void k_batch_advance(long long* counter, long long n) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *counter += n;
 }
 
 // Completes the records of levels t - 1 and t (reads after the last sweep):
@@ -1295,5 +1348,221 @@ int lbsep_wall_function(const double* dev_alpha, double* dev_psi, double* dev_h,
 }
 
 void lbsep_destroy(lbsep_channel* h) { delete h; }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batches: several channels advanced by one launch per step
+// ---------------------------------------------------------------------------
+struct lbsep_batch {
+  std::vector<lbsep_channel*> ch;
+  std::vector<int64_t> t_expect;  // member levels the device step counter was set up for
+  hipStream_t stream = nullptr;
+  int dtype = 0;
+  bool nt = false;
+  int total_blocks = 0;
+  long long* counter = nullptr;  // device: batch steps taken
+  BatchEntry* tab = nullptr;     // device
+  int* blk_inst = nullptr;       // device: block -> entry
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int64_t graph_steps = 0;
+};
+
+namespace {
+
+struct BatchLayout {
+  size_t counter, tab, blk, total;
+  int blocks;
+};
+
+int batch_layout(lbsep_channel* const* chans, int n, BatchLayout& B) {
+  if (!chans || n < 1) return fail(LBSEP_EINVAL, "need at least one channel");
+  B.blocks = 0;
+  for (int i = 0; i < n; ++i) {
+    if (!chans[i]) return fail(LBSEP_EINVAL, "channel " + std::to_string(i) + " is NULL");
+    for (int k = 0; k < i; ++k)
+      if (chans[k] == chans[i]) return fail(LBSEP_EINVAL, "a channel appears twice in the batch");
+    if (chans[i]->p.dtype != chans[0]->p.dtype) return fail(LBSEP_EINVAL, "all channels of a batch share one dtype");
+    if (chans[i]->stream != chans[0]->stream) return fail(LBSEP_EINVAL, "all channels of a batch share one stream");
+    const long long nb = (long long)chans[i]->L.lead + 8LL * chans[i]->L.chunk;
+    if (B.blocks + nb > (1LL << 30)) return fail(LBSEP_EINVAL, "batch grid too large");
+    B.blocks += (int)nb;
+  }
+  size_t off = 0;
+  B.counter = off;
+  off += 256;
+  B.tab = off;
+  off += align_up((size_t)n * sizeof(BatchEntry), 256);
+  B.blk = off;
+  off += align_up((size_t)B.blocks * sizeof(int), 256);
+  B.total = off;
+  return LBSEP_OK;
+}
+
+template <class MD>
+void launch_batch(lbsep_batch* b, int k_local) {
+  if (b->nt)
+    hipLaunchKernelGGL((k_sweep_batch<MD, true>), dim3(b->total_blocks), dim3(kThreads), 0, b->stream, b->tab,
+                       b->blk_inst, b->counter, k_local);
+  else
+    hipLaunchKernelGGL((k_sweep_batch<MD, false>), dim3(b->total_blocks), dim3(kThreads), 0, b->stream, b->tab,
+                       b->blk_inst, b->counter, k_local);
+}
+
+// n sweeps (k_local = 0 .. n-1 from the current counter), then counter += n.
+void enqueue_batch_steps(lbsep_batch* b, int64_t n) {
+  for (int64_t k = 0; k < n; ++k) {
+    switch (b->dtype) {
+      case LBSEP_F64:
+        launch_batch<ModeF64>(b, (int)k);
+        break;
+      case LBSEP_F32:
+        launch_batch<ModeF32>(b, (int)k);
+        break;
+      default:
+        launch_batch<ModeF16>(b, (int)k);
+        break;
+    }
+  }
+  hipLaunchKernelGGL(k_batch_advance, dim3(1), dim3(64), 0, b->stream, b->counter, (long long)n);
+}
+
+void drop_graph(lbsep_batch* b) {
+  if (b->exec) hipGraphExecDestroy(b->exec);
+  if (b->graph) hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  b->graph_steps = 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbsep_batch_workspace_bytes(lbsep_channel* const* chans, int32_t n) {
+  BatchLayout B;
+  if (batch_layout(chans, n, B)) return 0;
+  return B.total;
+}
+
+int lbsep_batch_create(lbsep_channel* const* chans, int32_t n, void* dev_ws, size_t ws_bytes, lbsep_batch** out) {
+  if (!out) return fail(LBSEP_EINVAL, "out is NULL");
+  *out = nullptr;
+  BatchLayout B;
+  if (int e = batch_layout(chans, n, B)) return e;
+  if (!dev_ws || (reinterpret_cast<uintptr_t>(dev_ws) & 255u))
+    return fail(LBSEP_EINVAL, "dev_ws must be a non-NULL 256-byte aligned device pointer");
+  if (ws_bytes < B.total) return fail(LBSEP_ESIZE, "workspace too small: need " + std::to_string(B.total) + " bytes");
+  auto* b = new (std::nothrow) lbsep_batch;
+  if (!b) return fail(LBSEP_EDEVICE, "out of host memory");
+  char* ws = static_cast<char*>(dev_ws);
+  b->stream = chans[0]->stream;
+  b->dtype = chans[0]->p.dtype;
+  b->counter = reinterpret_cast<long long*>(ws + B.counter);
+  b->tab = reinterpret_cast<BatchEntry*>(ws + B.tab);
+  b->blk_inst = reinterpret_cast<int*>(ws + B.blk);
+  b->total_blocks = B.blocks;
+  std::vector<BatchEntry> host(n);
+  std::vector<int> blk(B.blocks);
+  size_t node_state = 0;
+  int first = 0;
+  for (int i = 0; i < n; ++i) {
+    lbsep_channel* c = chans[i];
+    BatchEntry& e = host[i];
+    std::memset(&e, 0, sizeof(e));
+    e.kp = c->kp;
+    e.kb = c->kb;
+    e.f[0] = c->f[0];
+    e.f[1] = c->f[1];
+    e.t0 = c->t;
+    e.t_first = c->t_first;
+    e.cur0 = c->cur;
+    e.first_block = first;
+    e.split = c->L.split ? 1 : 0;
+    const int nb = c->L.lead + 8 * c->L.chunk;
+    for (int k = 0; k < nb; ++k) blk[first + k] = i;
+    first += nb;
+    if (!c->L.split) node_state += c->L.state_buf;
+    b->ch.push_back(c);
+    b->t_expect.push_back(c->t);
+  }
+  // non-temporal stores once the one-lane-per-node members' states outgrow
+  // half the last-level cache together
+  b->nt = node_state > (128ull << 20);
+  const long long zero = 0;
+  int rc = check_hip(hipMemcpyAsync(b->counter, &zero, sizeof(zero), hipMemcpyHostToDevice, b->stream), "batch copy");
+  if (!rc)
+    rc = check_hip(hipMemcpyAsync(b->tab, host.data(), n * sizeof(BatchEntry), hipMemcpyHostToDevice, b->stream),
+                   "batch copy");
+  if (!rc)
+    rc = check_hip(hipMemcpyAsync(b->blk_inst, blk.data(), blk.size() * sizeof(int), hipMemcpyHostToDevice,
+                                  b->stream),
+                   "batch copy");
+  if (!rc) rc = check_hip(hipStreamSynchronize(b->stream), "batch copy");
+  if (rc) {
+    delete b;
+    return rc;
+  }
+  *out = b;
+  return LBSEP_OK;
+}
+
+int lbsep_batch_step(lbsep_batch* b, int64_t nsteps) {
+  if (!b) return fail(LBSEP_EINVAL, "batch is NULL");
+  if (nsteps < 0) return fail(LBSEP_EINVAL, "nsteps must be >= 0");
+  for (size_t i = 0; i < b->ch.size(); ++i)
+    if (b->ch[i]->t != b->t_expect[i])
+      return fail(LBSEP_EINVAL, "channel " + std::to_string(i) + " was stepped or reset outside its batch");
+  int64_t left = nsteps;
+  while (b->exec && left >= b->graph_steps) {
+    if (int e = check_hip(hipGraphLaunch(b->exec, b->stream), "batch graph launch")) return e;
+    left -= b->graph_steps;
+  }
+  if (left > 0) enqueue_batch_steps(b, left);
+  for (size_t i = 0; i < b->ch.size(); ++i) {
+    lbsep_channel* c = b->ch[i];
+    c->t += nsteps;
+    c->cur = (c->cur + (int)(nsteps & 1)) & 1;
+    if (nsteps > 0) {
+      c->prev_pre = false;
+      c->finalized = false;
+    }
+    b->t_expect[i] = c->t;
+  }
+  return check_hip(hipGetLastError(), "batch step launch");
+}
+
+int lbsep_batch_capture(lbsep_batch* b, int64_t steps) {
+  if (!b) return fail(LBSEP_EINVAL, "batch is NULL");
+  drop_graph(b);
+  if (steps <= 0) return LBSEP_OK;
+  if (steps > 100000) return fail(LBSEP_EINVAL, "at most 100000 steps per graph");
+  if (!b->stream) return fail(LBSEP_EINVAL, "graph capture needs a non-default stream");
+  int rc = check_hip(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "begin capture");
+  if (rc) return rc;
+  enqueue_batch_steps(b, steps);
+  hipGraph_t g = nullptr;
+  rc = check_hip(hipStreamEndCapture(b->stream, &g), "end capture");
+  if (rc) return rc;
+  hipGraphExec_t x = nullptr;
+  rc = check_hip(hipGraphInstantiate(&x, g, nullptr, nullptr, 0), "graph instantiate");
+  if (rc) {
+    hipGraphDestroy(g);
+    return rc;
+  }
+  b->graph = g;
+  b->exec = x;
+  b->graph_steps = steps;
+  return LBSEP_OK;
+}
+
+int32_t lbsep_batch_size(const lbsep_batch* b) { return b ? (int32_t)b->ch.size() : -1; }
+
+void lbsep_batch_destroy(lbsep_batch* b) {
+  if (!b) return;
+  drop_graph(b);
+  delete b;
+}
 
 }  // extern "C"

@@ -74,6 +74,12 @@ def load():
         "lbsep_wall_function": (c_int, [c_void_p, c_void_p, c_void_p, c_int64, c_int32, c_void_p]),
         "lbsep_destroy": (None, [c_void_p]),
         "lbsep_last_error": (c_char_p, []),
+        "lbsep_batch_workspace_bytes": (c_size_t, [POINTER(c_void_p), c_int32]),
+        "lbsep_batch_create": (c_int, [POINTER(c_void_p), c_int32, c_void_p, c_size_t, POINTER(c_void_p)]),
+        "lbsep_batch_step": (c_int, [c_void_p, c_int64]),
+        "lbsep_batch_capture": (c_int, [c_void_p, c_int64]),
+        "lbsep_batch_size": (c_int32, [c_void_p]),
+        "lbsep_batch_destroy": (None, [c_void_p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -142,6 +148,8 @@ class Channel:
         self._raw = raw
         self.ws = raw[off:off + nbytes]
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        if self.stream != torch.cuda.current_stream(self.device):
+            raw.record_stream(self.stream)  # the allocator must not recycle it under the channel's work
         h = c_void_p()
         _check(L.lbsep_init(byref(params), c_void_p(self.ws.data_ptr()), c_size_t(nbytes),
                             c_void_p(self.stream.cuda_stream), byref(h)))
@@ -197,12 +205,14 @@ class Channel:
         """Raw state in the storage type (f for f64, deviations for f32/f16)."""
         out = torch.empty((2, 9, self.ny, self.nx), dtype=self.dtype, device=self.device)
         _check(load().lbsep_get_state(self._h, c_void_p(out.data_ptr())))
+        self._hand_over(out)
         return out
 
     def set_state(self, f: torch.Tensor, t: int = 0):
         if f.shape != (2, 9, self.ny, self.nx) or f.dtype != self.dtype or f.device.type != "cuda":
             raise ValueError(f"state must be a {self.dtype} cuda tensor of shape (2, 9, {self.ny}, {self.nx})")
         f = f.contiguous()
+        self._take_over()
         _check(load().lbsep_set_state(self._h, c_void_p(f.data_ptr()), int(t)))
         self._keep = f  # keep the source alive until the stream has consumed it
 
@@ -210,14 +220,79 @@ class Channel:
         """Pre-collision populations f in float64, whatever the storage type."""
         out = torch.empty((2, 9, self.ny, self.nx), dtype=torch.float64, device=self.device)
         _check(load().lbsep_get_populations(self._h, c_void_p(out.data_ptr())))
+        self._hand_over(out)
         return out
 
     def set_populations(self, f: torch.Tensor, t: int = 0):
         if f.shape != (2, 9, self.ny, self.nx) or f.dtype != torch.float64 or f.device.type != "cuda":
             raise ValueError(f"populations must be a float64 cuda tensor of shape (2, 9, {self.ny}, {self.nx})")
         f = f.contiguous()
+        self._take_over()
         _check(load().lbsep_set_populations(self._h, c_void_p(f.data_ptr()), int(t)))
         self._keep = f
 
     def synchronize(self):
         self.stream.synchronize()
+
+    # -- stream hand-over (the channel may run on a stream other than torch's) --
+    def _take_over(self):
+        """The channel's stream waits for torch's current stream (inputs ready)."""
+        cur = torch.cuda.current_stream(self.device)
+        if cur != self.stream:
+            self.stream.wait_stream(cur)
+
+    def _hand_over(self, out: torch.Tensor):
+        """torch's current stream waits for the channel's stream (output ready)."""
+        cur = torch.cuda.current_stream(self.device)
+        if cur != self.stream:
+            cur.wait_stream(self.stream)
+            out.record_stream(self.stream)
+
+
+class Batch:
+    """Several channels advanced by one sweep launch per step (lbsep_batch_*).
+
+    The channels must share one dtype and one stream; they stay usable through
+    their own readouts between batch steps. For a captured step graph
+    (``capture``) that stream must not be the default stream."""
+
+    def __init__(self, channels):
+        L = load()
+        self.channels = list(channels)
+        arr = (c_void_p * len(self.channels))(*[c._h.value for c in self.channels])
+        self._arr = arr
+        nbytes = L.lbsep_batch_workspace_bytes(arr, len(self.channels))
+        if nbytes == 0:
+            raise LbsepError(EINVAL, last_error())
+        dev = self.channels[0].device
+        raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        off = (-raw.data_ptr()) % 256
+        self._raw = raw
+        self.ws = raw[off:off + nbytes]
+        self.stream = self.channels[0].stream
+        if self.stream != torch.cuda.current_stream(dev):
+            raw.record_stream(self.stream)
+        h = c_void_p()
+        _check(L.lbsep_batch_create(arr, len(self.channels), c_void_p(self.ws.data_ptr()), c_size_t(nbytes),
+                                    byref(h)))
+        self._h = h
+
+    def step(self, nsteps: int = 1):
+        _check(load().lbsep_batch_step(self._h, int(nsteps)))
+
+    def capture(self, steps: int):
+        _check(load().lbsep_batch_capture(self._h, int(steps)))
+
+    def __len__(self):
+        return int(load().lbsep_batch_size(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().lbsep_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass

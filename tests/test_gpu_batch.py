@@ -1,0 +1,169 @@
+"""Batched sweeps (one launch per step over an instance table, optional HIP
+graph of the step loop): each member channel must evolve bitwise as it does
+when stepped alone (same kernels, same per-channel reductions), and so match
+the FP64 oracle wherever the single-channel path does."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import binary_lbm as O
+from paper_1603_08221_amd import lbsep
+from paper_1603_08221_amd.workloads import HE_AR, NE_AR, Workload, batch_instances
+
+from gpu_helpers import assert_cl, assert_moments, oracle_params, r_of
+
+pytestmark = pytest.mark.gpu
+
+# uneven members: lane-pair tiles (small) and one-lane-per-node tiles (the
+# 132 x 4000 channel has more than 2^19 nodes), ragged edges in x and y
+MEMBERS = [
+    Workload("b0", 80, 8, *HE_AR, 0.5, 0.5, 2.0, 0.1, 0),
+    Workload("b1", 333, 24, *NE_AR, 0.3, 0.3, 3.0, 0.05, 0),
+    Workload("b2", 150, 13, *HE_AR, 0.7, 0.4, 2.5, 0.5, 0),
+    Workload("b3", 4000, 132, *HE_AR, 0.5, 0.5, 2.0, 0.2, 0),
+    Workload("b4", 640, 32, *NE_AR, 0.6, 0.6, 1.5, 0.01, 0),
+]
+
+
+def _make(ws, dtype, stream=None):
+    out = []
+    for w in ws:
+        p = lbsep.make_params(w.nx, w.ny, w.m_a, w.m_b, w.cl_in, w.cl_out, w.theta, w.kn_out, r_of(w),
+                              dtype=dtype, hist_cap=512)
+        out.append(lbsep.Channel(p, device="cuda:0", stream=stream))
+    return out
+
+
+def _same(a, b, what):
+    for k, (x, y) in enumerate(zip(a, b)):
+        assert torch.equal(x.get_state(), y.get_state()), f"{what}: member {k} state differs"
+        ca, cb = x.read_cl(profile=True), y.read_cl(profile=True)
+        assert ca["cl"] == cb["cl"] and np.array_equal(ca["profile"], cb["profile"]), f"{what}: member {k} CL"
+        assert x.t == y.t
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "f16"])
+def test_batch_matches_members_stepped_alone(dtype):
+    batched = _make(MEMBERS, dtype)
+    alone = _make(MEMBERS, dtype)
+    b = lbsep.Batch(batched)
+    assert len(b) == len(MEMBERS)
+    b.step(1)
+    b.step(149)
+    for c in alone:
+        c.step(150)
+    _same(batched, alone, "after 150 steps")
+    # readouts between batch steps do not disturb the batch
+    b.step(7)
+    for c in alone:
+        c.step(7)
+    _same(batched, alone, "after 157 steps")
+
+
+def test_batch_fp64_members_match_the_oracle():
+    ws = MEMBERS[:3]
+    chans = _make(ws, "f64")
+    b = lbsep.Batch(chans)
+    b.step(300)
+    for w, c in zip(ws, chans):
+        p = oracle_params(w, r_of(w))
+        f, _ = O.run(p, 300)
+        assert_moments(c.read_moments(), O.moment_fields(f, p), 1e-12, w.name)
+        assert_cl(c.read_cl()["cl"], O.diagnostics(f, p).cl, 0.0, 1e-12)
+
+
+def test_batch_graph_replays_match_eager_steps():
+    """The captured step loop, replayed several times with eager work and
+    synchronisations between the replays, gives the eager result every time;
+    step counts that are not a multiple of the graph length finish eagerly."""
+    stream = torch.cuda.Stream()
+    batched = _make(MEMBERS, "f32", stream=stream)
+    alone = _make(MEMBERS, "f32")
+    b = lbsep.Batch(batched)
+    b.capture(25)
+    total = 0
+    for rep, n in enumerate((25, 25, 50, 30, 7)):
+        b.step(n)
+        total += n
+        for c in alone:
+            c.step(n)
+        torch.cuda.synchronize()
+        _same(batched, alone, f"replay round {rep} ({total} steps)")
+    b.capture(0)  # dropped: plain launches again
+    b.step(5)
+    for c in alone:
+        c.step(5)
+    _same(batched, alone, "after dropping the graph")
+
+
+def test_batch_rejects_members_stepped_alone_and_mixed_inputs():
+    chans = _make(MEMBERS[:2], "f32")
+    b = lbsep.Batch(chans)
+    b.step(3)
+    chans[0].step(1)
+    with pytest.raises(lbsep.LbsepError) as e:
+        b.step(1)
+    assert e.value.code == lbsep.EINVAL and "outside its batch" in str(e.value)
+    mixed = _make(MEMBERS[:1], "f32") + _make(MEMBERS[1:2], "f64")
+    with pytest.raises(lbsep.LbsepError):
+        lbsep.Batch(mixed)
+    with pytest.raises(lbsep.LbsepError):
+        lbsep.Batch([chans[1], chans[1]])
+    with pytest.raises(lbsep.LbsepError):
+        b.capture(10)  # default stream: no capture
+
+
+def _bits(t):
+    return t.view({torch.float64: torch.int64, torch.float32: torch.int32, torch.float16: torch.int16}[t.dtype])
+
+
+def _cl_or_error(c):
+    try:
+        return c.read_cl()["cl"]
+    except lbsep.LbsepError as e:
+        assert e.code == lbsep.ENONFINITE
+        return "non-finite"
+
+
+def test_batch_of_the_sweep_table_matches_members_stepped_alone():
+    """The 64-instance parametric table (seeded uneven H, C_l, theta, Kn_out),
+    FP32, 300 steps in one launch per step, against the same channels stepped
+    alone: bitwise equal states (NaN patterns included) and the same CL or the
+    same non-finite report. Some members with a mean free path below about one
+    lattice spacing diverge under the scheme itself (the oracle diverges on one
+    of them too, see the oracle pins): the batch must reproduce that, not hide it."""
+    ws = batch_instances()
+    batched = _make(ws, "f32")
+    b = lbsep.Batch(batched)
+    b.step(300)
+    for k, w in enumerate(ws):
+        alone = _make([w], "f32")[0]
+        alone.step(300)
+        assert torch.equal(_bits(batched[k].get_state()), _bits(alone.get_state())), w.name
+        assert _cl_or_error(batched[k]) == _cl_or_error(alone), w.name
+        del alone
+
+
+def test_autotuner_picks_a_candidate_and_caches_it(tmp_path):
+    from paper_1603_08221_amd import autotune
+
+    ps = [lbsep.make_params(w.nx, w.ny, w.m_a, w.m_b, w.cl_in, w.cl_out, w.theta, w.kn_out, r_of(w), dtype="f32")
+          for w in MEMBERS]
+    cache = str(tmp_path / "tune.json")
+    got = autotune.tune(ps, trial_steps=5, warmup=2, cache_file=cache)
+    cands = autotune.candidates(ps)
+    assert got["name"] in cands and got["modes"] == cands[got["name"]]
+    assert got["ms_per_step"] == min(got["timings"].values()) > 0
+    again = autotune.tune(ps, trial_steps=5, warmup=2, cache_file=cache)
+    assert again == got  # served from the cache
+    # the tuned assignment runs the same arithmetic: a tuned batch equals the default one
+    tuned = []
+    for w, m in zip(MEMBERS, got["modes"]):
+        p = lbsep.make_params(w.nx, w.ny, w.m_a, w.m_b, w.cl_in, w.cl_out, w.theta, w.kn_out, r_of(w),
+                              dtype="f32", hist_cap=512, tile_mode=m)
+        tuned.append(lbsep.Channel(p, device="cuda:0"))
+    plain = _make(MEMBERS, "f32")
+    lbsep.Batch(tuned).step(40)
+    lbsep.Batch(plain).step(40)
+    for a, b in zip(tuned, plain):
+        assert torch.equal(a.get_state(), b.get_state())

@@ -353,3 +353,21 @@ def test_equal_masses_do_not_separate():
     assert np.allclose(f[0] / f[1], 0.3 / 0.7, rtol=1e-12)
     d = O.diagnostics(f, p)
     assert abs(d.cl) < 1e-13 and abs(d.cl_tilde) < 1e-13
+
+
+def test_sweep_table_member_with_sub_lattice_mean_free_path_diverges():
+    """Member 32 of the seeded sweep table (Ne-Ar, H = 16, Kn_out = 0.0109, so
+    lambda_out = 0.17 lattice spacings, theta = 3.82) leaves the stable range of
+    the scheme: the oracle's populations turn non-finite within 300 steps. The
+    GPU batch reproduces such members bitwise instead of masking them."""
+    from paper_1603_08221_amd.workloads import batch_instances
+
+    w = batch_instances()[32]
+    assert (w.ny, round(w.kn_out, 4)) == (16, 0.0109)
+    p = O.Params(nx=w.nx, ny=w.ny, m_a=w.m_a, m_b=w.m_b, cl_in=w.cl_in, cl_out=w.cl_out, theta=w.theta,
+                 kn_out=w.kn_out, dbb_r=O.dbb_r_from_cm(w.c_m, w.m_a, w.m_b, w.cl_in))
+    f = O.initial_state(p)
+    with np.errstate(all="ignore"):
+        for _ in range(300):
+            f = O.step(f, p)
+    assert not np.isfinite(f).all()
