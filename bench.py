@@ -119,6 +119,7 @@ def batch_leg(torch, lbsep, dtype: str, steps: int):
             "frac_of_hbm_peak": round(alg / per / 1e9 / HBM_PEAK_GBS, 4), "tiles": tuned["name"],
             "tuning_ms_per_step": {k: round(v, 4) for k, v in tuned["timings"].items()},
             "graph_steps": 100, "diverged_members": diverged,
+            "traffic": (lambda v: None if v is None else round(v))(measured_traffic("sweep_table_64", dtype)),
             "t_final": chans[0].t}
 
 
