@@ -225,6 +225,39 @@ int32_t lbsep_batch_size(const lbsep_batch* b);
  * caller's). NULL is a no-op. */
 void lbsep_batch_destroy(lbsep_batch* b);
 
+/* ---- discrete adjoint (reverse mode) of the step --------------------------
+ * The step of Sec. 3 as a map of the pre-collision populations,
+ * f(t+1) = E(P(C(f(t)))): C the collision of Sec. 3.1 with the relaxation
+ * times of Eqs. (taos), (EQFrsp), (taoq) recomputed from the node's densities,
+ * P the streaming of Eq. (MRT) with the DBB walls of Eqs. (bot), (bot2), E the
+ * inlet/outlet of Eqs. (rho1), (rho2). The parameters differentiated are
+ * (theta, C_in, r): theta and C_in through the inlet densities of Eq. (rho2)
+ * and the initial state of R18, r through the DBB walls; C_out, Kn_out and the
+ * masses are held. All arithmetic is FP64 on populations and adjoints in the
+ * dense layout [2][9][ny][nx] of lbsep_get_populations (whatever the channel's
+ * storage type); the channel supplies the parameters and the stream. adj_ws:
+ * caller-owned device workspace, 256-byte aligned, of
+ * lbsep_adjoint_workspace_bytes. dparams: device double[3] (theta, C_in, r),
+ * accumulated (+=). All calls enqueue only. */
+size_t lbsep_adjoint_workspace_bytes(const lbsep_params* p);
+
+/* lam_out = (d f(t+1) / d f(t))^T lam_next at the pre-collision state f_t;
+ * dparams += lam_next . d f(t+1) / d(theta, C_in, r) at fixed f_t. lam_out
+ * must not alias f_t or lam_next. */
+int lbsep_adjoint_step(lbsep_channel* ch, const double* f_t, const double* lam_next, double* lam_out,
+                       double* dparams, void* adj_ws, size_t adj_ws_bytes);
+
+/* Seed of J = CL (Eq. (CL)) at the pre-collision state f_T: lam_out = dCL/df_T
+ * (nonzero on the column of the smallest C_l only, R16) and dparams[1] +=
+ * the explicit dCL/dC_in = C_l,min / C_in^2. */
+int lbsep_adjoint_seed_cl(lbsep_channel* ch, const double* f_T, double* lam_out, double* dparams, void* adj_ws,
+                          size_t adj_ws_bytes);
+
+/* dparams[0..1] += lam0 . d f(0) / d(theta, C_in) for the initial state of R18
+ * (local equilibrium at rest, pressure and C_l linear in x). Needs inlet and
+ * outlet (not LBSEP_PERIODIC_X). */
+int lbsep_adjoint_initial(lbsep_channel* ch, const double* lam0, double* dparams, void* adj_ws, size_t adj_ws_bytes);
+
 #ifdef __cplusplus
 }
 #endif

@@ -12,7 +12,7 @@ import tempfile
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = [os.path.join(HERE, "csrc", "lbsep.hip")]
+SOURCES = [os.path.join(HERE, "csrc", "lbsep.hip"), os.path.join(HERE, "csrc", "lbsep_adjoint.hip")]
 OUT = os.path.join(HERE, "liblbsep.so")
 
 FLAGS = [

@@ -198,12 +198,12 @@ def main():
             lines.append(f"#define LBSEP_E1_{tag}_NSEG {nseg}")
             lines.append(f"#define LBSEP_E1_{tag}_DEG {deg}")
         lines.append(f"#define LBSEP_E1_{tag}_NSER {nser}")
-        lines.append(f"__constant__ {name} lbsep_psi_a_{tag.lower()}[{nser}] = {{")
+        lines.append(f"static __constant__ {name} lbsep_psi_a_{tag.lower()}[{nser}] = {{")
         lines.append("    " + ", ".join(fmt(c, single) for c in al) + "};")
-        lines.append(f"__constant__ {name} lbsep_psi_b_{tag.lower()}[{nser}] = {{")
+        lines.append(f"static __constant__ {name} lbsep_psi_b_{tag.lower()}[{nser}] = {{")
         lines.append("    " + ", ".join(fmt(c, single) for c in be) + "};")
         if not single:  # FP32 uses the rational below for a > 1
-            lines.append(f"__constant__ {name} lbsep_e1_cheb_{tag.lower()}[{nseg}][{deg + 1}] = {{")
+            lines.append(f"static __constant__ {name} lbsep_e1_cheb_{tag.lower()}[{nseg}][{deg + 1}] = {{")
             for seg in segs:
                 lines.append("    {" + ", ".join(fmt(c, single) for c in seg) + "},")
             lines.append("};")

@@ -61,6 +61,7 @@
 
 #include "lbsep.h"
 #include "lbsep_device.h"
+#include "lbsep_view.h"
 
 namespace lbsep {
 namespace {
@@ -1429,14 +1430,30 @@ void enqueue_batch_steps(lbsep_batch* b, int64_t n) {
 }
 
 void drop_graph(lbsep_batch* b) {
-  if (b->exec) hipGraphExecDestroy(b->exec);
-  if (b->graph) hipGraphDestroy(b->graph);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
   b->exec = nullptr;
   b->graph = nullptr;
   b->graph_steps = 0;
 }
 
 }  // namespace
+
+namespace lbsep {
+
+bool channel_view(const lbsep_channel* h, ChannelView* out) {
+  if (!h || !out) return false;
+  out->p = h->p;
+  out->rc = h->kp.rc;
+  for (int e = 0; e < 2; ++e)
+    for (int s = 0; s < 2; ++s) out->rho_bc[e][s] = h->kp.rho_bc[e][s];
+  out->stream = h->stream;
+  return true;
+}
+
+int set_error(int code, const char* msg) { return fail(code, msg); }
+
+}  // namespace lbsep
 
 extern "C" {
 
@@ -1548,7 +1565,7 @@ int lbsep_batch_capture(lbsep_batch* b, int64_t steps) {
   hipGraphExec_t x = nullptr;
   rc = check_hip(hipGraphInstantiate(&x, g, nullptr, nullptr, 0), "graph instantiate");
   if (rc) {
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     return rc;
   }
   b->graph = g;

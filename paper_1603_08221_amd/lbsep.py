@@ -80,6 +80,10 @@ def load():
         "lbsep_batch_capture": (c_int, [c_void_p, c_int64]),
         "lbsep_batch_size": (c_int32, [c_void_p]),
         "lbsep_batch_destroy": (None, [c_void_p]),
+        "lbsep_adjoint_workspace_bytes": (c_size_t, [P]),
+        "lbsep_adjoint_step": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t]),
+        "lbsep_adjoint_seed_cl": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t]),
+        "lbsep_adjoint_initial": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_size_t]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)

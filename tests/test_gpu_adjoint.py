@@ -1,0 +1,146 @@
+"""The hand-written discrete adjoint (HIP, through the C ABI) against the CPU
+FP64 reverse sweep (oracle/adjoint.py: reverse-mode differentiation of the
+oracle's step) and against central finite differences of the GPU forward."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import adjoint as A
+from oracle import binary_lbm as O
+from paper_1603_08221_amd import lbsep
+from paper_1603_08221_amd.adjoint import Adjoint, SeparationDegree, cl_gradient
+from paper_1603_08221_amd.workloads import CONFIGS, HE_AR, NE_AR, Workload
+
+from gpu_helpers import channel, oracle_params, r_of
+
+pytestmark = pytest.mark.gpu
+
+SMALL = Workload("adj", 40, 6, *HE_AR, 0.5, 0.5, 2.0, 0.1, 0)
+MODES = [{}, {"periodic_x": True}, {"periodic_y": True, "mfp_off": True}, {"mfp_off": True}]
+
+
+def _state(p, seed=3):
+    rng = np.random.default_rng(seed)
+    f = O.initial_state(p) if not p.periodic_x else O.initial_state(
+        O.Params(**{**p.__dict__, "periodic_x": False}))
+    return f * (1.0 + 0.02 * rng.uniform(-1, 1, size=f.shape))
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+@pytest.mark.parametrize("modes", MODES, ids=["walls+ends", "periodic_x", "periodic_y+mfp_off", "mfp_off"])
+def test_adjoint_step_matches_the_cpu_reverse_sweep(modes):
+    w = SMALL.with_(ny=9) if "periodic_y" in modes else SMALL
+    r = r_of(w)
+    ch = channel(w, r, **modes)
+    p = oracle_params(w, r, **modes)
+    f = _state(p)
+    lam = np.random.default_rng(11).standard_normal(f.shape)
+    ref_lam, ref_dp = A.step_vjp(f, lam, p)
+    adj = Adjoint(ch)
+    got = adj.step(torch.from_numpy(f).cuda(), torch.from_numpy(lam).cuda()).cpu().numpy()
+    assert _rel(got, ref_lam) <= 1e-12
+    dp = adj.dparams.cpu().numpy()
+    for k in range(3):
+        assert abs(dp[k] - ref_dp[k]) <= 1e-11 * max(abs(ref_dp[k]), 1e-3), (k, dp[k], ref_dp[k])
+
+
+def test_adjoint_step_bgk_limit():
+    w = SMALL
+    r = r_of(w)
+    ch = channel(w, r, tau_bgk=0.8)
+    p = oracle_params(w, r, tau_bgk=0.8)
+    f = _state(p)
+    lam = np.random.default_rng(5).standard_normal(f.shape)
+    ref_lam, _ = A.step_vjp(f, lam, p)
+    got = Adjoint(ch).step(torch.from_numpy(f).cuda(), torch.from_numpy(lam).cuda()).cpu().numpy()
+    assert _rel(got, ref_lam) <= 1e-12
+
+
+def test_seed_and_initial_terms_match_the_cpu_reverse_sweep():
+    w = SMALL
+    r = r_of(w)
+    p = oracle_params(w, r)
+    f = O.run(p, 60)[0]
+    ft = torch.tensor(f, dtype=torch.float64, requires_grad=True)
+    cl_in = torch.tensor(p.cl_in, dtype=torch.float64, requires_grad=True)
+    g_f, g_c = torch.autograd.grad(A.separation_degree(ft, p, cl_in), (ft, cl_in))
+    ch = channel(w, r)
+    adj = Adjoint(ch)
+    seed = adj.seed_cl(torch.from_numpy(f).cuda()).cpu().numpy()
+    assert _rel(seed, g_f.numpy()) <= 1e-13
+    assert abs(adj.dparams[1].item() - g_c.item()) <= 1e-13 * abs(g_c.item())
+    # initial state: lam0 . d f0 / d(theta, C_in)
+    lam0 = np.random.default_rng(9).standard_normal(f.shape)
+    th = torch.tensor(p.theta, dtype=torch.float64, requires_grad=True)
+    cl = torch.tensor(p.cl_in, dtype=torch.float64, requires_grad=True)
+    f0 = A.initial_state(p, th, cl)
+    ref = torch.autograd.grad(f0, (th, cl), grad_outputs=torch.from_numpy(lam0))
+    adj2 = Adjoint(ch)
+    adj2.initial(torch.from_numpy(lam0).cuda())
+    got = adj2.dparams.cpu().numpy()
+    for k in range(2):
+        assert abs(got[k] - ref[k].item()) <= 1e-12 * abs(ref[k].item()), (k, got[k], ref[k].item())
+    assert got[2] == 0.0
+
+
+def _params(w, r, dtype="f64"):
+    return lbsep.make_params(w.nx, w.ny, w.m_a, w.m_b, w.cl_in, w.cl_out, w.theta, w.kn_out, r, dtype=dtype,
+                             hist_cap=64)
+
+
+def test_checkpointed_gradient_matches_the_cpu_reverse_sweep():
+    """150 steps, checkpoints every 40 (four segments, the last one short)."""
+    w = SMALL
+    r = r_of(w)
+    cl, grad = cl_gradient(_params(w, r), 150, checkpoint_every=40)
+    cl_ref, g_ref = A.gradients(oracle_params(w, r), 150)
+    assert abs(cl - cl_ref) <= 1e-12
+    grad = grad.cpu().numpy()
+    for k in range(3):
+        assert abs(grad[k] - g_ref[k]) <= 1e-9 * abs(g_ref[k]), (k, grad[k], g_ref[k])
+
+
+def _cl_run(w, r, steps, **over):
+    p = _params(w, r)
+    for k, v in over.items():
+        setattr(p, k, v)
+    ch = lbsep.Channel(p, device="cuda:0")
+    ch.step(steps)
+    out = ch.read_cl()
+    return out["cl"], out["x_min"]
+
+
+def test_gradient_of_the_adjoint_configuration_matches_central_differences():
+    """He-Ar, H = 64, L = 1280, C_l = 0.5, theta = 2.5, Kn_out = 0.1, FP64,
+    10,000 steps, checkpoints every 500: the three gradients against central
+    differences of the GPU forward with h = 1e-6 (relative), to 1e-4."""
+    w = CONFIGS["he_ar_64x1280"]
+    steps = 10000
+    r = r_of(w)
+    cl, grad = cl_gradient(_params(w, r), steps, checkpoint_every=500)
+    grad = grad.cpu().numpy()
+    base = {"theta": w.theta, "cl_in": w.cl_in, "dbb_r": r}
+    for k, name in enumerate(("theta", "cl_in", "dbb_r")):
+        h = 1e-6 * base[name]
+        c_up, x_up = _cl_run(w, r, steps, **{name: base[name] + h})
+        c_dn, x_dn = _cl_run(w, r, steps, **{name: base[name] - h})
+        assert x_up == x_dn
+        fd = (c_up - c_dn) / (2 * h)
+        assert abs(grad[k] - fd) <= 1e-4 * abs(fd), (name, grad[k], fd)
+
+
+def test_autograd_function_returns_the_adjoint_gradients():
+    w = SMALL
+    r = r_of(w)
+    base = _params(w, r)
+    th = torch.tensor(w.theta, dtype=torch.float64, requires_grad=True)
+    cl = torch.tensor(w.cl_in, dtype=torch.float64, requires_grad=True)
+    rr = torch.tensor(r, dtype=torch.float64, requires_grad=True)
+    out = SeparationDegree.apply(th, cl, rr, base, 100, 30)
+    (3.0 * out).backward()
+    _, g_ref = A.gradients(oracle_params(w, r), 100)
+    for t, g in zip((th, cl, rr), g_ref):
+        assert abs(t.grad.item() - 3.0 * g) <= 1e-9 * abs(3.0 * g)
