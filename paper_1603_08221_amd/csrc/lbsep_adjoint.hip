@@ -161,7 +161,7 @@ __device__ void taus_rev(const RelaxConsts& c, int j, double ra, double rb, doub
   bk += bts * lam * psi_m;
   if (!c.mfp_off) {
     const double bpsm = bts * lam * k;
-    double bay = bpsm * hay, bab = bpsm * hab;  // d psi_m / d ay = psi.(ay) / 2 = h(ay)
+    double bay = bpsm * hay, bab = bpsm * hab;  // d psi_m / d ay = psi'(ay) / 2 = h(ay)
     // psi_a = (psi(xa ay) + psi(xa ab)) / 2
     const double z1a = bpsa * h1a, z2a = bpsa * h2a;
     bxa += z1a * ay + z2a * ab;
