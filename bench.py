@@ -123,6 +123,28 @@ def batch_leg(torch, lbsep, dtype: str, steps: int):
             "t_final": chans[0].t}
 
 
+def adjoint_leg(torch, lbsep, steps: int):
+    """dCL/d(theta, C_in, r) of the He-Ar 64 x 1280 channel (C_l 0.5, theta 2.5,
+    Kn_out 0.1, FP64) over `steps` steps with checkpoints every 500: wall time of
+    the whole gradient (forward, recomputation, reverse sweep)."""
+    from paper_1603_08221_amd.adjoint import cl_gradient
+    from paper_1603_08221_amd.workloads import CONFIGS
+
+    w = CONFIGS["he_ar_64x1280"]
+    r = lbsep.dbb_r_from_cm(w.c_m, w.m_a, w.m_b, w.cl_in)
+    p = lbsep.make_params(w.nx, w.ny, w.m_a, w.m_b, w.cl_in, w.cl_out, w.theta, w.kn_out, r, dtype="f64",
+                          hist_cap=64)
+    cl_gradient(p, 200, checkpoint_every=100)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cl, g = cl_gradient(p, steps, checkpoint_every=500)
+    wall = time.perf_counter() - t0
+    g = g.cpu().tolist()
+    return {"workload": w.name, "steps": steps, "checkpoint_every": 500, "seconds": round(wall, 3),
+            "cl": cl, "dcl_dtheta": g[0], "dcl_dcl_in": g[1], "dcl_dr": g[2],
+            "us_per_step_forward_recompute_reverse": round(wall / steps * 1e6, 2)}
+
+
 def cpu_baseline(w, r, seconds: float):
     """The CPU oracle as it stands, on the same workload, for a bounded number
     of steps (about `seconds` of CPU work), single BLAS thread."""
@@ -177,6 +199,8 @@ def main():
     ap.add_argument("--no-large", action="store_true",
                     help="skip the leg on the 512 x 10240 channel (above the last-level cache)")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-channel batched sweep leg")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-gradient leg")
+    ap.add_argument("--adjoint-steps", type=int, default=10000)
     ap.add_argument("--batch-steps", type=int, default=1000)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device copy of this size (PMC calibration)")
@@ -273,6 +297,8 @@ def main():
         del chl
     if not args.no_batch:
         out["batch"] = batch_leg(torch, lbsep, args.dtype, args.batch_steps)
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_leg(torch, lbsep, args.adjoint_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, r, args.cpu_seconds)
         out["fp64_vs_oracle"] = oracle_parity(lbsep, w, r, 100)

@@ -179,6 +179,13 @@ def main():
         "// t = (2a - 3*2^s) / 2^s, evaluated by Clenshaw's recurrence.",
         "#pragma once",
         "",
+        "// Device code is compiled per translation unit, so every unit of the library",
+        "// that evaluates the wall function defines its own copy of the tables;",
+        "// LBSEP_TBL gives each unit's copy its own (external) name.",
+        "#ifndef LBSEP_TBL",
+        "#define LBSEP_TBL(name) name",
+        "#endif",
+        "",
         "#define LBSEP_EULER_GAMMA " + mp.nstr(mp.euler, 22),
     ]
     for name, (nseg, tol, nser) in cfg.items():
@@ -198,12 +205,12 @@ def main():
             lines.append(f"#define LBSEP_E1_{tag}_NSEG {nseg}")
             lines.append(f"#define LBSEP_E1_{tag}_DEG {deg}")
         lines.append(f"#define LBSEP_E1_{tag}_NSER {nser}")
-        lines.append(f"static __constant__ {name} lbsep_psi_a_{tag.lower()}[{nser}] = {{")
+        lines.append(f"__constant__ {name} LBSEP_TBL(lbsep_psi_a_{tag.lower()})[{nser}] = {{")
         lines.append("    " + ", ".join(fmt(c, single) for c in al) + "};")
-        lines.append(f"static __constant__ {name} lbsep_psi_b_{tag.lower()}[{nser}] = {{")
+        lines.append(f"__constant__ {name} LBSEP_TBL(lbsep_psi_b_{tag.lower()})[{nser}] = {{")
         lines.append("    " + ", ".join(fmt(c, single) for c in be) + "};")
         if not single:  # FP32 uses the rational below for a > 1
-            lines.append(f"static __constant__ {name} lbsep_e1_cheb_{tag.lower()}[{nseg}][{deg + 1}] = {{")
+            lines.append(f"__constant__ {name} LBSEP_TBL(lbsep_e1_cheb_{tag.lower()})[{nseg}][{deg + 1}] = {{")
             for seg in segs:
                 lines.append("    {" + ", ".join(fmt(c, single) for c in seg) + "},")
             lines.append("};")

@@ -25,6 +25,9 @@
 // Populations and adjoints use the dense FP64 layout [2][9][ny][nx] of
 // lbsep_get_populations.
 
+// this unit's own copy of the coefficient tables (see e1_table.h)
+#define LBSEP_TBL(name) adj_##name
+
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -74,11 +77,11 @@ __device__ double e1_dev(double a) {
   const double t2 = t + t;
   double b1 = 0.0, b2 = 0.0;
   for (int k = LBSEP_E1_F64_DEG; k >= 1; --k) {
-    const double b0 = lbsep_e1_cheb_f64[seg][k] + t2 * b1 - b2;
+    const double b0 = LBSEP_TBL(lbsep_e1_cheb_f64)[seg][k] + t2 * b1 - b2;
     b2 = b1;
     b1 = b0;
   }
-  const double g = lbsep_e1_cheb_f64[seg][0] + t * b1 - b2;
+  const double g = LBSEP_TBL(lbsep_e1_cheb_f64)[seg][0] + t * b1 - b2;
   return exp(-a) * g / a;
 }
 

@@ -22,9 +22,9 @@ template <> struct E1Traits<double> {
   static constexpr int kSeg = LBSEP_E1_F64_NSEG;
   static constexpr int kDeg = LBSEP_E1_F64_DEG;
   static constexpr int kSer = LBSEP_E1_F64_NSER;
-  __device__ static double pa(int k) { return lbsep_psi_a_f64[k]; }
-  __device__ static double pb(int k) { return lbsep_psi_b_f64[k]; }
-  __device__ static double cheb(int s, int k) { return lbsep_e1_cheb_f64[s][k]; }
+  __device__ static double pa(int k) { return LBSEP_TBL(lbsep_psi_a_f64)[k]; }
+  __device__ static double pb(int k) { return LBSEP_TBL(lbsep_psi_b_f64)[k]; }
+  __device__ static double cheb(int s, int k) { return LBSEP_TBL(lbsep_e1_cheb_f64)[s][k]; }
   __device__ static double ex(double a) { return exp(a); }
   __device__ static double ln(double a) { return log(a); }
   __device__ static double rsq(double a) { return 1.0 / sqrt(a); }
@@ -36,8 +36,8 @@ template <> struct E1Traits<float> {
   static constexpr int kSeg = 0;
   static constexpr int kDeg = 0;
   static constexpr int kSer = LBSEP_E1_F32_NSER;
-  __device__ static float pa(int k) { return lbsep_psi_a_f32[k]; }
-  __device__ static float pb(int k) { return lbsep_psi_b_f32[k]; }
+  __device__ static float pa(int k) { return LBSEP_TBL(lbsep_psi_a_f32)[k]; }
+  __device__ static float pb(int k) { return LBSEP_TBL(lbsep_psi_b_f32)[k]; }
   __device__ static float cheb(int, int) { return 0.0f; }
   __device__ static float ex(float a) { return __builtin_amdgcn_exp2f(a * 1.4426950408889634f); }
   __device__ static float ln(float a) { return __builtin_amdgcn_logf(a) * 0.6931471805599453f; }
