@@ -150,6 +150,12 @@ int lbsep_read_history(lbsep_channel* ch, int64_t t0, int64_t count, double* hos
  * workspace; synchronises. */
 int lbsep_read_moments(lbsep_channel* ch, double* host);
 
+/* Volume flow of the mixture through every cross-section (the Q_v of Sec. 4,
+ * whose formula is not printed; reading: Q_v(x) = sum_j u_x(x, j) delta_y with
+ * the mixture velocity u of Eq. (rhou), lattice units), host [nx] doubles.
+ * Uses the workspace; synchronises. */
+int lbsep_read_volume_flow(lbsep_channel* ch, double* host);
+
 /* Write the current raw state (storage representation, layout above) to
  * device memory dev_dst (lbsep_state_bytes bytes): a bitwise checkpoint.
  * Enqueues only. */

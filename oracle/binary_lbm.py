@@ -468,6 +468,14 @@ def diagnostics(f: np.ndarray, p: Params) -> Diagnostics:
     return Diagnostics(n_a, n_b, j_a, j_b, cl_x, float(cl), cl_tilde, x_min)
 
 
+def volume_flow(f: np.ndarray, p: Params) -> np.ndarray:
+    """Q_v(x) = sum_j u_x(x, j): volume flow of the mixture through each
+    cross-section (Sec. 4, Fig. of Q_v against Kn_out; the formula is not
+    printed, R25), u the mixture velocity of Eq. (rhou), delta_y = 1."""
+    _, _, _, _, ux, _ = moments(f)
+    return ux.sum(axis=0)
+
+
 def moment_fields(f: np.ndarray, p: Params) -> np.ndarray:
     """(6, ny, nx): rho_a, rho_b, u_ax, u_ay, u_bx, u_by (species velocity of Eq. (rhou))."""
     rho_s, ux_s, uy_s = species_velocity(f, p)

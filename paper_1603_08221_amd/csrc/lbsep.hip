@@ -813,6 +813,22 @@ __global__ void k_wall_function(const double* __restrict__ a, double* __restrict
   }
 }
 
+// Volume flow through each cross-section, Q_v(x) = sum_j u_x(x, j) (mixture
+// velocity; the species momenta of Eq. (rhou) add up to the mixture momentum),
+// from the moment fields [6][ny][nx]; one thread per column, rows in order.
+__global__ void k_volume_flow(const double* __restrict__ mom, int nx, int ny, double* __restrict__ q) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= nx) return;
+  const long long n = (long long)nx * ny;
+  double acc = 0.0;
+  for (int j = 0; j < ny; ++j) {
+    const long long o = (long long)j * nx + x;
+    const double ra = mom[o], rb = mom[n + o];
+    acc += (ra * mom[2 * n + o] + rb * mom[4 * n + o]) / (ra + rb);
+  }
+  q[x] = acc;
+}
+
 __global__ void k_zero_u32(unsigned* p, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0u;
@@ -1278,6 +1294,22 @@ int lbsep_read_moments(lbsep_channel* h, double* host) {
                                 h->stream),
                  "moments copy");
   if (!rc) rc = check_hip(hipStreamSynchronize(h->stream), "moments sync");
+  return rc;
+}
+
+int lbsep_read_volume_flow(lbsep_channel* h, double* host) {
+  if (!h || !host) return fail(LBSEP_EINVAL, "NULL argument");
+  int rc = eval_state(h, h->mom, nullptr, nullptr);
+  if (rc) return rc;
+  // the profile is written over the u_ay plane, which the flow does not read
+  double* q = h->mom + 3ull * h->p.ny * h->p.nx;
+  hipLaunchKernelGGL(k_volume_flow, dim3((h->p.nx + 255) / 256), dim3(256), 0, h->stream, h->mom, h->p.nx,
+                     h->p.ny, q);
+  rc = check_hip(hipGetLastError(), "volume flow launch");
+  if (!rc)
+    rc = check_hip(hipMemcpyAsync(host, q, (size_t)h->p.nx * sizeof(double), hipMemcpyDeviceToHost, h->stream),
+                   "volume flow copy");
+  if (!rc) rc = check_hip(hipStreamSynchronize(h->stream), "volume flow sync");
   return rc;
 }
 

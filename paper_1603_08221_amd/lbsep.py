@@ -66,6 +66,7 @@ def load():
         "lbsep_read_column_sums": (c_int, [c_void_p, POINTER(c_double)]),
         "lbsep_read_history": (c_int, [c_void_p, c_int64, c_int64, POINTER(c_double)]),
         "lbsep_read_moments": (c_int, [c_void_p, POINTER(c_double)]),
+        "lbsep_read_volume_flow": (c_int, [c_void_p, POINTER(c_double)]),
         "lbsep_get_state": (c_int, [c_void_p, c_void_p]),
         "lbsep_set_state": (c_int, [c_void_p, c_void_p, c_int64]),
         "lbsep_get_populations": (c_int, [c_void_p, c_void_p]),
@@ -203,6 +204,11 @@ class Channel:
     def read_moments(self) -> np.ndarray:
         out = np.empty((6, self.ny, self.nx))
         _check(load().lbsep_read_moments(self._h, _dptr(out)))
+        return out
+
+    def read_volume_flow(self) -> np.ndarray:
+        out = np.empty(self.nx)
+        _check(load().lbsep_read_volume_flow(self._h, _dptr(out)))
         return out
 
     def get_state(self) -> torch.Tensor:

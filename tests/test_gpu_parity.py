@@ -349,3 +349,18 @@ def test_fp64_parity_each_tile_shape(mode):
     f, _ = O.run(p, 500)
     assert_moments(ch.read_moments(), O.moment_fields(f, p), TOL64, f"tile mode {mode}")
     assert_cl(ch.read_cl()["cl"], O.diagnostics(f, p).cl, 0.0, CL64)
+
+
+def test_volume_flow_profile_matches_the_oracle():
+    """Q_v(x) of the device readout against the oracle, FP64 (1e-12 relative
+    to the largest column flow) and FP32 (1e-5)."""
+    w = CONFIGS["he_ar_8x80"].with_(nx=150, ny=12)
+    r = r_of(w)
+    p = oracle_params(w, r)
+    f, _ = O.run(p, 400)
+    ref = O.volume_flow(f, p)
+    for dtype, tol in (("f64", 1e-12), ("f32", 1e-5)):
+        ch = channel(w, r, dtype=dtype)
+        ch.step(400)
+        q = ch.read_volume_flow()
+        assert np.max(np.abs(q - ref)) <= tol * np.max(np.abs(ref)), dtype

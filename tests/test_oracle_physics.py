@@ -142,3 +142,25 @@ def test_near_continuum_poiseuille_is_parabolic():
     mu = rho[:, xm].mean() * O.CS2 * (rt.tau_s[:, xm].mean() - 0.5)
     curv = 2 * coef[0]
     assert abs(curv - dpdx / mu) / abs(dpdx / mu) < 0.02
+
+
+def test_volume_flow_equal_masses_matches_the_single_species_solver():
+    """R25 (Q_v of Sec. 4): with m_a = m_b the mixture volume flow sum_j u_x
+    equals that of the independent single-species solver (its own moments),
+    and it is also the density-weighted sum of the species velocities of
+    Eq. (rhou) (species momenta add up to the mixture momentum)."""
+    ny, nx, kn, r, theta = 6, 24, 0.2, 0.74, 2.0
+    p = O.Params(nx=nx, ny=ny, m_a=10, m_b=10, cl_in=0.35, cl_out=0.35, theta=theta, kn_out=kn, dbb_r=r)
+    f = O.initial_state(p)
+    g = f[0] + f[1]
+    for _ in range(150):
+        f = O.step(f, p)
+        g = _single_species_step(g, ny, nx, kn, r, theta, 1.0)
+    cx = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1], dtype=np.float64)
+    q_single = (np.tensordot(cx, g, axes=([0], [0])) / g.sum(axis=0)).sum(axis=0)
+    q = O.volume_flow(f, p)
+    assert np.max(np.abs(q - q_single)) <= 1e-12 * np.max(np.abs(q_single))
+    mf = O.moment_fields(f, p)
+    q_species = ((mf[0] * mf[2] + mf[1] * mf[4]) / (mf[0] + mf[1])).sum(axis=0)
+    assert np.max(np.abs(q - q_species)) <= 1e-12 * np.max(np.abs(q))
+    assert np.all(q > 0)  # the pressure drives the flow from inlet to outlet
