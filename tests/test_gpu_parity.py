@@ -76,6 +76,8 @@ def test_fp64_history_matches_oracle_per_step():
     (40, 6, HE_AR, 0.3, 0.3, 4.0, 0.3, 300),       # one column strip holds both ends
     (6, 2, NE_AR, 0.5, 0.5, 2.0, 0.5, 200),        # smallest channel
     (333, 24, HE_AR, 0.5, 0.5, 5.0, 0.01, 150),    # tiny mean free path, large tau_q
+    (24, 2048, HE_AR, 0.5, 0.5, 2.0, 0.1, 20),     # tallest channel: 32 end blocks per end
+    (24, 1000, NE_AR, 0.4, 0.4, 2.0, 0.2, 30),     # end blocks with a ragged last block
 ])
 def test_fp64_ragged_and_edge_shapes(nx, ny, pair, cin, cout, theta, kn, steps):
     w = Workload("edge", nx, ny, *pair, cin, cout, theta, kn, steps)
