@@ -366,3 +366,44 @@ def test_volume_flow_profile_matches_the_oracle():
         ch.step(400)
         q = ch.read_volume_flow()
         assert np.max(np.abs(q - ref)) <= tol * np.max(np.abs(ref)), dtype
+
+
+def _random_case(k):
+    """Seeded random problem statements (sizes, masses, composition, pressure
+    ratio, Kn_out, DBB coefficient, accommodation, boundary modes)."""
+    rng = np.random.default_rng(1000 + k)
+    nx = int(rng.integers(6, 90))
+    ny = int(rng.integers(2, 30))
+    m_a = float(rng.uniform(1.0, 30.0))
+    m_b = float(m_a * rng.uniform(1.0, 12.0))
+    cin, cout = (float(v) for v in rng.uniform(0.1, 0.9, size=2))
+    theta = float(rng.uniform(1.2, 4.0))
+    kn = float(10 ** rng.uniform(-1, 0.5))
+    r = float(rng.uniform(0.0, 1.6))
+    accom = float(rng.uniform(0.5, 1.0))
+    modes = {}
+    if k % 4 == 1:
+        modes["periodic_x"] = True
+    if k % 4 == 2:
+        modes["mfp_off"] = True
+        modes["periodic_y"] = bool(rng.integers(0, 2))
+    w = Workload(f"rand{k}", nx, ny, m_a, m_b, cin, cout, theta, kn, 60, accom=accom)
+    return w, r, modes
+
+
+@pytest.mark.parametrize("k", range(8))
+def test_fp64_random_problem_statements(k):
+    """FP64 parity (1e-12) on seeded random problem statements, each through
+    the tile shape AUTO picks and through the other one."""
+    w, r, modes = _random_case(k)
+    print(f"[case] random {k}: {w} r={r:.3f} {modes}", flush=True)
+    p = oracle_params(w, r, **modes)
+    f, _ = O.run(p, w.steps)
+    ref = O.moment_fields(f, p)
+    d = O.diagnostics(f, p)
+    for tm in (lbsep.TILE_SPLIT, lbsep.TILE_NODE):
+        ch = channel(w, r, tile_mode=tm, **modes)
+        ch.step(w.steps)
+        assert_moments(ch.read_moments(), ref, TOL64, f"random {k} tile {tm}")
+        if not modes.get("periodic_x"):
+            assert_cl(ch.read_cl()["cl"], d.cl, 0.0, CL64)
