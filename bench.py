@@ -123,6 +123,75 @@ def batch_leg(torch, lbsep, dtype: str, steps: int):
             "t_final": chans[0].t}
 
 
+def species_velocity_residual(m_now, m_then, gap: int) -> float:
+    """max over species of ||u_s(t) - u_s(t - gap)||_2 / (gap ||u_s(t)||_2), both
+    components, from two moment fields [6][ny][nx] (the steady-state test)."""
+    import numpy as np
+
+    out = 0.0
+    for k in (2, 4):
+        du = np.sqrt(np.sum((m_now[k] - m_then[k]) ** 2 + (m_now[k + 1] - m_then[k + 1]) ** 2))
+        un = np.sqrt(np.sum(m_now[k] ** 2 + m_now[k + 1] ** 2))
+        out = max(out, float(du / (gap * un)))
+    return out
+
+
+def steady_leg(torch, lbsep, w, max_steps: int = 50000, check_every: int = 1000, gap: int = 100,
+               tol: float = 1e-8):
+    """The headline channel run to steady state (species-velocity residual
+    below tol between levels `gap` apart, checked every `check_every` steps, or
+    max_steps) in FP32 deviation storage and in FP64: steps taken, residual,
+    CL, C~_l and the C_l(x) profile every 64 columns, FP32 against FP64."""
+    out = {}
+    for dtype in ("f32", "f64"):
+        ch, _ = make_channel(lbsep, w, dtype, hist_cap=64)
+        t0 = time.perf_counter()
+        res = float("inf")
+        while ch.t < max_steps:
+            ch.step(check_every - gap)
+            m_then = ch.read_moments()
+            ch.step(gap)
+            res = species_velocity_residual(ch.read_moments(), m_then, gap)
+            if res < tol:
+                break
+        cl = ch.read_cl(profile=True)
+        out[dtype] = {"steps": ch.t, "residual": res, "seconds": round(time.perf_counter() - t0, 2),
+                      "cl": cl["cl"], "cl_tilde": cl["cl_tilde"], "x_min": cl["x_min"],
+                      "cl_profile_every_64": [round(v, 9) for v in cl["profile"][::64].tolist()]}
+        del ch
+    out["cl_err_f32_vs_f64"] = abs(out["f32"]["cl"] - out["f64"]["cl"])
+    out["workload"] = w.name
+    out["criterion"] = f"residual < {tol} (levels {gap} apart) or {max_steps} steps"
+    return out
+
+
+def precision_leg(torch, lbsep, steps: int):
+    """He-Ar 256 x 5120 (C_l 0.5, theta 2, Kn_out 0.2) for `steps` steps in FP64,
+    FP32-deviation and FP16-deviation storage: time per step and the CL and
+    C~_l error of each reduced-precision run against the FP64 run."""
+    from paper_1603_08221_amd.workloads import CONFIGS
+
+    wl = CONFIGS["he_ar_256x5120"]
+    res = {"workload": wl.name, "steps": steps}
+    ref = None
+    for dtype in ("f64", "f32", "f16"):
+        ch, _ = make_channel(lbsep, wl, dtype, hist_cap=64)
+        ch.step(10)
+        wall, ev = time_steps(torch, ch, steps - 10)
+        cl = ch.read_cl()
+        entry = {"us_per_step": round(ev * 1e3 / (steps - 10), 2),
+                 "mlups": round(wl.nodes * (steps - 10) / wall / 1e6, 1),
+                 "cl": cl["cl"], "cl_tilde": cl["cl_tilde"]}
+        if ref is None:
+            ref = cl
+        else:
+            entry["cl_err_vs_f64"] = abs(cl["cl"] - ref["cl"])
+            entry["cl_tilde_err_vs_f64"] = abs(cl["cl_tilde"] - ref["cl_tilde"])
+        res[dtype] = entry
+        del ch
+    return res
+
+
 def adjoint_leg(torch, lbsep, steps: int):
     """dCL/d(theta, C_in, r) of the He-Ar 64 x 1280 channel (C_l 0.5, theta 2.5,
     Kn_out 0.1, FP64) over `steps` steps with checkpoints every 500: wall time of
@@ -200,6 +269,10 @@ def main():
                     help="skip the leg on the 512 x 10240 channel (above the last-level cache)")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-channel batched sweep leg")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-gradient leg")
+    ap.add_argument("--no-steady", action="store_true", help="skip the run of the channel to steady state")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the FP64 / FP32 / FP16 storage comparison on the 256 x 5120 channel")
+    ap.add_argument("--precision-steps", type=int, default=100000)
     ap.add_argument("--adjoint-steps", type=int, default=10000)
     ap.add_argument("--batch-steps", type=int, default=1000)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -299,6 +372,10 @@ def main():
         out["batch"] = batch_leg(torch, lbsep, args.dtype, args.batch_steps)
     if not args.no_adjoint:
         out["adjoint"] = adjoint_leg(torch, lbsep, args.adjoint_steps)
+    if not args.no_steady:
+        out["steady_state"] = steady_leg(torch, lbsep, w)
+    if not args.no_precision:
+        out["precision"] = precision_leg(torch, lbsep, args.precision_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, r, args.cpu_seconds)
         out["fp64_vs_oracle"] = oracle_parity(lbsep, w, r, 100)
