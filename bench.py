@@ -31,10 +31,18 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_1603_08221_amd", "csrc", n)
 
 
 def source_hash() -> str:
+    """Hash of the sweep kernel's source code with comments and blank lines
+    removed (a comment edit does not change the kernel the counters measured)."""
+    import re
+
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
-        with open(p, "rb") as fh:
-            h.update(fh.read())
+        with open(p, encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        lines = [ln.rstrip() for ln in text.splitlines() if ln.strip()]
+        h.update("\n".join(lines).encode())
     return h.hexdigest()[:16]
 
 

@@ -1,7 +1,8 @@
 // lbsep: fused sweep kernel and host implementation of include/lbsep.h.
 //
-// One time step = one launch of k_sweep<Mode, /*PULL=*/true, /*EVAL=*/false>:
-// every thread owns one node (x, j) and
+// One time step = one launch of k_sweep<Mode, /*PULL=*/true, /*EVAL=*/false, ...>
+// (or of k_sweep_batch for several channels at once). For each node (x, j)
+// the kernel
 //   1. pulls the 18 post-collision populations of the previous step from its
 //      neighbours (Eq. (MRT), pull form of the streaming),
 //   2. replaces the wall-crossing pulls by diffuse-bounce-back (Eqs. (bot),
@@ -38,17 +39,23 @@
 // state f'(t), the other the previous post-collision state f'(t-1) (or, right
 // after init / set_state, the pre-collision state f(t)).
 //
-// Work decomposition: a node is a lane pair, one lane per species. A tile
-// block is 4 wavefronts = 32 columns x (4 * rpt) rows; in each wavefront lanes
-// 0-31 hold species a and lanes 32-63 species b of the same 32 columns.
+// Work decomposition, two tile shapes with the same arithmetic per node
+// (chosen per channel, bitwise equal results):
+//   lane pair per node (SPLIT): a tile block is 4 wavefronts = 32 columns x
+//     (4 * rpt) rows; lanes 0-31 hold species a and lanes 32-63 species b of
+//     the same 32 columns; the relaxation-time work is split over the pair.
+//     Shortest chain per lane: for channels that leave the GPU mostly idle.
+//   one lane per node: 64 columns x (4 * rpt) rows, both species in one lane;
+//     fewest instructions per node: for channels that fill the GPU.
 // Lead blocks come first: 2 nend blocks own the inlet and outlet columns,
 // 64 rows each (they need whole-column sums of the inner layers before they
 // can rebuild the boundary nodes, so each end block sums the full column);
 // then nxt blocks reduce one column strip each of the previous step and one
 // block finishes the step before that; the lead count is rounded up to a
-// multiple of 8. Tiles follow, numbered so that each XCD (block id mod 8) takes a
-// contiguous run of tiles, vertically adjacent tiles first, which keeps the
-// halo rows of a tile in the same XCD's L2.
+// multiple of 8. Tiles follow, numbered so that each XCD (block id mod 8) takes
+// a contiguous run of tiles: down a column strip for lane-pair tiles, along a
+// row band for one-lane-per-node tiles (few, long open rows per plane on large
+// channels, whose stores are also non-temporal).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
