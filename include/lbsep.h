@@ -14,6 +14,10 @@
  *   - Sec. 3.2: diffuse-bounce-back walls (Eqs. (bot), (bot2), (taoq), (A12))
  *     and the extrapolation-correction pressure inlet/outlet (Eqs. (rho1), (rho2)).
  *
+ * Entry points: one channel (lbsep_init ... lbsep_destroy), batches of
+ * channels advanced by one launch per step (lbsep_batch_*), and the discrete
+ * adjoint of the step for gradients of CL (lbsep_adjoint_*).
+ *
  * Lattice units: delta_x = delta_t = 1, c_s^2 = 1/3, H = ny. Outlet pressure
  * P_out = 1/3 (so that n_out * m_min = 1); P_in = theta * P_out.
  *
