@@ -83,6 +83,7 @@ template <typename S, typename C, bool DEV>
 struct Mode {
   using St = S;  // storage type of a population
   using Ct = C;  // arithmetic type
+  using Pt = S __attribute__((ext_vector_type(2)));  // the two species of one population
   static constexpr bool kDev = DEV;
 };
 using ModeF64 = Mode<double, double, false>;
@@ -120,8 +121,12 @@ struct KBufs {
   long long part_stride;   // elements of one partials buffer: 4 * nrt * pitch
 };
 
+// State buffer layout: one plane per direction i, and in it the two species
+// of each node side by side, element ((i * ny + j) * pitch + x) * 2 + s. One
+// lane holding both species of a node then moves a direction with a single
+// 2-element access that stays aligned whatever the +-1 column shift.
 __device__ __forceinline__ long long pidx(const KParams& kp, int s, int i, int j, int x) {
-  return (long long)(s * 9 + i) * kp.plane + (long long)j * kp.pitch + x;
+  return ((long long)i * kp.plane + (long long)j * kp.pitch + x) * 2 + s;
 }
 
 // Population (s, i) at (j, x) of a state buffer as a wave-uniform plane base
@@ -129,15 +134,25 @@ __device__ __forceinline__ long long pidx(const KParams& kp, int s, int i, int j
 // through a scalar base register and one vector offset.
 template <typename S>
 __device__ __forceinline__ S* plane_at(const KParams& kp, S* base, int s, int i, int j, int x) {
-  const unsigned off = ((unsigned)j * (unsigned)kp.pitch + (unsigned)x) * (unsigned)sizeof(S);
-  char* pl = reinterpret_cast<char*>(base) + (size_t)(s * 9 + i) * (size_t)kp.plane * sizeof(S);
+  const unsigned off = (((unsigned)j * (unsigned)kp.pitch + (unsigned)x) * 2u + (unsigned)s) * (unsigned)sizeof(S);
+  char* pl = reinterpret_cast<char*>(base) + (size_t)i * (size_t)kp.plane * 2 * sizeof(S);
   return reinterpret_cast<S*>(pl + off);
 }
 template <typename S>
 __device__ __forceinline__ const S* plane_at(const KParams& kp, const S* base, int s, int i, int j, int x) {
-  const unsigned off = ((unsigned)j * (unsigned)kp.pitch + (unsigned)x) * (unsigned)sizeof(S);
-  const char* pl = reinterpret_cast<const char*>(base) + (size_t)(s * 9 + i) * (size_t)kp.plane * sizeof(S);
+  const unsigned off = (((unsigned)j * (unsigned)kp.pitch + (unsigned)x) * 2u + (unsigned)s) * (unsigned)sizeof(S);
+  const char* pl = reinterpret_cast<const char*>(base) + (size_t)i * (size_t)kp.plane * 2 * sizeof(S);
   return reinterpret_cast<const S*>(pl + off);
+}
+// Both species of population i at (j, x).
+template <class MD>
+__device__ __forceinline__ typename MD::Pt* pair_at(const KParams& kp, typename MD::St* base, int i, int j, int x) {
+  return reinterpret_cast<typename MD::Pt*>(plane_at(kp, base, 0, i, j, x));
+}
+template <class MD>
+__device__ __forceinline__ const typename MD::Pt* pair_at(const KParams& kp, const typename MD::St* base, int i, int j,
+                                                          int x) {
+  return reinterpret_cast<const typename MD::Pt*>(plane_at(kp, base, 0, i, j, x));
 }
 
 __device__ __forceinline__ double ref_rho(const KParams& kp, int s, int x) {
@@ -217,6 +232,79 @@ __device__ __forceinline__ void gather1(const KParams& kp, const typename MD::St
       f[4] = v0;
       f[7] = v1;
       f[8] = v2;
+    }
+  }
+}
+
+// Both species at node (x, j), one 2-element access per direction: the same
+// values as gather1 for s = 0 and s = 1.
+template <class MD, bool PULL>
+__device__ __forceinline__ void gather_pair(const KParams& kp, const typename MD::St* __restrict__ src, int x, int j,
+                                            typename MD::Ct fa[9], typename MD::Ct fb[9]) {
+  using C = typename MD::Ct;
+  if (!PULL) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const typename MD::Pt v = *pair_at<MD>(kp, src, i, j, x);
+      fa[i] = C(v[0]);
+      fb[i] = C(v[1]);
+    }
+    return;
+  }
+  int xm = x - 1, xp = x + 1, jm = j - 1, jp = j + 1;
+  if (kp.flags & LBSEP_PERIODIC_X) {
+    if (xm < 0) xm += kp.nx;
+    if (xp >= kp.nx) xp -= kp.nx;
+  } else {
+    if (xm < 0) xm = 0;
+    if (xp >= kp.nx) xp = kp.nx - 1;
+  }
+  bool bot = false, top = false;
+  if (kp.flags & LBSEP_PERIODIC_Y) {
+    if (jm < 0) jm += kp.ny;
+    if (jp >= kp.ny) jp -= kp.ny;
+  } else {
+    bot = (j == 0);
+    top = (j == kp.ny - 1);
+    if (bot) jm = j;
+    if (top) jp = j;
+  }
+  const int sx[9] = {x, xm, x, xp, x, xm, xp, xp, xm};
+  const int sy[9] = {j, j, jm, j, jp, jm, jm, jp, jp};
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const typename MD::Pt v = *pair_at<MD>(kp, src, i, sy[i], sx[i]);
+    fa[i] = C(v[0]);
+    fb[i] = C(v[1]);
+    if (MD::kDev && (i == 1 || i == 3 || i >= 5)) {
+      fa[i] += C(kp.corr[0][i]);
+      fb[i] += C(kp.corr[1][i]);
+    }
+  }
+  if (bot || top) {  // the DBB map of gather1, both species
+    const C r = C(kp.r);
+    const C q = C(1) - r;
+    const int o0 = bot ? 4 : 2, o1 = bot ? 7 : 5, o2 = bot ? 8 : 6;
+    const typename MD::Pt w0 = *pair_at<MD>(kp, src, o0, j, x);
+    const typename MD::Pt w1 = *pair_at<MD>(kp, src, o1, j, x);
+    const typename MD::Pt w2 = *pair_at<MD>(kp, src, o2, j, x);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const C l0 = C(w0[s]), l1 = C(w1[s]), l2 = C(w2[s]);
+      const C F = (l0 + l1) + l2;
+      const C v0 = r * (C(2.0 / 3.0) * F) + q * l0;
+      const C v1 = r * (F * C(1.0 / 6.0)) + q * l1;
+      const C v2 = r * (F * C(1.0 / 6.0)) + q * l2;
+      C* f = s ? fb : fa;
+      if (bot) {
+        f[2] = v0;
+        f[5] = v1;
+        f[6] = v2;
+      } else {
+        f[4] = v0;
+        f[7] = v1;
+        f[8] = v2;
+      }
     }
   }
 }
@@ -335,13 +423,13 @@ __device__ __forceinline__ void process_node(const KParams& kp, int x, int j, ty
   collide_species<C>(fb, cb, rho_b, ux, uy, C(kp.rc.s[1]), we, weps, wd, wq, ws);
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
-    if (NT) {  // the next read of these lines is a whole sweep away: bypass the caches
-      __builtin_nontemporal_store(typename MD::St(fa[i]), plane_at(kp, dst, 0, i, j, x));
-      __builtin_nontemporal_store(typename MD::St(fb[i]), plane_at(kp, dst, 1, i, j, x));
-    } else {
-      *plane_at(kp, dst, 0, i, j, x) = typename MD::St(fa[i]);
-      *plane_at(kp, dst, 1, i, j, x) = typename MD::St(fb[i]);
-    }
+    typename MD::Pt v;
+    v[0] = typename MD::St(fa[i]);
+    v[1] = typename MD::St(fb[i]);
+    if (NT)  // the next read of these lines is a whole sweep away: bypass the caches
+      __builtin_nontemporal_store(v, pair_at<MD>(kp, dst, i, j, x));
+    else
+      *pair_at<MD>(kp, dst, i, j, x) = v;
   }
 }
 
@@ -690,8 +778,7 @@ __device__ __forceinline__ void sweep_block(const KParams& kp, const KBufs& kb,
       const int j = by * (kTY * kp.rpt) + r * kTY + ty;
       if (xin && j < kp.ny) {
         C fa[9], fb[9];
-        gather1<MD, PULL>(kp, src, 0, x, j, fa);
-        gather1<MD, PULL>(kp, src, 1, x, j, fb);
+        gather_pair<MD, PULL>(kp, src, x, j, fa, fb);
         process_node<MD, EVAL, NT>(kp, x, j, fa, fb, dst, mom, fraw, ffull, acc);
       }
     }
@@ -841,7 +928,7 @@ __global__ void k_zero_u32(unsigned* p, int n) {
   if (i < n) p[i] = 0u;
 }
 
-// Dense [2*9*ny][nx] raw state -> pitched buffer.
+// Dense [2][9][ny][nx] raw state -> state buffer layout.
 template <typename S>
 __global__ void k_copy_in(KParams kp, const S* __restrict__ dense, S* __restrict__ f) {
   const long long n = 18LL * kp.ny * kp.nx;
@@ -849,7 +936,10 @@ __global__ void k_copy_in(KParams kp, const S* __restrict__ dense, S* __restrict
        e += (long long)gridDim.x * blockDim.x) {
     const long long row = e / kp.nx;
     const int x = int(e - row * kp.nx);
-    f[row * kp.pitch + x] = dense[e];
+    const int si = int(row / kp.ny);  // s * 9 + i
+    const int j = int(row - (long long)si * kp.ny);
+    const int s = si / 9, i = si - 9 * s;
+    f[pidx(kp, s, i, j, x)] = dense[e];
   }
 }
 
@@ -862,9 +952,10 @@ __global__ void k_set_pop(KParams kp, const double* __restrict__ dense, typename
     const long long row = e / kp.nx;
     const int x = int(e - row * kp.nx);
     const int si = int(row / kp.ny);  // s * 9 + i
+    const int j = int(row - (long long)si * kp.ny);
     const int s = si / 9, i = si - 9 * s;
     const double v = MD::kDev ? dense[e] - kp.wa[s][i] * ref_rho(kp, s, x) : dense[e];
-    f[row * kp.pitch + x] = typename MD::St(v);
+    f[pidx(kp, s, i, j, x)] = typename MD::St(v);
   }
 }
 
@@ -897,6 +988,9 @@ bool validate(const lbsep_params* p, std::string& why) {
   if (p->nx < (px ? 1 : 6)) return why = "nx must be >= 6 (>= 1 with LBSEP_PERIODIC_X)", false;
   if (p->ny < 2) return why = "ny must be >= 2", false;
   if ((long long)p->nx * p->ny > (1LL << 31)) return why = "nx * ny too large", false;
+  if (p->dtype >= LBSEP_F64 && p->dtype <= LBSEP_F16 &&
+      (long long)p->ny * (long long)align_up((size_t)p->nx, kTX) * 2 * (long long)elem_bytes(p->dtype) >= (1LL << 32))
+    return why = "channel too large: one direction plane must stay below 4 GiB", false;
   if (p->ny > 64 * kMaxEnd) return why = "ny must be <= " + std::to_string(64 * kMaxEnd), false;
   if (!(p->m_a > 0) || !(p->m_b >= p->m_a) || !std::isfinite(p->m_b))
     return why = "need 0 < m_a <= m_b (species a is the light one)", false;
