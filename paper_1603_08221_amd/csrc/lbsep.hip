@@ -1023,8 +1023,8 @@ Layout make_layout(const lbsep_params* p) {
     L.split = true;
   else if (p->tile_mode == LBSEP_TILE_NODE)
     L.split = false;
-  else  // measured crossovers: FP64 (longer per-node chain) between 14k and 82k nodes, FP32/FP16 above 1.3 M
-    L.split = (long long)p->nx * p->ny <= (p->dtype == LBSEP_F64 ? (1LL << 15) : (1LL << 19));
+  else  // measured crossover, every dtype: between 61k and 82k nodes
+    L.split = (long long)p->nx * p->ny <= (1LL << 16);
   const int cols = L.split ? 32 : 64;
   L.ntx = (p->nx + cols - 1) / cols;
   // rows per thread: the largest of 4, 2, 1 that still gives >= 2048 tiles

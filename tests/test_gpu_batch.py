@@ -15,7 +15,7 @@ from gpu_helpers import assert_cl, assert_moments, oracle_params, r_of
 pytestmark = pytest.mark.gpu
 
 # uneven members: lane-pair tiles (small) and one-lane-per-node tiles (the
-# 132 x 4000 channel has more than 2^19 nodes), ragged edges in x and y
+# 132 x 4000 channel has more than 2^16 nodes), ragged edges in x and y
 MEMBERS = [
     Workload("b0", 80, 8, *HE_AR, 0.5, 0.5, 2.0, 0.1, 0),
     Workload("b1", 333, 24, *NE_AR, 0.3, 0.3, 3.0, 0.05, 0),
