@@ -32,9 +32,11 @@
 // same formulas on d (f0 is at rest and linear in x); the collision uses
 // rho - rho0 for the density terms.
 //
-// Layout in HBM (structure of arrays): population (s, i) of node (x, j) of a
-// state buffer is at element ((s * 9 + i) * ny + j) * pitch + x, pitch =
-// nx rounded up to 64, so a wavefront reads 64 consecutive x of one row.
+// Layout in HBM (tile-blocked): each row is cut into blocks of 64 columns, and
+// a block stores its nine directions one after the other, each as 64 nodes
+// with the two species side by side (see pidx). A wavefront working on the 64
+// columns of one block of one row reads and writes one contiguous 64-node run
+// per direction, and the nine runs of a block are adjacent in memory.
 // Two state buffers alternate; the one written last holds the post-collision
 // state f'(t), the other the previous post-collision state f'(t-1) (or, right
 // after init / set_state, the pre-collision state f(t)).
@@ -54,8 +56,9 @@
 // block finishes the step before that; the lead count is rounded up to a
 // multiple of 8. Tiles follow, numbered so that each XCD (block id mod 8) takes
 // a contiguous run of tiles: down a column strip for lane-pair tiles, along a
-// row band for one-lane-per-node tiles (few, long open rows per plane on large
-// channels, whose stores are also non-temporal).
+// row band for one-lane-per-node tiles (on large channels consecutive tiles
+// then touch adjacent blocks of the same few rows; their stores are also
+// non-temporal).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -98,7 +101,7 @@ struct KParams {
   int tiles, chunk;     // nxt * nrt, ceil(tiles / 8)
   int lead;             // lead blocks (multiple of 8) before the first tile
   int nend;             // blocks per inlet/outlet column (64 rows each)
-  long long plane;      // ny * pitch
+  long long row;        // elements per row of a state buffer: 18 * pitch
   unsigned flags;
   double r;             // DBB coefficient
   double rho_bc[2][2];  // [inlet/outlet][species] densities of Eq. (rho2)
@@ -121,38 +124,44 @@ struct KBufs {
   long long part_stride;   // elements of one partials buffer: 4 * nrt * pitch
 };
 
-// State buffer layout: one plane per direction i, and in it the two species
-// of each node side by side, element ((i * ny + j) * pitch + x) * 2 + s. One
-// lane holding both species of a node then moves a direction with a single
-// 2-element access that stays aligned whatever the +-1 column shift.
+// State buffer layout: row j holds pitch / 64 blocks of 64 columns; block b
+// holds direction 0, then 1, ... 8, each as 64 consecutive nodes with the two
+// species of a node side by side:
+//   element j * 18 pitch + ((b * 9 + i) * 64 + (x mod 64)) * 2 + s,  b = x / 64.
+// One lane holding both species of a node moves a direction with a single
+// 2-element access that stays aligned whatever the +-1 column shift; the
+// nine direction runs and the write-back of a block are contiguous.
+// element offset of (s = 0, i = 0) of column x inside its row
+__device__ __forceinline__ unsigned col_off(int x) {
+  return (((unsigned)x >> 6) * 576u + ((unsigned)x & 63u)) * 2u;
+}
 __device__ __forceinline__ long long pidx(const KParams& kp, int s, int i, int j, int x) {
-  return ((long long)i * kp.plane + (long long)j * kp.pitch + x) * 2 + s;
+  return (long long)j * kp.row + i * 128 + s + col_off(x);
 }
 
-// Population (s, i) at (j, x) of a state buffer as a wave-uniform plane base
-// plus a 32-bit byte offset inside the plane, so loads and stores address
-// through a scalar base register and one vector offset.
+// Population (s, i) at (j, x) of a state buffer as a base for (row, direction,
+// species), wave-uniform where j is, plus a 32-bit byte offset of the column
+// inside the row: loads and stores then address through a scalar base and one
+// of three column offsets (x - 1, x, x + 1).
 template <typename S>
-__device__ __forceinline__ S* plane_at(const KParams& kp, S* base, int s, int i, int j, int x) {
-  const unsigned off = (((unsigned)j * (unsigned)kp.pitch + (unsigned)x) * 2u + (unsigned)s) * (unsigned)sizeof(S);
-  char* pl = reinterpret_cast<char*>(base) + (size_t)i * (size_t)kp.plane * 2 * sizeof(S);
-  return reinterpret_cast<S*>(pl + off);
+__device__ __forceinline__ S* pop_at(const KParams& kp, S* base, int s, int i, int j, int x) {
+  S* rw = base + ((long long)j * kp.row + (i * 128 + s));
+  return reinterpret_cast<S*>(reinterpret_cast<char*>(rw) + col_off(x) * (unsigned)sizeof(S));
 }
 template <typename S>
-__device__ __forceinline__ const S* plane_at(const KParams& kp, const S* base, int s, int i, int j, int x) {
-  const unsigned off = (((unsigned)j * (unsigned)kp.pitch + (unsigned)x) * 2u + (unsigned)s) * (unsigned)sizeof(S);
-  const char* pl = reinterpret_cast<const char*>(base) + (size_t)i * (size_t)kp.plane * 2 * sizeof(S);
-  return reinterpret_cast<const S*>(pl + off);
+__device__ __forceinline__ const S* pop_at(const KParams& kp, const S* base, int s, int i, int j, int x) {
+  const S* rw = base + ((long long)j * kp.row + (i * 128 + s));
+  return reinterpret_cast<const S*>(reinterpret_cast<const char*>(rw) + col_off(x) * (unsigned)sizeof(S));
 }
 // Both species of population i at (j, x).
 template <class MD>
 __device__ __forceinline__ typename MD::Pt* pair_at(const KParams& kp, typename MD::St* base, int i, int j, int x) {
-  return reinterpret_cast<typename MD::Pt*>(plane_at(kp, base, 0, i, j, x));
+  return reinterpret_cast<typename MD::Pt*>(pop_at(kp, base, 0, i, j, x));
 }
 template <class MD>
 __device__ __forceinline__ const typename MD::Pt* pair_at(const KParams& kp, const typename MD::St* base, int i, int j,
                                                           int x) {
-  return reinterpret_cast<const typename MD::Pt*>(plane_at(kp, base, 0, i, j, x));
+  return reinterpret_cast<const typename MD::Pt*>(pop_at(kp, base, 0, i, j, x));
 }
 
 __device__ __forceinline__ double ref_rho(const KParams& kp, int s, int x) {
@@ -177,7 +186,7 @@ __device__ __forceinline__ void gather1(const KParams& kp, const typename MD::St
   using C = typename MD::Ct;
   if (!PULL) {
 #pragma unroll
-    for (int i = 0; i < 9; ++i) f[i] = C(*plane_at(kp, src, s, i, j, x));
+    for (int i = 0; i < 9; ++i) f[i] = C(*pop_at(kp, src, s, i, j, x));
     return;
   }
   int xm = x - 1, xp = x + 1, jm = j - 1, jp = j + 1;
@@ -204,7 +213,7 @@ __device__ __forceinline__ void gather1(const KParams& kp, const typename MD::St
   const int sy[9] = {j, j, jm, j, jp, jm, jm, jp, jp};
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
-    f[i] = C(*plane_at(kp, src, s, i, sy[i], sx[i]));
+    f[i] = C(*pop_at(kp, src, s, i, sy[i], sx[i]));
     if (MD::kDev && (i == 1 || i == 3 || i >= 5)) f[i] += C(kp.corr[s][i]);
   }
   if (bot || top) {
@@ -217,9 +226,9 @@ __device__ __forceinline__ void gather1(const KParams& kp, const typename MD::St
     const C r = C(kp.r);
     const C q = C(1) - r;
     const int o0 = bot ? 4 : 2, o1 = bot ? 7 : 5, o2 = bot ? 8 : 6;  // leaving
-    const C l0 = C(*plane_at(kp, src, s, o0, j, x));
-    const C l1 = C(*plane_at(kp, src, s, o1, j, x));
-    const C l2 = C(*plane_at(kp, src, s, o2, j, x));
+    const C l0 = C(*pop_at(kp, src, s, o0, j, x));
+    const C l1 = C(*pop_at(kp, src, s, o1, j, x));
+    const C l2 = C(*pop_at(kp, src, s, o2, j, x));
     const C F = (l0 + l1) + l2;
     const C v0 = r * (C(2.0 / 3.0) * F) + q * l0;
     const C v1 = r * (F * C(1.0 / 6.0)) + q * l1;
@@ -506,7 +515,7 @@ __device__ __forceinline__ void process_pair(const KParams& kp, int x, int j, in
   acc[0] += r_own * kp.rc.inv_m[s];
   acc[1] += double(px);
 #pragma unroll
-  for (int i = 0; i < 9; ++i) *plane_at(kp, dst, s, i, j, x) = typename MD::St(f[i]);
+  for (int i = 0; i < 9; ++i) *pop_at(kp, dst, s, i, j, x) = typename MD::St(f[i]);
 }
 
 // Column sums of one strip (64 columns) of level `step`: add the row-tile
@@ -727,8 +736,8 @@ __device__ __forceinline__ void sweep_block(const KParams& kp, const KBufs& kb,
   const int lin = xcd * kp.chunk + k;
   if (lin >= kp.tiles) return;
   // consecutive tiles of an XCD run down a column strip (small channels: the
-  // strip's rows stay together) or along a row band (large channels: the
-  // concurrently open rows of every plane stay few and long)
+  // strip's rows stay together) or along a row band (large channels: an
+  // XCD's concurrent tiles read and write adjacent blocks of a few rows)
   int bx, by;
   if (kp.flags & kRowMajorTiles) {
     by = lin / kp.ntx;
@@ -738,7 +747,9 @@ __device__ __forceinline__ void sweep_block(const KParams& kp, const KBufs& kb,
     by = lin - bx * kp.nrt;
   }
   const int lane = threadIdx.x & (kTX - 1);
-  const int ty = threadIdx.x / kTX;
+  // the wave's row within the tile, uniform across the wave: row bases of the
+  // state buffers then stay in scalar registers
+  const int ty = __builtin_amdgcn_readfirstlane(threadIdx.x / kTX);
   if (SPLIT) {
     // 32 columns x (4 rpt) rows; lanes 0-31 hold species a, 32-63 species b
     const int s = lane >> 5;
@@ -989,8 +1000,8 @@ bool validate(const lbsep_params* p, std::string& why) {
   if (p->ny < 2) return why = "ny must be >= 2", false;
   if ((long long)p->nx * p->ny > (1LL << 31)) return why = "nx * ny too large", false;
   if (p->dtype >= LBSEP_F64 && p->dtype <= LBSEP_F16 &&
-      (long long)p->ny * (long long)align_up((size_t)p->nx, kTX) * 2 * (long long)elem_bytes(p->dtype) >= (1LL << 32))
-    return why = "channel too large: one direction plane must stay below 4 GiB", false;
+      18LL * (long long)align_up((size_t)p->nx, kTX) * (long long)elem_bytes(p->dtype) >= (1LL << 32))
+    return why = "channel too long: one row of a state buffer must stay below 4 GiB", false;
   if (p->ny > 64 * kMaxEnd) return why = "ny must be <= " + std::to_string(64 * kMaxEnd), false;
   if (!(p->m_a > 0) || !(p->m_b >= p->m_a) || !std::isfinite(p->m_b))
     return why = "need 0 < m_a <= m_b (species a is the light one)", false;
@@ -1239,7 +1250,7 @@ int lbsep_init(const lbsep_params* p, void* dev_ws, size_t ws_bytes, void* hip_s
   kp.chunk = L.chunk;
   kp.lead = L.lead;
   kp.nend = L.nend;
-  kp.plane = (long long)p->ny * L.pitch;
+  kp.row = 18LL * L.pitch;
   kp.flags = p->flags | (h->L.split ? 0u : kRowMajorTiles);
   kp.r = p->dbb_r;
   kp.cl_in = p->cl_in;

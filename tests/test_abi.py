@@ -73,11 +73,13 @@ def test_init_rejects_unaligned_or_small_workspace_before_any_device_call():
     assert "workspace too small" in lbsep.last_error()
 
 
-def test_channel_whose_direction_plane_exceeds_4_gib_is_rejected():
-    # 2048 rows x 131072 columns x 2 species x 8 bytes = 4 GiB per direction plane
+def test_channel_whose_state_row_exceeds_4_gib_is_rejected():
+    # 2^25 columns x 9 directions x 2 species x 8 bytes = 4.5 GiB per row
     with pytest.raises(lbsep.LbsepError, match="4 GiB"):
-        lbsep.workspace_bytes(_params(nx=131072, ny=2048, dtype="f64"))
-    assert lbsep.workspace_bytes(_params(nx=131072, ny=2048, dtype="f32")) > 0
+        lbsep.workspace_bytes(_params(nx=1 << 25, ny=4, dtype="f64"))
+    assert lbsep.workspace_bytes(_params(nx=1 << 25, ny=4, dtype="f32")) > 0
+    # the former per-direction-plane limit no longer applies
+    assert lbsep.workspace_bytes(_params(nx=131072, ny=2048, dtype="f64")) > 0
 
 
 def test_periodic_x_allows_short_channels():
