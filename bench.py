@@ -97,8 +97,9 @@ def batch_leg(torch, lbsep, dtype: str, steps: int):
     tuned = autotune.tune(ps)
     stream = torch.cuda.Stream()
     chans = []
-    for p, m in zip(ps, tuned["modes"]):
+    for p, m, rows in zip(ps, tuned["modes"], tuned["rows"]):
         p.tile_mode = m
+        p.tile_rows = rows
         chans.append(lbsep.Channel(p, device="cuda:0", stream=stream))
     b = lbsep.Batch(chans)
     b.capture(100)

@@ -3,12 +3,15 @@
 The sweep kernel maps nodes to lanes either as a lane pair per node (species
 split; shortest chain per lane, pays when a channel leaves the GPU mostly idle)
 or as one lane per node (fewest instructions per node, pays when the work
-fills the GPU several times). Which one is faster depends on the whole launch:
-a small channel alone wants the lane pair, the same channel inside a batch that
-fills the GPU wants one lane per node. The tuner times candidate assignments on
-scratch channels (fresh workspaces, same shapes and parameters, so the caller's
-states are never touched) and returns the fastest. Results are bitwise
-independent of the choice, so the choice is purely a speed decision.
+fills the GPU several times), and each wavefront of a tile walks 1, 2 or 4 rows
+(more rows: fewer row-tile partial sums, less parallelism). Which shape is
+faster depends on the whole launch: a small channel alone wants the lane pair
+and one row, the same channel inside a batch that fills the GPU wants one lane
+per node and four rows. The tuner times candidate assignments on scratch
+channels (fresh workspaces, same shapes and parameters, so the caller's states
+are never touched) and returns the fastest. The states are bitwise independent
+of the choice (CL sums may differ in the last bits with the rows), so the
+choice is a speed decision.
 
 Choices can be cached in a JSON file keyed by the device name, the dtype and
 the member shapes.
@@ -28,6 +31,7 @@ SPLIT, NODE = lbsep.TILE_SPLIT, lbsep.TILE_NODE
 
 def _key(params_list, device) -> str:
     h = hashlib.sha256()
+    h.update(b"tile modes and rows")
     h.update(torch.cuda.get_device_name(device).encode())
     for p in params_list:
         h.update(f"{p.nx},{p.ny},{p.dtype},{p.flags}".encode())
@@ -35,27 +39,35 @@ def _key(params_list, device) -> str:
 
 
 def candidates(params_list):
-    """Tile-mode assignments to try: all lane pairs, all one-lane-per-node, and
-    size thresholds in between (lane pairs for members up to T nodes)."""
+    """Assignments to try, {name: {"modes": [...], "rows": [...]}} per member:
+    tile modes all lane pairs, all one-lane-per-node, and size thresholds in
+    between (lane pairs for members up to T nodes), each with the rows chosen
+    by size (0) and with four rows per wavefront."""
     sizes = [p.nx * p.ny for p in params_list]
-    out = {"split": [SPLIT] * len(sizes), "node": [NODE] * len(sizes)}
+    modes = {"split": [SPLIT] * len(sizes), "node": [NODE] * len(sizes)}
     for t in (1 << 14, 1 << 16, 1 << 18):
         a = [SPLIT if n <= t else NODE for n in sizes]
-        if a not in out.values():
-            out[f"split<={t}"] = a
+        if a not in modes.values():
+            modes[f"split<={t}"] = a
+    out = {}
+    for name, m in modes.items():
+        out[name] = {"modes": m, "rows": [0] * len(sizes)}
+        out[name + ",rows4"] = {"modes": m, "rows": [4] * len(sizes)}
     return out
 
 
-def _with_mode(p, mode):
+def _with_shape(p, mode, rows):
     q = lbsep.Params.from_buffer_copy(p)
     q.tile_mode = mode
+    q.tile_rows = rows
     q.hist_cap = 16
     return q
 
 
-def _time_batch(params_list, modes, device, trial_steps, warmup):
+def _time_batch(params_list, modes, rows, device, trial_steps, warmup):
     stream = torch.cuda.Stream(device)
-    chans = [lbsep.Channel(_with_mode(p, m), device=device, stream=stream) for p, m in zip(params_list, modes)]
+    chans = [lbsep.Channel(_with_shape(p, m, r), device=device, stream=stream)
+             for p, m, r in zip(params_list, modes, rows)]
     b = lbsep.Batch(chans) if len(chans) > 1 else None
     step = b.step if b is not None else chans[0].step
     step(warmup)
@@ -75,8 +87,9 @@ def _time_batch(params_list, modes, device, trial_steps, warmup):
 
 
 def tune(params_list, device="cuda:0", trial_steps=40, warmup=10, cache_file=None):
-    """Fastest tile-mode assignment for sweeping `params_list` together (one
-    channel: alone). Returns {"name", "modes", "ms_per_step", "timings"}."""
+    """Fastest tile assignment for sweeping `params_list` together (one
+    channel: alone). Returns {"name", "modes", "rows", "ms_per_step",
+    "timings"}: set each member's tile_mode and tile_rows from modes and rows."""
     params_list = list(params_list)
     key = _key(params_list, device)
     cache = {}
@@ -86,10 +99,12 @@ def tune(params_list, device="cuda:0", trial_steps=40, warmup=10, cache_file=Non
         if key in cache:
             return cache[key]
     timings = {}
-    for name, modes in candidates(params_list).items():
-        timings[name] = _time_batch(params_list, modes, device, trial_steps, warmup)
+    cands = candidates(params_list)
+    for name, c in cands.items():
+        timings[name] = _time_batch(params_list, c["modes"], c["rows"], device, trial_steps, warmup)
     best = min(timings, key=timings.get)
-    out = {"name": best, "modes": candidates(params_list)[best], "ms_per_step": timings[best], "timings": timings}
+    out = {"name": best, "modes": cands[best]["modes"], "rows": cands[best]["rows"], "ms_per_step": timings[best],
+           "timings": timings}
     if cache_file:
         cache[key] = out
         tmp = cache_file + ".tmp"

@@ -1018,6 +1018,8 @@ bool validate(const lbsep_params* p, std::string& why) {
     return why = "dtype must be LBSEP_F64, LBSEP_F32 or LBSEP_F16", false;
   if (p->hist_cap < 1) return why = "hist_cap must be >= 1", false;
   if (p->tile_mode < LBSEP_TILE_AUTO || p->tile_mode > LBSEP_TILE_NODE) return why = "bad tile_mode", false;
+  if (p->tile_rows != 0 && p->tile_rows != 1 && p->tile_rows != 2 && p->tile_rows != 4)
+    return why = "tile_rows must be 0, 1, 2 or 4", false;
   return true;
 }
 
@@ -1038,13 +1040,19 @@ Layout make_layout(const lbsep_params* p) {
     L.split = (long long)p->nx * p->ny <= (1LL << 16);
   const int cols = L.split ? 32 : 64;
   L.ntx = (p->nx + cols - 1) / cols;
-  // rows per thread: the largest of 4, 2, 1 that still gives >= 2048 tiles
+  // rows per thread: as asked, else the largest of 4, 2, 1 that still gives
+  // >= 2048 tiles (a channel alone needs the parallelism; in a batch that fills
+  // the GPU, 4 rows cut the row-tile partial sums to a quarter)
   L.rpt = 1;
-  for (int r : {4, 2}) {
-    const int nrt = (p->ny + kTY * r - 1) / (kTY * r);
-    if ((long long)L.ntx * nrt >= 2048) {
-      L.rpt = r;
-      break;
+  if (p->tile_rows > 0) {
+    L.rpt = p->tile_rows;
+  } else {
+    for (int r : {4, 2}) {
+      const int nrt = (p->ny + kTY * r - 1) / (kTY * r);
+      if ((long long)L.ntx * nrt >= 2048) {
+        L.rpt = r;
+        break;
+      }
     }
   }
   L.nrt = (p->ny + kTY * L.rpt - 1) / (kTY * L.rpt);

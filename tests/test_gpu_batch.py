@@ -152,15 +152,16 @@ def test_autotuner_picks_a_candidate_and_caches_it(tmp_path):
     cache = str(tmp_path / "tune.json")
     got = autotune.tune(ps, trial_steps=5, warmup=2, cache_file=cache)
     cands = autotune.candidates(ps)
-    assert got["name"] in cands and got["modes"] == cands[got["name"]]
+    assert got["name"] in cands and cands[got["name"]] == {"modes": got["modes"], "rows": got["rows"]}
+    assert any(c["rows"] == [4] * len(ps) for c in cands.values())
     assert got["ms_per_step"] == min(got["timings"].values()) > 0
     again = autotune.tune(ps, trial_steps=5, warmup=2, cache_file=cache)
     assert again == got  # served from the cache
     # the tuned assignment runs the same arithmetic: a tuned batch equals the default one
     tuned = []
-    for w, m in zip(MEMBERS, got["modes"]):
+    for w, m, rows in zip(MEMBERS, got["modes"], got["rows"]):
         p = lbsep.make_params(w.nx, w.ny, w.m_a, w.m_b, w.cl_in, w.cl_out, w.theta, w.kn_out, r_of(w),
-                              dtype="f32", hist_cap=512, tile_mode=m)
+                              dtype="f32", hist_cap=512, tile_mode=m, tile_rows=rows)
         tuned.append(lbsep.Channel(p, device="cuda:0"))
     plain = _make(MEMBERS, "f32")
     lbsep.Batch(tuned).step(40)

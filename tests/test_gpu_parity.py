@@ -341,6 +341,28 @@ def test_tile_shapes_give_identical_results(dtype, shape):
     assert out[0][1]["cl"] == out[1][1]["cl"] and np.array_equal(out[0][1]["profile"], out[1][1]["profile"])
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_tile_rows_give_identical_states(dtype):
+    """Wavefronts walking 1, 2 or 4 rows of a tile, in both tile shapes, update
+    every node the same way: the states agree bitwise. CL and the C_l profile
+    come from column sums associated per row tile, so they agree to rounding
+    (24 rows: a ragged last row tile for 2 and 4 rows per wavefront)."""
+    w = Workload("rows", 517, 24, *NE_AR, 0.3, 0.7, 3.0, 0.05, 300)
+    r = r_of(w)
+    out = []
+    for mode in (lbsep.TILE_SPLIT, lbsep.TILE_NODE):
+        for rows in (1, 2, 4):
+            ch = channel(w, r, dtype=dtype, tile_mode=mode, tile_rows=rows)
+            ch.step(300)
+            out.append(((mode, rows), ch.get_state(), ch.read_cl(profile=True)))
+            del ch
+    ref_state, ref_cl = out[0][1], out[0][2]
+    for shape, state, cl in out[1:]:
+        assert torch.equal(state, ref_state), shape
+        assert abs(cl["cl"] - ref_cl["cl"]) <= 1e-13 * abs(ref_cl["cl"]), shape
+        np.testing.assert_allclose(cl["profile"], ref_cl["profile"], rtol=1e-13, atol=0, err_msg=str(shape))
+
+
 @pytest.mark.parametrize("mode", [1, 2])
 def test_fp64_parity_each_tile_shape(mode):
     w = CONFIGS["he_ar_8x80"].with_(nx=200, ny=20)
