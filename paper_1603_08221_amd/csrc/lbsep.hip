@@ -532,10 +532,28 @@ __device__ void strip_reduce(const KParams& kp, const KBufs& kb, int bx, long lo
   if (x < kp.nx) {
     if (!px && (x == 0 || x == kp.nx - 1)) {
       const int e = x == 0 ? 0 : 1;
-      for (int blk = 0; blk < kp.nend; ++blk) v += kb.endsum[((par * 2 + e) * kMaxEnd + blk) * 4 + q];
+      const double* p = kb.endsum + (par * 2 + e) * kMaxEnd * 4 + q;
+      for (int b0 = 0; b0 < kp.nend; b0 += 8) {
+        double w[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) w[k] = b0 + k < kp.nend ? p[(b0 + k) * 4] : 0.0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          if (b0 + k < kp.nend) v += w[k];
+      }
     } else {
+      // loads issued 16 at a time (the partials were just written by other
+      // XCDs, so each one is a trip past this XCD's L2); the additions keep
+      // their sequential order
       const double* p = kb.partials + par * kb.part_stride + (long long)q * kp.nrt * kp.pitch + x;
-      for (int by = 0; by < kp.nrt; ++by) v += p[(long long)by * kp.pitch];
+      for (int b0 = 0; b0 < kp.nrt; b0 += 16) {
+        double w[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) w[k] = b0 + k < kp.nrt ? p[(long long)(b0 + k) * kp.pitch] : 0.0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+          if (b0 + k < kp.nrt) v += w[k];
+      }
     }
     kb.colsum[(long long)q * kp.pitch + x] = v;
   }
