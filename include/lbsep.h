@@ -180,6 +180,13 @@ int lbsep_set_state(lbsep_channel* ch, const void* dev_src, int64_t t);
  * Enqueues only. */
 int lbsep_get_populations(lbsep_channel* ch, double* dev_dst);
 
+/* Write the current post-collision populations f'(t) = C(f(t)) in double
+ * (2 * 9 * ny * nx doubles, layout above) to device memory dev_dst: the state
+ * the next step streams, as the last sweep (or set / init) computed it. For
+ * deviation storage the stored value plus f0 of the node's column. Sec. 3.1,
+ * Eq. (MRT): the collision's output before streaming. Enqueues only. */
+int lbsep_get_post_collision(lbsep_channel* ch, double* dev_dst);
+
 /* Replace the state by the populations f given in double (device, layout
  * above), converted to the storage type, at time level t >= 0, and record
  * its diagnostics. Enqueues only. */
@@ -257,10 +264,13 @@ void lbsep_batch_destroy(lbsep_batch* b);
 size_t lbsep_adjoint_workspace_bytes(const lbsep_params* p);
 
 /* lam_out = (d f(t+1) / d f(t))^T lam_next at the pre-collision state f_t;
- * dparams += lam_next . d f(t+1) / d(theta, C_in, r) at fixed f_t. lam_out
- * must not alias f_t or lam_next. */
-int lbsep_adjoint_step(lbsep_channel* ch, const double* f_t, const double* lam_next, double* lam_out,
-                       double* dparams, void* adj_ws, size_t adj_ws_bytes);
+ * dparams += lam_next . d f(t+1) / d(theta, C_in, r) at fixed f_t.
+ *   f_post : C(f_t), the post-collision populations of the same level as
+ *            written by lbsep_get_post_collision, or NULL: the library then
+ *            recomputes C(f_t) in the adjoint workspace (one more launch).
+ * lam_out must not alias f_t, f_post or lam_next. */
+int lbsep_adjoint_step(lbsep_channel* ch, const double* f_t, const double* f_post, const double* lam_next,
+                       double* lam_out, double* dparams, void* adj_ws, size_t adj_ws_bytes);
 
 /* Seed of J = CL (Eq. (CL)) at the pre-collision state f_T: lam_out = dCL/df_T
  * (nonzero on the column of the smallest C_l only, R16) and dparams[1] +=

@@ -6,9 +6,9 @@ steps, the CL seed and the initial-state term all run in the HIP library
 (``lbsep_step``, ``lbsep_adjoint_step``, ``lbsep_adjoint_seed_cl``,
 ``lbsep_adjoint_initial``). torch holds the device buffers.
 
-Memory: one FP64 state per step of a checkpoint segment is kept during the
-reverse sweep (checkpoint_every * 18 * ny * nx doubles) plus one raw state per
-checkpoint.
+Memory: two FP64 states per step of a checkpoint segment (pre- and
+post-collision) are kept during the reverse sweep (2 * checkpoint_every * 18 *
+ny * nx doubles) plus one raw state per checkpoint.
 """
 from __future__ import annotations
 
@@ -44,12 +44,18 @@ class Adjoint:
         if t.shape != self.shape or t.dtype != torch.float64 or not t.is_contiguous():
             raise ValueError(f"expected a contiguous float64 tensor of shape {self.shape}")
 
-    def step(self, f_t: torch.Tensor, lam_next: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    def step(self, f_t: torch.Tensor, lam_next: torch.Tensor, out: torch.Tensor | None = None,
+             f_post: torch.Tensor | None = None) -> torch.Tensor:
+        """lam(t) from lam(t+1) at the pre-collision state f_t; f_post = C(f_t)
+        from Channel.get_post_collision at the same level, or None (recomputed)."""
         self._check_state(f_t)
         self._check_state(lam_next)
+        if f_post is not None:
+            self._check_state(f_post)
         out = torch.empty_like(lam_next) if out is None else out
         self.ch._take_over()
         lbsep._check(lbsep.load().lbsep_adjoint_step(self.ch._h, c_void_p(f_t.data_ptr()),
+                                                     c_void_p(f_post.data_ptr() if f_post is not None else None),
                                                      c_void_p(lam_next.data_ptr()), c_void_p(out.data_ptr()),
                                                      c_void_p(self.dparams.data_ptr()), *self._args()))
         self.ch._hand_over(out)
@@ -76,8 +82,9 @@ def cl_gradient(params: lbsep.Params, nsteps: int, checkpoint_every: int = 500, 
 
     Forward: nsteps sweeps, a raw checkpoint every `checkpoint_every` levels.
     Reverse: per segment (last first) restore the checkpoint, recompute and keep
-    the segment's pre-collision states, then run the adjoint steps back through
-    it; finally add the initial state's term. Returns (cl, tensor[3])."""
+    the segment's pre- and post-collision states, then run the adjoint steps
+    back through it; finally add the initial state's term. Returns (cl,
+    tensor[3])."""
     ch = lbsep.Channel(params, device=device)
     adj = Adjoint(ch)
     ckpt = {0: ch.get_state()}
@@ -97,10 +104,10 @@ def cl_gradient(params: lbsep.Params, nsteps: int, checkpoint_every: int = 500, 
         ch.set_state(ckpt[t0], t0)
         seg = []
         for _ in range(t0, t1):
-            seg.append(ch.get_populations())
+            seg.append((ch.get_populations(), ch.get_post_collision()))
             ch.step(1)
         for k in range(len(seg) - 1, -1, -1):
-            adj.step(seg[k], lam, out=spare)
+            adj.step(seg[k][0], lam, out=spare, f_post=seg[k][1])
             lam, spare = spare, lam
         del seg
     adj.initial(lam)

@@ -972,6 +972,23 @@ __global__ void k_copy_in(KParams kp, const S* __restrict__ dense, S* __restrict
   }
 }
 
+// Post-collision state (storage representation) -> dense [2][9][ny][nx] FP64
+// populations: the stored value, plus f0 of the node's column for deviations.
+template <class MD>
+__global__ void k_copy_post(KParams kp, const typename MD::St* __restrict__ f, double* __restrict__ dense) {
+  const long long n = 18LL * kp.ny * kp.nx;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long row = e / kp.nx;
+    const int x = int(e - row * kp.nx);
+    const int si = int(row / kp.ny);  // s * 9 + i
+    const int j = int(row - (long long)si * kp.ny);
+    const int s = si / 9, i = si - 9 * s;
+    const double v = double(f[pidx(kp, s, i, j, x)]);
+    dense[e] = MD::kDev ? v + kp.wa[s][i] * ref_rho(kp, s, x) : v;
+  }
+}
+
 // Dense [2][9][ny][nx] FP64 populations -> pitched storage representation.
 template <class MD>
 __global__ void k_set_pop(KParams kp, const double* __restrict__ dense, typename MD::St* __restrict__ f) {
@@ -1459,6 +1476,26 @@ int lbsep_get_state(lbsep_channel* h, void* dev_dst) {
 int lbsep_get_populations(lbsep_channel* h, double* dev_dst) {
   if (!h || !dev_dst) return fail(LBSEP_EINVAL, "NULL argument");
   return eval_state(h, nullptr, nullptr, dev_dst);
+}
+
+int lbsep_get_post_collision(lbsep_channel* h, double* dev_dst) {
+  if (!h || !dev_dst) return fail(LBSEP_EINVAL, "NULL argument");
+  const void* cur = h->f[h->cur];
+  switch (h->p.dtype) {
+    case LBSEP_F64:
+      hipLaunchKernelGGL(k_copy_post<ModeF64>, dim3(2048), dim3(256), 0, h->stream, h->kp,
+                         static_cast<const double*>(cur), dev_dst);
+      break;
+    case LBSEP_F32:
+      hipLaunchKernelGGL(k_copy_post<ModeF32>, dim3(2048), dim3(256), 0, h->stream, h->kp,
+                         static_cast<const float*>(cur), dev_dst);
+      break;
+    default:
+      hipLaunchKernelGGL(k_copy_post<ModeF16>, dim3(2048), dim3(256), 0, h->stream, h->kp,
+                         static_cast<const _Float16*>(cur), dev_dst);
+      break;
+  }
+  return check_hip(hipGetLastError(), "post-collision copy");
 }
 
 int lbsep_set_state(lbsep_channel* h, const void* dev_src, int64_t t) {

@@ -85,55 +85,69 @@ __device__ double e1_dev(double a) {
   return exp(-a) * g / a;
 }
 
-// Forward relaxation times and their reverse: given the adjoints of
-// (tau_s, tau_d, tau_q), add d/d(rho_a, rho_b) to (ga, gb). The forward
-// formulas are those of relaxation_times in the device header.
+// Forward relaxation times (the same arithmetic as relaxation_times in the
+// device header, so the same values) together with what their reverse needs:
+// the mixture quantities and the wall-function values psi and h = psi' / 2 of
+// the seven arguments, each evaluated once.
 struct TauState {
   double ts, td, tq;
+  NodeGas<double> g;
+  double y, ay, ab, aw;
+  double hay, hab, h1a, h2a, h1b, h2b, pw, hw;
+  double psi_m, psi_a, psi_b;
 };
 
 __device__ TauState taus_fwd(const RelaxConsts& c, int j, double ra, double rb) {
-  TauState o;
-  relaxation_times<double>(c, j, ra, rb, o.ts, o.td, o.tq);
+  TauState o{};
+  if (c.bgk) {
+    o.ts = o.td = o.tq = c.tau_bgk;
+    return o;
+  }
+  o.g = node_gas<double>(c, ra, rb);
+  const NodeGas<double>& g = o.g;
+  if (c.mfp_off) {
+    o.psi_m = o.psi_a = o.psi_b = 1.0;
+    taus_from_psi<double>(c, g, 1.0, 1.0, 1.0, g.k * g.lam, 0.0, o.ts, o.td, o.tq);
+    return o;
+  }
+  o.y = double(j) + 0.5;
+  o.ay = o.y * g.il;
+  o.ab = (c.height - o.y) * g.il;
+  double p1, p2;
+  wall_psi<double, true>(o.ay, p1, o.hay);
+  wall_psi<double, true>(o.ab, p2, o.hab);
+  o.psi_m = 0.5 * (p1 + p2);
+  wall_psi<double, true>(g.xa * o.ay, p1, o.h1a);
+  wall_psi<double, true>(g.xa * o.ab, p2, o.h2a);
+  o.psi_a = 0.5 * (p1 + p2);
+  wall_psi<double, true>(g.xb * o.ay, p1, o.h1b);
+  wall_psi<double, true>(g.xb * o.ab, p2, o.h2b);
+  o.psi_b = 0.5 * (p1 + p2);
+  o.aw = c.height * g.il;
+  wall_psi<double, true>(o.aw, o.pw, o.hw);
+  taus_from_psi<double>(c, g, o.psi_m, o.psi_a, o.psi_b, 0.5 * g.k * g.lam * o.pw, g.k * (1.0 - o.hw), o.ts, o.td,
+                        o.tq);
   return o;
 }
 
-__device__ void taus_rev(const RelaxConsts& c, int j, double ra, double rb, double bts, double btd, double btq,
-                         double& ga, double& gb) {
+// Reverse of taus_fwd: given the adjoints of (tau_s, tau_d, tau_q), add
+// d/d(rho_a, rho_b) to (ga, gb).
+__device__ void taus_rev(const RelaxConsts& c, const TauState& st, double ra, double rb, double bts, double btd,
+                         double btq, double& ga, double& gb) {
   if (c.bgk) return;  // constant relaxation times
-  const double na = ra * c.inv_m[0], nb = rb * c.inv_m[1];
-  const double n = na + nb, inv_n = 1.0 / n;
-  const double xa = na * inv_n, xb = nb * inv_n;
-  const double mx = (ra + rb) * inv_n;
+  const NodeGas<double>& g = st.g;
+  const double inv_n = 1.0 / (ra * c.inv_m[0] + rb * c.inv_m[1]);
+  const double xa = g.xa, xb = g.xb, mx = g.mx, lam = g.lam, k = g.k;
   const double pres = (1.0 / 3.0) * (c.s[0] * ra + c.s[1] * rb);
-  const double il = pres * c.inv_lam_p;
-  const double lam = c.lam_p / pres;
-  const double k = c.kpref / sqrt(mx);
-  double psi_m = 1.0, psi_a = 1.0, psi_b = 1.0, pw = 0.0, hw = 0.0;
-  double hay = 0, hab = 0, h1a = 0, h2a = 0, h1b = 0, h2b = 0, ay = 0, ab = 0, aw = 0;
-  const double y = double(j) + 0.5;
   double tt0, dtt0;
   if (c.mfp_off) {
     tt0 = k * lam;
     dtt0 = 0.0;
   } else {
-    ay = y * il;
-    ab = (c.height - y) * il;
-    double p1, p2;
-    wall_psi<double, true>(ay, p1, hay);
-    wall_psi<double, true>(ab, p2, hab);
-    psi_m = 0.5 * (p1 + p2);
-    wall_psi<double, true>(xa * ay, p1, h1a);
-    wall_psi<double, true>(xa * ab, p2, h2a);
-    psi_a = 0.5 * (p1 + p2);
-    wall_psi<double, true>(xb * ay, p1, h1b);
-    wall_psi<double, true>(xb * ab, p2, h2b);
-    psi_b = 0.5 * (p1 + p2);
-    aw = c.height * il;
-    wall_psi<double, true>(aw, pw, hw);
-    tt0 = 0.5 * k * lam * pw;
-    dtt0 = k * (1.0 - hw);
+    tt0 = 0.5 * k * lam * st.pw;
+    dtt0 = k * (1.0 - st.hw);
   }
+  const double psi_m = st.psi_m, psi_a = st.psi_a, psi_b = st.psi_b;
   const double sa = 1.0 / sqrt(psi_a) + 1.0 / sqrt(psi_b);
   const double q = c.dpref * lam / (mx * sa * sa);
   const double r0 = 1.0 / tt0;
@@ -146,11 +160,11 @@ __device__ void taus_rev(const RelaxConsts& c, int j, double ra, double rb, doub
     bk += btt0 * lam;
     blam += btt0 * k;
   } else {
-    bk += btt0 * 0.5 * lam * pw + bdtt0 * (1.0 - hw);
-    blam += btt0 * 0.5 * k * pw;
+    bk += btt0 * 0.5 * lam * st.pw + bdtt0 * (1.0 - st.hw);
+    blam += btt0 * 0.5 * k * st.pw;
     const double bpw = btt0 * 0.5 * k * lam;
     const double bhw = -bdtt0 * k;
-    const double baw = bpw * 2.0 * hw - bhw * e1_dev(aw);  // psi' = 2h, h' = -E1
+    const double baw = bpw * 2.0 * st.hw - bhw * e1_dev(st.aw);  // psi' = 2h, h' = -E1
     bil += baw * c.height;
   }
   // tau_d = 1/2 + q, q = dpref lam / (mx sa^2)
@@ -164,17 +178,17 @@ __device__ void taus_rev(const RelaxConsts& c, int j, double ra, double rb, doub
   bk += bts * lam * psi_m;
   if (!c.mfp_off) {
     const double bpsm = bts * lam * k;
-    double bay = bpsm * hay, bab = bpsm * hab;  // d psi_m / d ay = psi'(ay) / 2 = h(ay)
+    double bay = bpsm * st.hay, bab = bpsm * st.hab;  // d psi_m / d ay = psi'(ay) / 2 = h(ay)
     // psi_a = (psi(xa ay) + psi(xa ab)) / 2
-    const double z1a = bpsa * h1a, z2a = bpsa * h2a;
-    bxa += z1a * ay + z2a * ab;
+    const double z1a = bpsa * st.h1a, z2a = bpsa * st.h2a;
+    bxa += z1a * st.ay + z2a * st.ab;
     bay += z1a * xa;
     bab += z2a * xa;
-    const double z1b = bpsb * h1b, z2b = bpsb * h2b;
-    bxb += z1b * ay + z2b * ab;
+    const double z1b = bpsb * st.h1b, z2b = bpsb * st.h2b;
+    bxb += z1b * st.ay + z2b * st.ab;
     bay += z1b * xb;
     bab += z2b * xb;
-    bil += bay * y + bab * (c.height - y);
+    bil += bay * st.y + bab * (c.height - st.y);
   }
   // k = kpref / sqrt(mx)
   bmx += bk * (-0.5) * k / mx;
@@ -195,6 +209,7 @@ __device__ void taus_rev(const RelaxConsts& c, int j, double ra, double rb, doub
 __device__ void collide_fwd(const RelaxConsts& rc, int j, const double fa[9], const double fb[9], double oa[9],
                             double ob[9]) {
   double ra = 0, rb = 0, jxa = 0, jya = 0, jxb = 0, jyb = 0;
+#pragma unroll
   for (int i = 0; i < 9; ++i) {
     ra += fa[i];
     rb += fb[i];
@@ -215,6 +230,7 @@ __device__ void collide_fwd(const RelaxConsts& rc, int j, const double fa[9], co
     weps = 1.0 / 1.2;
   }
   const double wd = 1.0 / t.td, wq = 1.0 / t.tq;
+#pragma unroll
   for (int i = 0; i < 9; ++i) {
     oa[i] = fa[i];
     ob[i] = fb[i];
@@ -256,8 +272,10 @@ __device__ void collide_rev(const RelaxConsts& rc, int j, const double fa[9], co
   const double* g[2] = {ga, gb};
   double* o[2] = {oa, ob};
   double rho[2], jx[2], jy[2];
+#pragma unroll
   for (int s = 0; s < 2; ++s) {
     rho[s] = jx[s] = jy[s] = 0.0;
+#pragma unroll
     for (int i = 0; i < 9; ++i) {
       rho[s] += f[s][i];
       jx[s] += kCx[i] * f[s][i];
@@ -270,6 +288,7 @@ __device__ void collide_rev(const RelaxConsts& rc, int j, const double fa[9], co
   const TauState t = taus_fwd(rc, j, rho[0], rho[1]);
   double w[9];
   if (rc.bgk) {
+#pragma unroll
     for (int k = 0; k < 9; ++k) w[k] = 1.0 / t.ts;
   } else {
     w[0] = 1.0;
@@ -284,6 +303,7 @@ __device__ void collide_rev(const RelaxConsts& rc, int j, const double fa[9], co
   double bw[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   double bux = 0.0, buy = 0.0, brho[2] = {0.0, 0.0};
   double bm[2][9];
+#pragma unroll
   for (int s = 0; s < 2; ++s) {
     const double sv = rc.s[s];
     double m[9], mg[9];
@@ -300,6 +320,7 @@ __device__ void collide_rev(const RelaxConsts& rc, int j, const double fa[9], co
                            r * (ux * ux - uy * uy),
                            r * ux * uy};
     double be[9];
+#pragma unroll
     for (int k = 0; k < 9; ++k) {
       const double bmp = d[k] * mg[k];  // adjoint of m'_k
       bm[s][k] = (1.0 - w[k]) * bmp;
@@ -320,10 +341,11 @@ __device__ void collide_rev(const RelaxConsts& rc, int j, const double fa[9], co
     btq = -(bw[4] + bw[6]) * w[4] * w[4];
     bts = -(bw[7] + bw[8]) * w[7] * w[7];
   }
-  taus_rev(rc, j, rho[0], rho[1], bts, btd, btq, brho[0], brho[1]);
+  taus_rev(rc, t, rho[0], rho[1], bts, btd, btq, brho[0], brho[1]);
   // u = (jx_a + jx_b) / rho
   const double bjx = bux / rt, bjy = buy / rt;
   const double brt = -(bux * ux + buy * uy) / rt;
+#pragma unroll
   for (int s = 0; s < 2; ++s) {
     bm[s][0] += brho[s] + brt;
     bm[s][3] += bjx;
@@ -341,11 +363,13 @@ __global__ __launch_bounds__(kAT) void k_adj_post(AdjParams ap, const double* __
   if (e >= n) return;
   const int j = int(e / ap.nx), x = int(e - (long long)j * ap.nx);
   double fa[9], fb[9], oa[9], ob[9];
+#pragma unroll
   for (int i = 0; i < 9; ++i) {
     fa[i] = ft[didx(ap, 0, i, j, x)];
     fb[i] = ft[didx(ap, 1, i, j, x)];
   }
   collide_fwd(ap.rc, j, fa, fb, oa, ob);
+#pragma unroll
   for (int i = 0; i < 9; ++i) {
     fpost[didx(ap, 0, i, j, x)] = oa[i];
     fpost[didx(ap, 1, i, j, x)] = ob[i];
@@ -356,6 +380,7 @@ __global__ __launch_bounds__(kAT) void k_adj_post(AdjParams ap, const double* __
 // the inlet/outlet closure), from the post-collision state.
 __device__ void pulled(const AdjParams& ap, const double* __restrict__ fpost, int s, int x, int j, double out[9]) {
   const bool px = ap.flags & LBSEP_PERIODIC_X, py = ap.flags & LBSEP_PERIODIC_Y;
+#pragma unroll
   for (int i = 0; i < 9; ++i) {
     int xs = x - kCx[i], ys = j - kCy[i];
     if (xs < 0 || xs >= ap.nx) xs = px ? (xs + ap.nx) % ap.nx : (xs < 0 ? 0 : ap.nx - 1);  // unknown dirs: replaced
@@ -370,61 +395,73 @@ __device__ void pulled(const AdjParams& ap, const double* __restrict__ fpost, in
     const double v0 = ap.r * (2.0 / 3.0) * F + (1.0 - ap.r) * a;
     const double v1 = ap.r * F / 6.0 + (1.0 - ap.r) * b;
     const double v2 = ap.r * F / 6.0 + (1.0 - ap.r) * c;
-    out[bot ? 2 : 4] = v0;
-    out[bot ? 5 : 7] = v1;
-    out[bot ? 6 : 8] = v2;
+    if (bot) {  // constant indices keep out in registers
+      out[2] = v0;
+      out[5] = v1;
+      out[6] = v2;
+    } else {
+      out[4] = v0;
+      out[7] = v1;
+      out[8] = v2;
+    }
   }
 }
 
+// Block sum in a fixed order (wavefront trees, then the four wavefront results
+// in order); every thread gets it. sh: at least four doubles of shared memory.
 __device__ double block_sum_d(double v, double* sh) {
-  const int t = threadIdx.x;
-  sh[t] = v;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+  __syncthreads();  // sh may still be read from a previous call
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
   __syncthreads();
-  for (int o = kAT / 2; o > 0; o >>= 1) {
-    if (t < o) sh[t] += sh[t + o];
-    __syncthreads();
+  return ((sh[0] + sh[1]) + sh[2]) + sh[3];
+}
+
+// Block sums of two values per thread in a fixed order: wavefront trees
+// (shuffles), then the four wavefront results in order. Every thread gets both.
+__device__ void block_sum2(double& u, double& v, double (*sh)[kAT / 64]) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    u += __shfl_xor(u, off);
+    v += __shfl_xor(v, off);
   }
-  const double r = sh[0];
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][w] = u;
+    sh[1][w] = v;
+  }
   __syncthreads();
-  return r;
+  u = ((sh[0][0] + sh[0][1]) + sh[0][2]) + sh[0][3];
+  v = ((sh[1][0] + sh[1][1]) + sh[1][2]) + sh[1][3];
 }
 
 // Reverse of the inlet/outlet closure. Block (e, s): end e (0 inlet, 1 outlet),
 // species s. Writes lamP[e][s][c][i][j] for c = 0 (boundary column), 1, 2
 // (first and second inner layer: the adjoint passing through unchanged plus the
 // closure's dependence on them) and the rho_bc partials part[e][s][0..1].
+// Two passes over the column: the sums S = sum_j rho'(j) and
+// kappa-bar = sum_j A(j) rho'(j) / rho_node(j) (neither needs kappa), then the
+// per-row adjoints.
 __global__ __launch_bounds__(kAT) void k_adj_ends(AdjParams ap, const double* __restrict__ fpost,
                                                   const double* __restrict__ lam_next, double* __restrict__ lamP,
                                                   double* __restrict__ part) {
-  __shared__ double sh[kAT];
+  static_assert(kAT == 256, "block_sum2 assumes four wavefronts");
+  __shared__ double sh[2][kAT / 64];
   const int e = blockIdx.x >> 1, s = blockIdx.x & 1;
   const int col = e ? ap.nx - 1 : 0, l1 = e ? ap.nx - 2 : 1, l2 = e ? ap.nx - 3 : 2;
   const int ny = ap.ny;
   double* out = lamP + (long long)(e * 2 + s) * 3 * 9 * ny;  // [c][i][j]
   auto unknown = [&](int i) { return e == 0 ? kCx[i] == 1 : kCx[i] == -1; };
-  // pass 1: S = sum_j rho'(j)
-  double acc = 0.0;
-  for (int j = threadIdx.x; j < ny; j += kAT) {
-    double g1[9], g2[9];
-    pulled(ap, fpost, s, l1, j, g1);
-    pulled(ap, fpost, s, l2, j, g2);
-    double r1 = 0, r2 = 0;
-    for (int i = 0; i < 9; ++i) {
-      r1 += g1[i];
-      r2 += g2[i];
-    }
-    acc += 2.0 * r1 - r2;
-  }
-  const double S = block_sum_d(acc, sh);
-  const double kappa = double(ny) * ap.rho_bc[e][s] / S;
-  // pass 2: kappa-bar = sum_j A(j) rho'(j) / rho_node(j), A = sum_i lam_E,i ghat_i
-  acc = 0.0;
+  // pass 1: S and kappa-bar
+  double accS = 0.0, accK = 0.0;
   for (int j = threadIdx.x; j < ny; j += kAT) {
     double g0[9], g1[9], g2[9];
     pulled(ap, fpost, s, col, j, g0);
     pulled(ap, fpost, s, l1, j, g1);
     pulled(ap, fpost, s, l2, j, g2);
     double r1 = 0, r2 = 0, rn = 0, A = 0;
+#pragma unroll
     for (int i = 0; i < 9; ++i) {
       const double gh = unknown(i) ? 2.0 * g1[i] - g2[i] : g0[i];
       r1 += g1[i];
@@ -432,16 +469,21 @@ __global__ __launch_bounds__(kAT) void k_adj_ends(AdjParams ap, const double* __
       rn += gh;
       A += lam_next[didx(ap, s, i, j, col)] * gh;
     }
-    acc += A * (2.0 * r1 - r2) / rn;
+    const double rp = 2.0 * r1 - r2;
+    accS += rp;
+    accK += A * rp / rn;
   }
-  const double kbar = block_sum_d(acc, sh);
-  // pass 3: per-row adjoints
+  block_sum2(accS, accK, sh);
+  const double S = accS, kbar = accK;
+  const double kappa = double(ny) * ap.rho_bc[e][s] / S;
+  // pass 2: per-row adjoints
   for (int j = threadIdx.x; j < ny; j += kAT) {
     double g0[9], g1[9], g2[9], gh[9], lE[9];
     pulled(ap, fpost, s, col, j, g0);
     pulled(ap, fpost, s, l1, j, g1);
     pulled(ap, fpost, s, l2, j, g2);
     double r1 = 0, r2 = 0, rn = 0, A = 0;
+#pragma unroll
     for (int i = 0; i < 9; ++i) {
       gh[i] = unknown(i) ? 2.0 * g1[i] - g2[i] : g0[i];
       lE[i] = lam_next[didx(ap, s, i, j, col)];
@@ -453,6 +495,7 @@ __global__ __launch_bounds__(kAT) void k_adj_ends(AdjParams ap, const double* __
     const double rp = 2.0 * r1 - r2;
     const double scale = kappa * rp / rn;
     const double brp = A * kappa / rn - kbar * kappa / S;  // d/d rho'(j), with d kappa / d rho'(j) = -kappa / S
+#pragma unroll
     for (int i = 0; i < 9; ++i) {
       const double bgh = lE[i] * scale - A * scale / rn;
       double b0 = 0.0, b1 = lam_next[didx(ap, s, i, j, l1)] + 2.0 * brp,
@@ -507,7 +550,9 @@ __global__ __launch_bounds__(kAT) void k_adj_main(AdjParams ap, const double* __
     const int j = int(e / ap.nx), x = int(e - (long long)j * ap.nx);
     const bool px = ap.flags & LBSEP_PERIODIC_X, py = ap.flags & LBSEP_PERIODIC_Y;
     double g[2][9];
+#pragma unroll
     for (int s = 0; s < 2; ++s) {
+#pragma unroll
       for (int i = 0; i < 9; ++i) {
         int xd = x + kCx[i], yd = j + kCy[i];
         double v = 0.0;
@@ -533,29 +578,44 @@ __global__ __launch_bounds__(kAT) void k_adj_main(AdjParams ap, const double* __
       if (!py && (j == 0 || j == ap.ny - 1)) {
         // DBB at this node: returning k = r share_k F + (1 - r) f'_leaving(k)
         const bool bot = j == 0;
-        const int ret[3] = {bot ? 2 : 4, bot ? 5 : 7, bot ? 6 : 8};
-        const int lea[3] = {bot ? 4 : 2, bot ? 7 : 5, bot ? 8 : 6};
         const double share[3] = {2.0 / 3.0, 1.0 / 6.0, 1.0 / 6.0};
-        double lr[3], F = 0.0, fl[3];
+        double lr[3], fl[3], F = 0.0;
+#pragma unroll
         for (int q = 0; q < 3; ++q) {
-          lr[q] = lam_p(ap, lam_next, lamP, s, ret[q], j, x);
-          fl[q] = fpost[didx(ap, s, lea[q], j, x)];
+          const int rq = bot ? (q == 0 ? 2 : q == 1 ? 5 : 6) : (q == 0 ? 4 : q == 1 ? 7 : 8);
+          const int lq = bot ? (q == 0 ? 4 : q == 1 ? 7 : 8) : (q == 0 ? 2 : q == 1 ? 5 : 6);
+          lr[q] = lam_p(ap, lam_next, lamP, s, rq, j, x);
+          fl[q] = fpost[didx(ap, s, lq, j, x)];
           F += fl[q];
         }
         double sl = 0.0;
+#pragma unroll
         for (int q = 0; q < 3; ++q) sl += lr[q] * share[q];
+        double add[3];
+#pragma unroll
         for (int q = 0; q < 3; ++q) {
-          g[s][lea[q]] += ap.r * sl + (1.0 - ap.r) * lr[q];
+          add[q] = ap.r * sl + (1.0 - ap.r) * lr[q];
           dr += lr[q] * (share[q] * F - fl[q]);
+        }
+        if (bot) {  // constant indices keep g in registers
+          g[s][4] += add[0];
+          g[s][7] += add[1];
+          g[s][8] += add[2];
+        } else {
+          g[s][2] += add[0];
+          g[s][5] += add[1];
+          g[s][6] += add[2];
         }
       }
     }
     double fa[9], fb[9], oa[9], ob[9];
+#pragma unroll
     for (int i = 0; i < 9; ++i) {
       fa[i] = ft[didx(ap, 0, i, j, x)];
       fb[i] = ft[didx(ap, 1, i, j, x)];
     }
     collide_rev(ap.rc, j, fa, fb, g[0], g[1], oa, ob);
+#pragma unroll
     for (int i = 0; i < 9; ++i) {
       lam_out[didx(ap, 0, i, j, x)] = oa[i];
       lam_out[didx(ap, 1, i, j, x)] = ob[i];
@@ -601,6 +661,7 @@ __global__ void k_adj_colsum(AdjParams ap, const double* __restrict__ f, double*
   if (x >= ap.nx) return;
   double na = 0.0, nb = 0.0;
   for (int j = 0; j < ap.ny; ++j)
+#pragma unroll
     for (int i = 0; i < 9; ++i) {
       na += f[didx(ap, 0, i, j, x)];
       nb += f[didx(ap, 1, i, j, x)];
@@ -669,9 +730,11 @@ __global__ void k_adj_initial(AdjParams ap, const double* __restrict__ lam0, dou
   const double dra[2] = {c * dp_dth / (ap.rc.s[0] * kCs2), dc_dc * pres / (ap.rc.s[0] * kCs2)};
   const double drb[2] = {(1.0 - c) * dp_dth / (ap.rc.s[1] * kCs2), -dc_dc * pres / (ap.rc.s[1] * kCs2)};
   double la = 0.0, lb = 0.0;  // sum_{i, j} lam0 w_i alpha_si
+#pragma unroll
   for (int s = 0; s < 2; ++s) {
     const double sv = ap.rc.s[s];
     double acc = 0.0;
+#pragma unroll
     for (int i = 0; i < 9; ++i) {
       const double alpha = i == 0 ? (9.0 - 5.0 * sv) / 4.0 : sv;
       double sj = 0.0;
@@ -727,6 +790,7 @@ int make_adj(const lbsep_channel* ch, void* ws, size_t bytes, AdjParams& ap, Adj
   ap.flags = v.p.flags;
   ap.r = v.p.dbb_r;
   for (int e = 0; e < 2; ++e)
+#pragma unroll
     for (int s = 0; s < 2; ++s) ap.rho_bc[e][s] = v.rho_bc[e][s];
   const double pout = kCs2, pin = v.p.theta * pout;
   ap.drho_in[0][0] = v.p.cl_in * pout / (v.rc.s[0] * kCs2);
@@ -757,20 +821,25 @@ size_t lbsep_adjoint_workspace_bytes(const lbsep_params* p) {
   return adj_layout(p).total;
 }
 
-int lbsep_adjoint_step(lbsep_channel* ch, const double* f_t, const double* lam_next, double* lam_out, double* dparams,
-                       void* adj_ws, size_t adj_ws_bytes) {
+int lbsep_adjoint_step(lbsep_channel* ch, const double* f_t, const double* f_post, const double* lam_next,
+                       double* lam_out, double* dparams, void* adj_ws, size_t adj_ws_bytes) {
   AdjParams ap;
   AdjLayout L;
   hipStream_t st;
   if (int e = make_adj(ch, adj_ws, adj_ws_bytes, ap, L, st)) return e;
   if (!f_t || !lam_next || !lam_out || !dparams) return set_error(LBSEP_EINVAL, "NULL buffer");
-  if (lam_out == lam_next || lam_out == f_t) return set_error(LBSEP_EINVAL, "lam_out must not alias the inputs");
+  if (lam_out == lam_next || lam_out == f_t || (f_post && lam_out == f_post))
+    return set_error(LBSEP_EINVAL, "lam_out must not alias the inputs");
   char* ws = static_cast<char*>(adj_ws);
-  double* fpost = reinterpret_cast<double*>(ws + L.fpost);
+  const double* fpost = f_post;
   double* lamP = reinterpret_cast<double*>(ws + L.lamP);
   double* pe = reinterpret_cast<double*>(ws + L.part_ends);
   double* pr = reinterpret_cast<double*>(ws + L.part_r);
-  hipLaunchKernelGGL(k_adj_post, dim3(L.nblocks), dim3(kAT), 0, st, ap, f_t, fpost);
+  if (!fpost) {  // recompute C(f_t) into the workspace
+    double* own = reinterpret_cast<double*>(ws + L.fpost);
+    hipLaunchKernelGGL(k_adj_post, dim3(L.nblocks), dim3(kAT), 0, st, ap, f_t, own);
+    fpost = own;
+  }
   const bool ends = !(ap.flags & LBSEP_PERIODIC_X);
   if (ends) hipLaunchKernelGGL(k_adj_ends, dim3(4), dim3(kAT), 0, st, ap, fpost, lam_next, lamP, pe);
   hipLaunchKernelGGL(k_adj_main, dim3(L.nblocks), dim3(kAT), 0, st, ap, f_t, fpost, lam_next, lamP, lam_out, pr);

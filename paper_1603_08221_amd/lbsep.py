@@ -71,6 +71,7 @@ def load():
         "lbsep_get_state": (c_int, [c_void_p, c_void_p]),
         "lbsep_set_state": (c_int, [c_void_p, c_void_p, c_int64]),
         "lbsep_get_populations": (c_int, [c_void_p, c_void_p]),
+        "lbsep_get_post_collision": (c_int, [c_void_p, c_void_p]),
         "lbsep_set_populations": (c_int, [c_void_p, c_void_p, c_int64]),
         "lbsep_dbb_r_from_cm": (c_double, [c_double, c_double, c_double, c_double]),
         "lbsep_wall_function": (c_int, [c_void_p, c_void_p, c_void_p, c_int64, c_int32, c_void_p]),
@@ -83,7 +84,8 @@ def load():
         "lbsep_batch_size": (c_int32, [c_void_p]),
         "lbsep_batch_destroy": (None, [c_void_p]),
         "lbsep_adjoint_workspace_bytes": (c_size_t, [P]),
-        "lbsep_adjoint_step": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t]),
+        "lbsep_adjoint_step": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                       c_size_t]),
         "lbsep_adjoint_seed_cl": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t]),
         "lbsep_adjoint_initial": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_size_t]),
     }
@@ -232,6 +234,14 @@ class Channel:
         """Pre-collision populations f in float64, whatever the storage type."""
         out = torch.empty((2, 9, self.ny, self.nx), dtype=torch.float64, device=self.device)
         _check(load().lbsep_get_populations(self._h, c_void_p(out.data_ptr())))
+        self._hand_over(out)
+        return out
+
+    def get_post_collision(self) -> torch.Tensor:
+        """Post-collision populations f'(t) = C(f(t)) of the current level in
+        float64 (the state the next step streams)."""
+        out = torch.empty((2, 9, self.ny, self.nx), dtype=torch.float64, device=self.device)
+        _check(load().lbsep_get_post_collision(self._h, c_void_p(out.data_ptr())))
         self._hand_over(out)
         return out
 

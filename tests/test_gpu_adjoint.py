@@ -47,6 +47,38 @@ def test_adjoint_step_matches_the_cpu_reverse_sweep(modes):
         assert abs(dp[k] - ref_dp[k]) <= 1e-11 * max(abs(ref_dp[k]), 1e-3), (k, dp[k], ref_dp[k])
 
 
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-13), ("f32", 1e-5)])
+def test_post_collision_state_is_the_collision_of_the_populations(dtype, tol):
+    """The forward's own post-collision state f'(t) against the oracle's
+    collision of the forward's pre-collision state f(t), after 30 steps."""
+    w = SMALL
+    r = r_of(w)
+    ch = channel(w, r, dtype=dtype)
+    ch.step(30)
+    f = ch.get_populations().cpu().numpy()
+    got = ch.get_post_collision().cpu().numpy()
+    ref = O.collide(f, oracle_params(w, r))
+    assert _rel(got, ref) <= tol
+
+
+def test_adjoint_step_with_the_forward_post_collision_state():
+    """lam(t) and the parameter partials with f_post from the forward agree with
+    the step that recomputes C(f_t) itself (same map, two FP64 evaluations)."""
+    w = SMALL
+    r = r_of(w)
+    ch = channel(w, r)
+    ch.step(25)
+    f, fp = ch.get_populations(), ch.get_post_collision()
+    lam = torch.from_numpy(np.random.default_rng(7).standard_normal(tuple(f.shape))).cuda()
+    a1, a2 = Adjoint(ch), Adjoint(ch)
+    got = a1.step(f, lam, f_post=fp).cpu().numpy()
+    ref = a2.step(f, lam).cpu().numpy()
+    assert _rel(got, ref) <= 1e-12
+    d1, d2 = a1.dparams.cpu().numpy(), a2.dparams.cpu().numpy()
+    for k in range(3):
+        assert abs(d1[k] - d2[k]) <= 1e-11 * max(abs(d2[k]), 1e-3), (k, d1[k], d2[k])
+
+
 def test_adjoint_step_bgk_limit():
     w = SMALL
     r = r_of(w)
