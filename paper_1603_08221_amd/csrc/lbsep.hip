@@ -354,14 +354,25 @@ __device__ __forceinline__ void end_rebuild(const KParams& kp, int e, int s, int
   }
 }
 
-// Moments, relaxation times and (STEP) collision + store or (EVAL) output of
-// one node by one lane holding both species (fa, fb: populations, deviations
-// in the FP32/FP16 modes). acc receives (n_a, n_b, rho_a u_ax, rho_b u_bx).
-template <class MD, bool EVAL, bool NT = false>
-__device__ __forceinline__ void process_node(const KParams& kp, int x, int j, typename MD::Ct fa[9],
-                                             typename MD::Ct fb[9], typename MD::St* __restrict__ dst,
-                                             double* __restrict__ mom, typename MD::St* __restrict__ fraw,
-                                             double* __restrict__ ffull, double acc[4]) {
+// What the collision of a node needs from its moments and relaxation times.
+template <typename C>
+struct NodeState {
+  C ca, cb;        // conserved density parts (rho, or rho - rho0 for deviations)
+  C rho_a, rho_b;  // species densities
+  C ux, uy;        // mixture velocity
+  C ts, tq, h2;    // tau_s, tau_q and 1 / (2 tau_d)
+};
+
+// Moments and relaxation times of one node by one lane holding both species
+// (fa, fb: populations, deviations in the FP32/FP16 modes); (STEP) adds the
+// node to acc = (n_a, n_b, rho_a u_ax, rho_b u_bx), (EVAL) writes the outputs.
+template <class MD, bool EVAL>
+__device__ __forceinline__ NodeState<typename MD::Ct> node_moments(const KParams& kp, int x, int j,
+                                                                   const typename MD::Ct fa[9],
+                                                                   const typename MD::Ct fb[9],
+                                                                   double* __restrict__ mom,
+                                                                   typename MD::St* __restrict__ fraw,
+                                                                   double* __restrict__ ffull, double acc[4]) {
   using C = typename MD::Ct;
   using E = E1Traits<C>;
   const C ca = sum9(fa);  // rho_a, or rho_a - rho0_a(x)
@@ -386,6 +397,7 @@ __device__ __forceinline__ void process_node(const KParams& kp, int x, int j, ty
   const C g = C(1) - h2;
   const C pxa = g * jxa + rho_a * ux * h2;
   const C pxb = g * jxb + rho_b * ux * h2;
+  const NodeState<C> st{ca, cb, rho_a, rho_b, ux, uy, ts, tq, h2};
   if (EVAL) {
     const long long n = (long long)kp.nx * kp.ny;
     const long long o = (long long)j * kp.nx + x;
@@ -413,23 +425,39 @@ __device__ __forceinline__ void process_node(const KParams& kp, int x, int j, ty
         ffull[(9 + i) * n + o] = double(fb[i]) + (MD::kDev ? kp.wa[1][i] * r0b : 0.0);
       }
     }
-    return;
+    return st;
   }
   acc[0] += ra_d * kp.rc.inv_m[0];
   acc[1] += rb_d * kp.rc.inv_m[1];
   acc[2] += double(pxa);
   acc[3] += double(pxb);
+  return st;
+}
+
+// Collision of both species of one node (moment state from node_moments), in
+// place.
+template <class MD>
+__device__ __forceinline__ void node_collide_only(const KParams& kp, typename MD::Ct fa[9], typename MD::Ct fb[9],
+                                                  const NodeState<typename MD::Ct>& st) {
+  using C = typename MD::Ct;
+  using E = E1Traits<C>;
   C we, weps;
-  const C ws = E::rcp(ts);
+  const C ws = E::rcp(st.ts);
   if (kp.rc.bgk) {
     we = weps = ws;
   } else {
     we = C(1.0 / 1.1);    // tau_e = 1.1 (Sec. 3.3)
     weps = C(1.0 / 1.2);  // tau_eps = 1.2
   }
-  const C wd = C(2) * h2, wq = E::rcp(tq);
-  collide_species<C>(fa, ca, rho_a, ux, uy, C(kp.rc.s[0]), we, weps, wd, wq, ws);
-  collide_species<C>(fb, cb, rho_b, ux, uy, C(kp.rc.s[1]), we, weps, wd, wq, ws);
+  const C wd = C(2) * st.h2, wq = E::rcp(st.tq);
+  collide_species<C>(fa, st.ca, st.rho_a, st.ux, st.uy, C(kp.rc.s[0]), we, weps, wd, wq, ws);
+  collide_species<C>(fb, st.cb, st.rho_b, st.ux, st.uy, C(kp.rc.s[1]), we, weps, wd, wq, ws);
+}
+
+// The post-collision pair of each direction of node (x, j) to dst.
+template <class MD, bool NT>
+__device__ __forceinline__ void node_store(const KParams& kp, int x, int j, const typename MD::Ct fa[9],
+                                           const typename MD::Ct fb[9], typename MD::St* __restrict__ dst) {
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     typename MD::Pt v;
@@ -439,6 +467,19 @@ __device__ __forceinline__ void process_node(const KParams& kp, int x, int j, ty
       __builtin_nontemporal_store(v, pair_at<MD>(kp, dst, i, j, x));
     else
       *pair_at<MD>(kp, dst, i, j, x) = v;
+  }
+}
+
+// node_moments, then (STEP) the collision and the store.
+template <class MD, bool EVAL, bool NT = false>
+__device__ __forceinline__ void process_node(const KParams& kp, int x, int j, typename MD::Ct fa[9],
+                                             typename MD::Ct fb[9], typename MD::St* __restrict__ dst,
+                                             double* __restrict__ mom, typename MD::St* __restrict__ fraw,
+                                             double* __restrict__ ffull, double acc[4]) {
+  const NodeState<typename MD::Ct> st = node_moments<MD, EVAL>(kp, x, j, fa, fb, mom, fraw, ffull, acc);
+  if (!EVAL) {
+    node_collide_only<MD>(kp, fa, fb, st);
+    node_store<MD, NT>(kp, x, j, fa, fb, dst);
   }
 }
 
@@ -521,15 +562,17 @@ __device__ __forceinline__ void process_pair(const KParams& kp, int x, int j, in
 // Column sums of one strip (64 columns) of level `step`: add the row-tile
 // partials (the inlet/outlet columns come from their own blocks), store them,
 // and reduce the strip to (min C_l, its column, sum (C_l - C_in), bad flag).
-__device__ void strip_reduce(const KParams& kp, const KBufs& kb, int bx, long long step,
-                             double (*red)[kTY][kTX]) {
-  const int tx = threadIdx.x & (kTX - 1);
-  const int q = threadIdx.x / kTX;  // which sum
+// par: the level's slot in the reduction buffers; nrt: row tiles of the
+// partials. Run by 256 threads (tid = 0..255) with their own red; with
+// valid == false they only meet the barrier.
+__device__ void strip_reduce(const KParams& kp, const KBufs& kb, int bx, long long step, int par, int nrt,
+                             double (*red)[kTY][kTX], int tid, bool valid, bool store_cols = true) {
+  const int tx = tid & (kTX - 1);
+  const int q = tid / kTX;  // which sum
   const int x = bx * kTX + tx;
-  const int par = int(step & 1);
   const bool px = kp.flags & LBSEP_PERIODIC_X;
   double v = 0.0;
-  if (x < kp.nx) {
+  if (valid && x < kp.nx) {
     if (!px && (x == 0 || x == kp.nx - 1)) {
       const int e = x == 0 ? 0 : 1;
       const double* p = kb.endsum + (par * 2 + e) * kMaxEnd * 4 + q;
@@ -545,21 +588,21 @@ __device__ void strip_reduce(const KParams& kp, const KBufs& kb, int bx, long lo
       // loads issued 16 at a time (the partials were just written by other
       // XCDs, so each one is a trip past this XCD's L2); the additions keep
       // their sequential order
-      const double* p = kb.partials + par * kb.part_stride + (long long)q * kp.nrt * kp.pitch + x;
-      for (int b0 = 0; b0 < kp.nrt; b0 += 16) {
+      const double* p = kb.partials + par * kb.part_stride + (long long)q * nrt * kp.pitch + x;
+      for (int b0 = 0; b0 < nrt; b0 += 16) {
         double w[16];
 #pragma unroll
-        for (int k = 0; k < 16; ++k) w[k] = b0 + k < kp.nrt ? p[(long long)(b0 + k) * kp.pitch] : 0.0;
+        for (int k = 0; k < 16; ++k) w[k] = b0 + k < nrt ? p[(long long)(b0 + k) * kp.pitch] : 0.0;
 #pragma unroll
         for (int k = 0; k < 16; ++k)
-          if (b0 + k < kp.nrt) v += w[k];
+          if (b0 + k < nrt) v += w[k];
       }
     }
-    kb.colsum[(long long)q * kp.pitch + x] = v;
+    if (store_cols) kb.colsum[(long long)q * kp.pitch + x] = v;
   }
   red[q][0][tx] = v;
   __syncthreads();
-  if (q == 0) {
+  if (valid && q == 0) {
     double cl = 1e300, dev = 0.0, arg = 1e300;
     double bad = 0.0;
     if (x < kp.nx) {
@@ -596,12 +639,10 @@ __device__ void strip_reduce(const KParams& kp, const KBufs& kb, int bx, long lo
   }
 }
 
-// Record of level `step` from its strip results: CL (Eq. (CL)), C~_l
-// (Eq. (Clline)) and the column of the smallest C_l. Wavefront 0 only.
-__device__ void global_reduce(const KParams& kp, const KBufs& kb, long long step) {
-  if (threadIdx.x >= kTX) return;
-  const int lane = threadIdx.x;
-  const int par = int(step & 1);
+// Record of level `step` from its strip results (slot par): CL (Eq. (CL)),
+// C~_l (Eq. (Clline)) and the column of the smallest C_l. One wavefront.
+__device__ void global_reduce(const KParams& kp, const KBufs& kb, long long step, int par) {
+  const int lane = threadIdx.x & (kTX - 1);
   double cl = 1e300, arg = 1e300, dev = 0.0, bad = 0.0;
   for (int k = lane; k < kp.nxt; k += kTX) {
     const double* st = kb.strip + ((long long)par * kp.nxt + k) * 4;
@@ -639,8 +680,9 @@ __device__ void global_reduce(const KParams& kp, const KBufs& kb, long long step
 // quantity k is left in red[k][0][0]. Every thread reaches every barrier.
 __device__ void block_sum(double (*red)[kTY][kTX], const double* v, int nv) {
   const int tx = threadIdx.x & (kTX - 1);
-  const int w = threadIdx.x / kTX;
-  for (int k = 0; k < nv; ++k) red[k][w][tx] = v[k];
+  const int w = threadIdx.x / kTX;  // wavefronts beyond the fourth only meet the barriers
+  if (w < kTY)
+    for (int k = 0; k < nv; ++k) red[k][w][tx] = v[k];
   __syncthreads();
   const int k = w;  // wavefront w sums quantity k = w (wave-uniform)
   double s = 0.0;
@@ -652,6 +694,45 @@ __device__ void block_sum(double (*red)[kTY][kTX], const double* v, int nv) {
   __syncthreads();
   if (k < nv && tx == 0) red[k][0][0] = s;
   __syncthreads();
+}
+
+// kappa of Eq. (rho2) for end e and both species: sum_j rho'(j) over the whole
+// column from the pulled populations of the two inner layers of state src
+// (Eq. (rho1)), in one fixed order whatever the calling block: thread
+// L < 256 takes (row, species, layer) = (it / 4, (it / 2) % 2, it % 2) for
+// it = L, L + 256, ...; then block_sum. Every thread of the block must call
+// it (barriers); all of them receive kap[s] = kappa and km1[s] = kappa - 1.
+template <class MD>
+__device__ void column_kappa(const KParams& kp, const typename MD::St* __restrict__ src, int e,
+                             double (*red)[kTY][kTX], double kap[2], double km1[2]) {
+  using C = typename MD::Ct;
+  const int l1 = e ? kp.nx - 2 : 1, l2 = e ? kp.nx - 3 : 2;
+  const int col = e ? kp.nx - 1 : 0;
+  double sums[2] = {0.0, 0.0};
+  if (threadIdx.x < kThreads)
+    for (int it = threadIdx.x; it < 4 * kp.ny; it += kThreads) {
+      const int jj = it >> 2, ss = (it >> 1) & 1, ll = it & 1;
+      C h[9];
+      gather1<MD, true>(kp, src, ss, ll ? l2 : l1, jj, h);
+      const double v = double(sum9(h));
+      sums[ss] += ll ? -v : 2.0 * v;
+    }
+  block_sum(red, sums, 2);
+  const double n = double(kp.ny);
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const double sum = red[s][0][0];
+    if (MD::kDev) {
+      // sum_j rho' = n rho0(col) + sum (deviation sums)
+      const double r0 = ref_rho(kp, s, col);
+      km1[s] = (n * (kp.rho_bc[e][s] - r0) - sum) / (n * r0 + sum);
+      kap[s] = 1.0 + km1[s];
+    } else {
+      kap[s] = n * kp.rho_bc[e][s] / sum;
+      km1[s] = kap[s] - 1.0;
+    }
+  }
+  __syncthreads();  // red is reused by the caller
 }
 
 // One block of the fused sweep of a channel, block index b of the channel's
@@ -670,9 +751,9 @@ __device__ __forceinline__ void sweep_block(const KParams& kp, const KBufs& kb,
       if (EVAL) return;
       const int r = b - 2 * kp.nend;
       if (r < kp.nxt) {
-        if (t - 1 >= t_first) strip_reduce(kp, kb, r, t - 1, red);
+        if (t - 1 >= t_first) strip_reduce(kp, kb, r, t - 1, int((t - 1) & 1), kp.nrt, red, threadIdx.x, true);
       } else if (r == kp.nxt) {
-        if (t - 2 >= t_first) global_reduce(kp, kb, t - 2);
+        if (t - 2 >= t_first && threadIdx.x < kTX) global_reduce(kp, kb, t - 2, int((t - 2) & 1));
       }
       return;
     }
@@ -704,34 +785,12 @@ __device__ __forceinline__ void sweep_block(const KParams& kp, const KBufs& kb,
         gather1<MD, true>(kp, src, s, layer ? l2 : l1, j, g);
         if (layer == 0) gather1<MD, true>(kp, src, s, col, j, f);
       }
-      // kappa needs sum_j rho'(col, j) over the whole column: own rows from the
-      // registers, the other end blocks' rows pulled again (sum only)
-      double sums[2] = {0.0, 0.0};
-      if (active) {
-        const double v = double(sum9(g));
-        if (s) sums[1] += layer ? -v : 2.0 * v; else sums[0] += layer ? -v : 2.0 * v;
-      }
-      for (int it = L; it < 4 * kp.ny; it += kThreads) {
-        const int jj = it >> 2;
-        if ((jj >> 6) == blk) continue;
-        const int ss = (it >> 1) & 1, ll = it & 1;
-        C h[9];
-        gather1<MD, true>(kp, src, ss, ll ? l2 : l1, jj, h);
-        const double v = double(sum9(h));
-        if (ss) sums[1] += ll ? -v : 2.0 * v; else sums[0] += ll ? -v : 2.0 * v;
-      }
-      block_sum(red, sums, 2);
-      const double n = double(kp.ny), sum = red[s][0][0];
-      __syncthreads();  // red is reused by the block sum below
-      if (MD::kDev) {
-        // sum_j rho' = n rho0(col) + sum (deviation sums)
-        const double r0 = ref_rho(kp, s, col);
-        km1 = (n * (kp.rho_bc[e][s] - r0) - sum) / (n * r0 + sum);
-        kap = 1.0 + km1;
-      } else {
-        kap = n * kp.rho_bc[e][s] / sum;
-        km1 = kap - 1.0;
-      }
+      // kappa needs sum_j rho'(col, j) over the whole column (pulled again,
+      // in the one order every caller uses)
+      double kk[2], km[2];
+      column_kappa<MD>(kp, src, e, red, kk, km);
+      kap = s ? kk[1] : kk[0];
+      km1 = s ? km[1] : km[0];
       // layer-1 values to the layer-0 lane of the same (row, species)
       C g2[9];
 #pragma unroll
@@ -884,11 +943,11 @@ __global__ __launch_bounds__(kThreads) void k_finalize(KParams kp, KBufs kb, lon
   const int b = blockIdx.x;
   if (phase == 0) {
     if (b < kp.nxt)
-      strip_reduce(kp, kb, b, t, red);
-    else if (t - 1 >= t_first)
-      global_reduce(kp, kb, t - 1);
-  } else {
-    global_reduce(kp, kb, t);
+      strip_reduce(kp, kb, b, t, int(t & 1), kp.nrt, red, threadIdx.x, true);
+    else if (t - 1 >= t_first && threadIdx.x < kTX)
+      global_reduce(kp, kb, t - 1, int((t - 1) & 1));
+  } else if (threadIdx.x < kTX) {
+    global_reduce(kp, kb, t, int(t & 1));
   }
 }
 
