@@ -102,6 +102,9 @@ struct KParams {
   int lead;             // lead blocks (multiple of 8) before the first tile
   int nend;             // blocks per inlet/outlet column (64 rows each)
   long long row;        // elements per row of a state buffer: 18 * pitch
+  int ntx2, nrt2;       // two-level sweep: 62-column tile strips, 6-row tiles
+  int tiles2, chunk2;   // ntx2 * nrt2, ceil(tiles2 / 8)
+  int lead2;            // its lead blocks (multiple of 8)
   unsigned flags;
   double r;             // DBB coefficient
   double rho_bc[2][2];  // [inlet/outlet][species] densities of Eq. (rho2)
@@ -122,6 +125,7 @@ struct KBufs {
   unsigned* status;    // [1] bit 0: non-finite or non-positive column density seen
   long long hist_cap;
   long long part_stride;   // elements of one partials buffer: 4 * nrt * pitch
+  long long part_stride2;  // the same for the two-level sweep's tiles: 4 * nrt2 * pitch
 };
 
 // State buffer layout: row j holds pitch / 64 blocks of 64 columns; block b
@@ -245,6 +249,35 @@ __device__ __forceinline__ void gather1(const KParams& kp, const typename MD::St
   }
 }
 
+// DBB of gather1 for both species of a wall node (bot: the bottom wall):
+// w0, w1, w2 are the node's own leaving pairs (directions 4, 7, 8 at the
+// bottom, 2, 5, 6 at the top); the returning directions of fa, fb are replaced.
+template <class MD>
+__device__ __forceinline__ void dbb_pair(const KParams& kp, bool bot, typename MD::Pt w0, typename MD::Pt w1,
+                                         typename MD::Pt w2, typename MD::Ct fa[9], typename MD::Ct fb[9]) {
+  using C = typename MD::Ct;
+  const C r = C(kp.r);
+  const C q = C(1) - r;
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const C l0 = C(w0[s]), l1 = C(w1[s]), l2 = C(w2[s]);
+    const C F = (l0 + l1) + l2;
+    const C v0 = r * (C(2.0 / 3.0) * F) + q * l0;
+    const C v1 = r * (F * C(1.0 / 6.0)) + q * l1;
+    const C v2 = r * (F * C(1.0 / 6.0)) + q * l2;
+    C* f = s ? fb : fa;
+    if (bot) {
+      f[2] = v0;
+      f[5] = v1;
+      f[6] = v2;
+    } else {
+      f[4] = v0;
+      f[7] = v1;
+      f[8] = v2;
+    }
+  }
+}
+
 // Both species at node (x, j), one 2-element access per direction: the same
 // values as gather1 for s = 0 and s = 1.
 template <class MD, bool PULL>
@@ -291,30 +324,9 @@ __device__ __forceinline__ void gather_pair(const KParams& kp, const typename MD
     }
   }
   if (bot || top) {  // the DBB map of gather1, both species
-    const C r = C(kp.r);
-    const C q = C(1) - r;
     const int o0 = bot ? 4 : 2, o1 = bot ? 7 : 5, o2 = bot ? 8 : 6;
-    const typename MD::Pt w0 = *pair_at<MD>(kp, src, o0, j, x);
-    const typename MD::Pt w1 = *pair_at<MD>(kp, src, o1, j, x);
-    const typename MD::Pt w2 = *pair_at<MD>(kp, src, o2, j, x);
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      const C l0 = C(w0[s]), l1 = C(w1[s]), l2 = C(w2[s]);
-      const C F = (l0 + l1) + l2;
-      const C v0 = r * (C(2.0 / 3.0) * F) + q * l0;
-      const C v1 = r * (F * C(1.0 / 6.0)) + q * l1;
-      const C v2 = r * (F * C(1.0 / 6.0)) + q * l2;
-      C* f = s ? fb : fa;
-      if (bot) {
-        f[2] = v0;
-        f[5] = v1;
-        f[6] = v2;
-      } else {
-        f[4] = v0;
-        f[7] = v1;
-        f[8] = v2;
-      }
-    }
+    dbb_pair<MD>(kp, bot, *pair_at<MD>(kp, src, o0, j, x), *pair_at<MD>(kp, src, o1, j, x),
+                 *pair_at<MD>(kp, src, o2, j, x), fa, fb);
   }
 }
 
@@ -562,11 +574,12 @@ __device__ __forceinline__ void process_pair(const KParams& kp, int x, int j, in
 // Column sums of one strip (64 columns) of level `step`: add the row-tile
 // partials (the inlet/outlet columns come from their own blocks), store them,
 // and reduce the strip to (min C_l, its column, sum (C_l - C_in), bad flag).
-// par: the level's slot in the reduction buffers; nrt: row tiles of the
-// partials. Run by 256 threads (tid = 0..255) with their own red; with
-// valid == false they only meet the barrier.
+// par: the level's slot in the reduction buffers; nrt, stride: row tiles and
+// slot size of the partials. Run by 256 threads (tid = 0..255) with their own
+// red; with valid == false they only meet the barrier.
 __device__ void strip_reduce(const KParams& kp, const KBufs& kb, int bx, long long step, int par, int nrt,
-                             double (*red)[kTY][kTX], int tid, bool valid, bool store_cols = true) {
+                             long long stride, double (*red)[kTY][kTX], int tid, bool valid,
+                             bool store_cols = true) {
   const int tx = tid & (kTX - 1);
   const int q = tid / kTX;  // which sum
   const int x = bx * kTX + tx;
@@ -588,7 +601,7 @@ __device__ void strip_reduce(const KParams& kp, const KBufs& kb, int bx, long lo
       // loads issued 16 at a time (the partials were just written by other
       // XCDs, so each one is a trip past this XCD's L2); the additions keep
       // their sequential order
-      const double* p = kb.partials + par * kb.part_stride + (long long)q * nrt * kp.pitch + x;
+      const double* p = kb.partials + par * stride + (long long)q * nrt * kp.pitch + x;
       for (int b0 = 0; b0 < nrt; b0 += 16) {
         double w[16];
 #pragma unroll
@@ -751,7 +764,7 @@ __device__ __forceinline__ void sweep_block(const KParams& kp, const KBufs& kb,
       if (EVAL) return;
       const int r = b - 2 * kp.nend;
       if (r < kp.nxt) {
-        if (t - 1 >= t_first) strip_reduce(kp, kb, r, t - 1, int((t - 1) & 1), kp.nrt, red, threadIdx.x, true);
+        if (t - 1 >= t_first) strip_reduce(kp, kb, r, t - 1, int((t - 1) & 1), kp.nrt, kb.part_stride, red, threadIdx.x, true);
       } else if (r == kp.nxt) {
         if (t - 2 >= t_first && threadIdx.x < kTX) global_reduce(kp, kb, t - 2, int((t - 2) & 1));
       }
@@ -937,13 +950,304 @@ __global__ void k_batch_advance(long long* counter, long long n) {
 // Completes the records of levels t - 1 and t (reads after the last sweep):
 // phase 0 reduces the strips of level t (blocks 0 .. nxt-1) and finishes level
 // t - 1 (block nxt); phase 1 finishes level t.
+// ---- two time levels per launch ---------------------------------------------
+// k_sweep2 advances the state by nlev = 1 or 2 levels in one launch. A tile of
+// kW2 wavefronts x 64 lanes computes the first level on its rows and columns
+// plus a one-node halo (wavefront w: row 6 by - 1 + w; lane l: column
+// 62 bx + l), keeps those post-collision pairs in LDS in the storage type (the
+// values the next pull would read back from memory), and computes the second
+// level on the 6 x 62 nodes it owns from LDS alone. The inlet and outlet
+// columns couple every row through kappa (Eq. (rho2)): one block per end
+// computes the first level on its four outermost columns for all rows into a
+// third state buffer, takes kappa of the second level from there, and computes
+// the end column's second level; a tile whose halo holds an end column
+// computes that column's first level itself from the same kappa (the same
+// function, the same summation order). Every node therefore goes through the
+// same arithmetic as in two single-level sweeps: the states are bitwise those.
+// The lead blocks reduce the row-tile partials of earlier levels (level lists
+// from the host, four slots by level mod 4).
+constexpr int kW2 = 8;            // wavefronts per block
+constexpr int kT2 = kW2 * kTX;    // threads per block
+constexpr int kR2 = kW2 - 2;      // rows a tile owns
+constexpr int kC2 = kTX - 2;      // columns a tile owns
+
+struct Lv2 {
+  long long t1;        // first level this launch computes (current level + 1)
+  int nlev;            // levels computed: 1 or 2
+  int reduce;          // write row-tile partials and end sums (0: a replay)
+  long long strip[2];  // levels to strip-reduce, -1 = none
+  long long glob[2];   // levels to reduce to a record, -1 = none
+};
+
+// The pulled populations of node (lane l, wavefront w, row j) of a tile from
+// the first level's post-collision pairs in LDS: gather_pair with LDS as the
+// source (same deviation correction, same DBB).
+template <class MD>
+__device__ __forceinline__ void lds_gather(const KParams& kp, const typename MD::Pt (*lds)[9][kTX], int l, int w,
+                                           int j, typename MD::Ct fa[9], typename MD::Ct fb[9]) {
+  using C = typename MD::Ct;
+  const bool bot = j == 0, top = j == kp.ny - 1;
+  const int wm = bot ? w : w - 1, wp = top ? w : w + 1;  // the wall-crossing loads are discarded
+  const int sl[9] = {l, l - 1, l, l + 1, l, l - 1, l + 1, l + 1, l - 1};
+  const int sw[9] = {w, w, wm, w, wp, wm, wm, wp, wp};
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const typename MD::Pt v = lds[sw[i]][i][sl[i]];
+    fa[i] = C(v[0]);
+    fb[i] = C(v[1]);
+    if (MD::kDev && (i == 1 || i == 3 || i >= 5)) {
+      fa[i] += C(kp.corr[0][i]);
+      fb[i] += C(kp.corr[1][i]);
+    }
+  }
+  if (bot || top) {
+    const int o0 = bot ? 4 : 2, o1 = bot ? 7 : 5, o2 = bot ? 8 : 6;
+    dbb_pair<MD>(kp, bot, lds[w][o0][l], lds[w][o1][l], lds[w][o2][l], fa, fb);
+  }
+}
+
+// Sum over the kW2 wavefronts of quantity q per lane, first four quantities
+// (red[q][w][lane] written by every wavefront beforehand; fixed order).
+__device__ __forceinline__ double wave_column_sum(const double (*red)[kW2][kTX], int q, int lane, int w0, int w1) {
+  double v = 0.0;
+  for (int w = w0; w <= w1; ++w) v += red[q][w][lane];
+  return v;
+}
+
+// Rebuilt pre-collision populations of species s at row j of the end column of
+// end e, pulled from state src (the end-block arithmetic of the single-level
+// sweep: the node and its two inner layers, then end_rebuild).
+template <class MD>
+__device__ __forceinline__ void end_node(const KParams& kp, const typename MD::St* __restrict__ src, int e, int s,
+                                         double kap, double km1, int j, typename MD::Ct f[9]) {
+  using C = typename MD::Ct;
+  const int col = e ? kp.nx - 1 : 0, l1 = e ? kp.nx - 2 : 1, l2 = e ? kp.nx - 3 : 2;
+  C g1[9], g2[9];
+  gather1<MD, true>(kp, src, s, col, j, f);
+  gather1<MD, true>(kp, src, s, l1, j, g1);
+  gather1<MD, true>(kp, src, s, l2, j, g2);
+  end_rebuild<MD>(kp, e, s, col, kap, km1, g1, g2, f);
+}
+
+// Inlet (e = 0) or outlet (e = 1) block of k_sweep2.
+template <class MD, bool NT>
+__device__ void end_block2(const KParams& kp, const KBufs& kb, const Lv2& lv, const typename MD::St* __restrict__ src,
+                           typename MD::St* __restrict__ dst, typename MD::St* __restrict__ scr, int e,
+                           double (*red)[kW2][kTX], double (*redk)[kTY][kTX]) {
+  using C = typename MD::Ct;
+  if (lv.nlev == 0) return;  // a reductions-only launch
+  const int sgn = e ? -1 : 1, col = e ? kp.nx - 1 : 0;
+  double kap[2], km1[2];
+  column_kappa<MD>(kp, src, e, redk, kap, km1);
+  double acc[2][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};  // end column, levels t1, t1 + 1
+  // first level: the end column (rebuilt) and, with two levels, the next three
+  // columns (into scr, for the second level's kappa and end column)
+  const int ncol = lv.nlev == 2 ? 4 : 1;
+  for (int task = threadIdx.x; task < ncol * kp.ny; task += kT2) {
+    const int c = task % ncol, j = task / ncol;
+    const int x = col + sgn * c;
+    C fa[9], fb[9];
+    if (c == 0) {
+      end_node<MD>(kp, src, e, 0, kap[0], km1[0], j, fa);
+      end_node<MD>(kp, src, e, 1, kap[1], km1[1], j, fb);
+    } else {
+      gather_pair<MD, true>(kp, src, x, j, fa, fb);
+    }
+    double tmp[4] = {0.0, 0.0, 0.0, 0.0};
+    const NodeState<C> st = node_moments<MD, false>(kp, x, j, fa, fb, nullptr, nullptr, nullptr, tmp);
+    if (c == 0)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[0][q] += tmp[q];
+    node_collide_only<MD>(kp, fa, fb, st);
+    if (lv.nlev == 2)
+      node_store<MD, false>(kp, x, j, fa, fb, scr);
+    else
+      node_store<MD, NT>(kp, x, j, fa, fb, dst);
+  }
+  if (lv.nlev == 2) {
+    __threadfence();  // the first level's columns, visible to the whole block
+    __syncthreads();
+    column_kappa<MD>(kp, scr, e, redk, kap, km1);
+    for (int j = threadIdx.x; j < kp.ny; j += kT2) {
+      C fa[9], fb[9];
+      end_node<MD>(kp, scr, e, 0, kap[0], km1[0], j, fa);
+      end_node<MD>(kp, scr, e, 1, kap[1], km1[1], j, fb);
+      double tmp[4] = {0.0, 0.0, 0.0, 0.0};
+      const NodeState<C> st = node_moments<MD, false>(kp, col, j, fa, fb, nullptr, nullptr, nullptr, tmp);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[1][q] += tmp[q];
+      node_collide_only<MD>(kp, fa, fb, st);
+      node_store<MD, NT>(kp, col, j, fa, fb, dst);
+    }
+  }
+  if (!lv.reduce) return;  // uniform over the block
+  // end sums: per lane over the wavefronts, then over the lanes (fixed order);
+  // the whole column goes to end block 0 of the level's slot, zeros to the rest
+  const int lane = threadIdx.x & (kTX - 1), w = threadIdx.x / kTX;
+  for (int lev = 0; lev < lv.nlev; ++lev) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) red[q][w][lane] = acc[lev][q];
+    __syncthreads();
+    if (w < 4) {
+      double v = wave_column_sum(red, w, lane, 0, kW2 - 1);
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+      const long long level = lv.t1 + lev;
+      double* es = kb.endsum + ((long long)(level & 3) * 2 + e) * kMaxEnd * 4;
+      if (lane == 0) es[w] = v;
+      for (int blk = 1 + lane; blk < kp.nend; blk += kTX) es[blk * 4 + w] = 0.0;
+    }
+    __syncthreads();
+  }
+}
+
+// Tile of k_sweep2 (see above).
+template <class MD, bool NT>
+__device__ void tile2(const KParams& kp, const KBufs& kb, const Lv2& lv, const typename MD::St* __restrict__ src,
+                      typename MD::St* __restrict__ dst, int b, typename MD::Pt (*lds)[9][kTX],
+                      double (*red)[kW2][kTX], double (*redk)[kTY][kTX]) {
+  using C = typename MD::Ct;
+  const int xcd = b & 7;
+  const int k = (b - kp.lead2) >> 3;
+  const int lin = xcd * kp.chunk2 + k;
+  if (lin >= kp.tiles2) return;  // uniform over the block
+  const int by = lin / kp.ntx2, bx = lin - by * kp.ntx2;
+  const int lane = threadIdx.x & (kTX - 1);
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kTX);
+  const int x0 = 1 + kC2 * bx;
+  const int x = x0 - 1 + lane;
+  const int j = by * kR2 - 1 + w;
+  const bool in_j = j >= 0 && j < kp.ny;
+  const bool valid = x < kp.nx && in_j;
+  const bool has_in = bx == 0;                 // lane 0 is the inlet column
+  const bool has_out = x0 + kC2 >= kp.nx - 1;  // some lane is the outlet column
+  const bool own_x = lane >= 1 && lane <= kC2 && x <= kp.nx - 2;
+  const bool own = own_x && w >= 1 && w <= kR2 && j < kp.ny;
+  double kin[2] = {1.0, 1.0}, kin1[2] = {0.0, 0.0}, kout[2] = {1.0, 1.0}, kout1[2] = {0.0, 0.0};
+  if (has_in) column_kappa<MD>(kp, src, 0, redk, kin, kin1);
+  if (has_out) column_kappa<MD>(kp, src, 1, redk, kout, kout1);
+  // ---- first level: own nodes and halo
+  C fa[9], fb[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) fa[i] = fb[i] = C(0);
+  if (valid) gather_pair<MD, true>(kp, src, x, j, fa, fb);
+  if (has_in || has_out) {
+    // the inner layers' pulled populations to the end lanes: lanes + 1, + 2
+    // (inlet) or - 1, - 2 (outlet) of the same row
+    const bool is_in = has_in && lane == 0 && in_j;
+    const bool is_out = has_out && x == kp.nx - 1 && in_j;
+    // species by species: the inner layers' pulled values first, for both
+    C g1[2][9], g2[2][9];
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        const C v = s ? fb[i] : fa[i];
+        const C d1 = __shfl_down(v, 1), d2 = __shfl_down(v, 2);
+        const C u1 = __shfl_up(v, 1), u2 = __shfl_up(v, 2);
+        g1[s][i] = is_out ? u1 : d1;
+        g2[s][i] = is_out ? u2 : d2;
+      }
+    if (is_in) {
+      end_rebuild<MD>(kp, 0, 0, 0, kin[0], kin1[0], g1[0], g2[0], fa);
+      end_rebuild<MD>(kp, 0, 1, 0, kin[1], kin1[1], g1[1], g2[1], fb);
+    }
+    if (is_out) {
+      end_rebuild<MD>(kp, 1, 0, kp.nx - 1, kout[0], kout1[0], g1[0], g2[0], fa);
+      end_rebuild<MD>(kp, 1, 1, kp.nx - 1, kout[1], kout1[1], g1[1], g2[1], fb);
+    }
+  }
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  if (valid) {
+    double tmp[4] = {0.0, 0.0, 0.0, 0.0};
+    const NodeState<C> st = node_moments<MD, false>(kp, x, j, fa, fb, nullptr, nullptr, nullptr, tmp);
+    if (own)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] = tmp[q];
+    node_collide_only<MD>(kp, fa, fb, st);
+  }
+  if (lv.nlev == 2) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      typename MD::Pt v;
+      v[0] = typename MD::St(fa[i]);
+      v[1] = typename MD::St(fb[i]);
+      lds[w][i][lane] = v;
+    }
+  } else if (own) {
+    node_store<MD, NT>(kp, x, j, fa, fb, dst);
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) red[q][w][lane] = acc[q];
+  __syncthreads();
+  if (lv.reduce && w < 4 && own_x) {
+    const long long level = lv.t1;
+    kb.partials[(level & 3) * kb.part_stride2 + ((long long)w * kp.nrt2 + by) * kp.pitch + x] =
+        wave_column_sum(red, w, lane, 1, kR2);
+  }
+  if (lv.nlev == 1) return;  // uniform over the block
+  // ---- second level: own nodes from LDS
+#pragma unroll
+  for (int q = 0; q < 4; ++q) acc[q] = 0.0;
+  if (own) {
+    C ha[9], hb[9];
+    lds_gather<MD>(kp, lds, lane, w, j, ha, hb);
+    double tmp[4] = {0.0, 0.0, 0.0, 0.0};
+    const NodeState<C> st = node_moments<MD, false>(kp, x, j, ha, hb, nullptr, nullptr, nullptr, tmp);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = tmp[q];
+    node_collide_only<MD>(kp, ha, hb, st);
+    node_store<MD, NT>(kp, x, j, ha, hb, dst);
+  }
+  __syncthreads();  // the first level's sums are read
+#pragma unroll
+  for (int q = 0; q < 4; ++q) red[q][w][lane] = acc[q];
+  __syncthreads();
+  if (lv.reduce && w < 4 && own_x) {
+    const long long level = lv.t1 + 1;
+    kb.partials[(level & 3) * kb.part_stride2 + ((long long)w * kp.nrt2 + by) * kp.pitch + x] =
+        wave_column_sum(red, w, lane, 1, kR2);
+  }
+}
+
+template <class MD, bool NT>
+__global__ __launch_bounds__(kT2) void k_sweep2(KParams kp, KBufs kb, Lv2 lv, const typename MD::St* __restrict__ src,
+                                                typename MD::St* __restrict__ dst, typename MD::St* __restrict__ scr) {
+  __shared__ typename MD::Pt lds[kW2][9][kTX];
+  __shared__ double red[4][kW2][kTX];
+  double (*redk)[kTY][kTX] = reinterpret_cast<double (*)[kTY][kTX]>(&red[0][0][0]);
+  const int b = blockIdx.x;
+  if (b < kp.lead2) {
+    if (b < 2) {
+      if (!(kp.flags & LBSEP_PERIODIC_X)) end_block2<MD, NT>(kp, kb, lv, src, dst, scr, b, red, redk);
+      return;
+    }
+    const int r = b - 2;
+    if (r < kp.nxt) {
+      // strip reductions in two 256-thread groups, task = (level, strip)
+      const int g = threadIdx.x / kThreads;
+      const int task = 2 * r + g;
+      const int li = task / kp.nxt, bx = task - li * kp.nxt;
+      const long long level = li < 2 ? lv.strip[li] : -1;
+      const bool last = li == 1 || lv.strip[1] < 0;  // the latest level keeps the column sums
+      strip_reduce(kp, kb, bx, level, int(level & 3), kp.nrt2, kb.part_stride2, redk + 4 * g,
+                   threadIdx.x & (kThreads - 1), level >= 0, last);
+    } else if (r == kp.nxt) {
+      const int w = threadIdx.x / kTX;
+      if (w < 2 && lv.glob[w] >= 0) global_reduce(kp, kb, lv.glob[w], int(lv.glob[w] & 3));
+    }
+    return;
+  }
+  tile2<MD, NT>(kp, kb, lv, src, dst, b, lds, red, redk);
+}
+
 __global__ __launch_bounds__(kThreads) void k_finalize(KParams kp, KBufs kb, long long t, long long t_first,
                                                        int phase) {
   __shared__ double red[4][kTY][kTX];
   const int b = blockIdx.x;
   if (phase == 0) {
     if (b < kp.nxt)
-      strip_reduce(kp, kb, b, t, int(t & 1), kp.nrt, red, threadIdx.x, true);
+      strip_reduce(kp, kb, b, t, int(t & 1), kp.nrt, kb.part_stride, red, threadIdx.x, true);
     else if (t - 1 >= t_first && threadIdx.x < kTX)
       global_reduce(kp, kb, t - 1, int((t - 1) & 1));
   } else if (threadIdx.x < kTX) {
@@ -1082,7 +1386,9 @@ struct Layout {
   int pitch, nxt, ntx, nrt, rpt, tiles, chunk, lead, nend;
   bool split;
   bool big;  // a state buffer exceeds half the last-level cache: row-major tiles, non-temporal stores
-  size_t elem, state_buf, f0, f1, partials, endsum, colsum, strip, hist, status, mom, total;
+  bool two;  // two time levels per launch (k_sweep2)
+  int ntx2, nrt2, tiles2, chunk2, lead2;
+  size_t elem, state_buf, f0, f1, f2, partials, endsum, colsum, strip, hist, status, mom, total;
 };
 
 bool validate(const lbsep_params* p, std::string& why) {
@@ -1114,6 +1420,8 @@ bool validate(const lbsep_params* p, std::string& why) {
   if (p->tile_mode < LBSEP_TILE_AUTO || p->tile_mode > LBSEP_TILE_NODE) return why = "bad tile_mode", false;
   if (p->tile_rows != 0 && p->tile_rows != 1 && p->tile_rows != 2 && p->tile_rows != 4)
     return why = "tile_rows must be 0, 1, 2 or 4", false;
+  if (p->fused_steps < 0 || p->fused_steps > 2) return why = "fused_steps must be 0, 1 or 2", false;
+  if (p->fused_steps == 2 && (px || py)) return why = "fused_steps = 2 needs an inlet, an outlet and walls", false;
   return true;
 }
 
@@ -1156,19 +1464,30 @@ Layout make_layout(const lbsep_params* p) {
   L.lead = (int)align_up((size_t)(2 * L.nend + L.nxt + 1), 8);
   L.state_buf = align_up(18ull * p->ny * L.pitch * L.elem, 256);
   L.big = !L.split && L.state_buf > (128ull << 20);
+  // two levels per launch: tiles own 62 columns x 6 rows of the interior
+  L.two = p->fused_steps == 2;
+  L.ntx2 = (p->nx - 2 + kC2 - 1) / kC2;
+  L.nrt2 = (p->ny + kR2 - 1) / kR2;
+  L.tiles2 = L.ntx2 * L.nrt2;
+  L.chunk2 = (L.tiles2 + 7) / 8;
+  L.lead2 = (int)align_up((size_t)(2 + L.nxt + 1), 8);
   size_t off = 0;
   L.f0 = off;
   off += L.state_buf;
   L.f1 = off;
   off += L.state_buf;
+  L.f2 = off;  // the two-level sweep's end columns, and the replayed level for readouts
+  if (L.two) off += L.state_buf;
+  // reduction buffers: two slots (by level parity) for single-level launches,
+  // four (level mod 4) for two-level launches
   L.partials = off;
-  off += align_up(2ull * 4 * L.nrt * L.pitch * sizeof(double), 256);
+  off += align_up(std::max(2ull * 4 * L.nrt, L.two ? 4ull * 4 * L.nrt2 : 0ull) * L.pitch * sizeof(double), 256);
   L.endsum = off;
-  off += align_up(2ull * 2 * kMaxEnd * 4 * sizeof(double), 256);
+  off += align_up(4ull * 2 * kMaxEnd * 4 * sizeof(double), 256);
   L.colsum = off;
   off += align_up(4ull * L.pitch * sizeof(double), 256);
   L.strip = off;
-  off += align_up(2ull * 4 * L.nxt * sizeof(double), 256);
+  off += align_up(4ull * 4 * L.nxt * sizeof(double), 256);
   L.hist = off;
   off += align_up(4ull * p->hist_cap * sizeof(double), 256);
   L.status = off;
@@ -1198,6 +1517,12 @@ struct lbsep_channel {
   int64_t t;
   int64_t t_first;  // first level with a history record
   bool finalized;   // records of levels t-1 and t are complete
+  // two levels per launch
+  void* f2;           // third state buffer
+  int prev_buf;       // buffer holding f'(t-1) for readouts: 0, 1, 2 (f2), -1: not held (replay first)
+  int64_t strip_next;  // levels below are strip-reduced
+  int64_t glob_next;   // levels below have their record
+  bool pipe2;          // levels since the last set / init came from two-level launches
 };
 
 namespace {
@@ -1241,31 +1566,105 @@ void sweep_any(lbsep_channel* h, const void* src, void* dst, double* mom, void* 
   }
 }
 
+template <class MD>
+void launch_sweep2_md(lbsep_channel* h, const Lv2& lv, int grid, const void* src, void* dst) {
+  using S = typename MD::St;
+  if (h->L.big)
+    hipLaunchKernelGGL((k_sweep2<MD, true>), dim3(grid), dim3(kT2), 0, h->stream, h->kp, h->kb, lv,
+                       static_cast<const S*>(src), static_cast<S*>(dst), static_cast<S*>(h->f2));
+  else
+    hipLaunchKernelGGL((k_sweep2<MD, false>), dim3(grid), dim3(kT2), 0, h->stream, h->kp, h->kb, lv,
+                       static_cast<const S*>(src), static_cast<S*>(dst), static_cast<S*>(h->f2));
+}
+
+// k_sweep2 over the whole grid, or (nlev == 0) its lead blocks only.
+void launch_sweep2(lbsep_channel* h, const Lv2& lv, const void* src, void* dst) {
+  const int grid = lv.nlev == 0 ? h->L.lead2 : h->L.lead2 + 8 * h->L.chunk2;
+  switch (h->p.dtype) {
+    case LBSEP_F64:
+      launch_sweep2_md<ModeF64>(h, lv, grid, src, dst);
+      break;
+    case LBSEP_F32:
+      launch_sweep2_md<ModeF32>(h, lv, grid, src, dst);
+      break;
+    default:
+      launch_sweep2_md<ModeF16>(h, lv, grid, src, dst);
+      break;
+  }
+}
+
+// Level lists of a two-level launch: strip-reduce the levels not yet
+// strip-reduced, reduce to records those strip-reduced before.
+Lv2 pending_levels(const lbsep_channel* h, int nlev, int reduce) {
+  Lv2 lv{};
+  lv.t1 = h->t + 1;
+  lv.nlev = nlev;
+  lv.reduce = reduce;
+  lv.strip[0] = lv.strip[1] = lv.glob[0] = lv.glob[1] = -1;
+  int k = 0;
+  for (int64_t l = h->strip_next; l <= h->t && k < 2; ++l) lv.strip[k++] = l;
+  k = 0;
+  for (int64_t l = h->glob_next; l < h->strip_next && k < 2; ++l) lv.glob[k++] = l;
+  return lv;
+}
+
+int finalize(lbsep_channel* h);
+
 // Collide the pre-collision state held in f[0] into f[1] at level t.
 int collide_loaded(lbsep_channel* h, int64_t t) {
   h->t_first = t;
   sweep_any<false, false>(h, h->f[0], h->f[1], nullptr, nullptr, nullptr, t);
   h->cur = 1;
   h->prev_pre = true;
+  h->prev_buf = 0;
   h->t = t;
   h->finalized = false;
-  return check_hip(hipGetLastError(), "collide launch");
+  h->pipe2 = false;
+  int rc = check_hip(hipGetLastError(), "collide launch");
+  if (rc == LBSEP_OK && h->L.two) {
+    // complete the record of level t with the single-level reductions, so the
+    // two-level pipeline starts with nothing pending
+    rc = finalize(h);
+    h->strip_next = h->glob_next = t + 1;
+  }
+  return rc;
 }
 
-// Complete the records of the last two levels (idempotent).
+// Complete the records of the last levels (idempotent).
 int finalize(lbsep_channel* h) {
   if (h->finalized) return LBSEP_OK;
-  hipLaunchKernelGGL(k_finalize, dim3(h->L.nxt + 1), dim3(kThreads), 0, h->stream, h->kp, h->kb,
-                     (long long)h->t, (long long)h->t_first, 0);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, h->stream, h->kp, h->kb, (long long)h->t,
-                     (long long)h->t_first, 1);
+  if (h->pipe2) {
+    Lv2 lv = pending_levels(h, 0, 0);
+    launch_sweep2(h, lv, nullptr, nullptr);
+    h->glob_next = h->strip_next;
+    h->strip_next = h->t + 1;
+    lv = pending_levels(h, 0, 0);
+    launch_sweep2(h, lv, nullptr, nullptr);
+    h->glob_next = h->strip_next;
+  } else {
+    hipLaunchKernelGGL(k_finalize, dim3(h->L.nxt + 1), dim3(kThreads), 0, h->stream, h->kp, h->kb,
+                       (long long)h->t, (long long)h->t_first, 0);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, h->stream, h->kp, h->kb, (long long)h->t,
+                       (long long)h->t_first, 1);
+  }
   h->finalized = true;
   return check_hip(hipGetLastError(), "finalize launch");
 }
 
 // EVAL sweep of the current state into mom, fraw and/or ffull.
 int eval_state(lbsep_channel* h, double* mom, void* fraw, double* ffull) {
-  const void* prev = h->f[1 - h->cur];
+  if (h->prev_buf < 0) {
+    // the last launch advanced two levels: recompute f'(t-1) from f'(t-2)
+    // (held by the other buffer) into f2, without reductions
+    Lv2 lv{};
+    lv.t1 = h->t - 1;
+    lv.nlev = 1;
+    lv.reduce = 0;
+    lv.strip[0] = lv.strip[1] = lv.glob[0] = lv.glob[1] = -1;
+    launch_sweep2(h, lv, h->f[1 - h->cur], h->f2);
+    h->prev_buf = 2;
+  }
+  const void* prev = h->prev_buf == 2 ? h->f2 : h->f[h->prev_buf];
   if (h->prev_pre)
     sweep_any<false, true>(h, prev, nullptr, mom, fraw, ffull, h->t);
   else
@@ -1335,6 +1734,7 @@ int lbsep_init(const lbsep_params* p, void* dev_ws, size_t ws_bytes, void* hip_s
   h->ws = static_cast<char*>(dev_ws);
   h->f[0] = h->ws + L.f0;
   h->f[1] = h->ws + L.f1;
+  h->f2 = L.two ? h->ws + L.f2 : nullptr;
   h->mom = reinterpret_cast<double*>(h->ws + L.mom);
 
   KParams& kp = h->kp;
@@ -1353,6 +1753,11 @@ int lbsep_init(const lbsep_params* p, void* dev_ws, size_t ws_bytes, void* hip_s
   kp.lead = L.lead;
   kp.nend = L.nend;
   kp.row = 18LL * L.pitch;
+  kp.ntx2 = L.ntx2;
+  kp.nrt2 = L.nrt2;
+  kp.tiles2 = L.tiles2;
+  kp.chunk2 = L.chunk2;
+  kp.lead2 = L.lead2;
   kp.flags = p->flags | (h->L.split ? 0u : kRowMajorTiles);
   kp.r = p->dbb_r;
   kp.cl_in = p->cl_in;
@@ -1400,6 +1805,7 @@ int lbsep_init(const lbsep_params* p, void* dev_ws, size_t ws_bytes, void* hip_s
   kb.status = reinterpret_cast<unsigned*>(h->ws + L.status);
   kb.hist_cap = p->hist_cap;
   kb.part_stride = 4LL * L.nrt * L.pitch;
+  kb.part_stride2 = 4LL * L.nrt2 * L.pitch;
 
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(256), 0, h->stream, kb.status, 1);
   switch (p->dtype) {
@@ -1426,9 +1832,28 @@ int lbsep_init(const lbsep_params* p, void* dev_ws, size_t ws_bytes, void* hip_s
 int lbsep_step(lbsep_channel* h, int64_t nsteps) {
   if (!h) return fail(LBSEP_EINVAL, "channel is NULL");
   if (nsteps < 0) return fail(LBSEP_EINVAL, "nsteps must be >= 0");
+  if (h->L.two) {
+    for (int64_t n = nsteps; n > 0;) {
+      const int nlev = n >= 2 ? 2 : 1;
+      const int nxt_buf = 1 - h->cur;
+      const Lv2 lv = pending_levels(h, nlev, 1);
+      launch_sweep2(h, lv, h->f[h->cur], h->f[nxt_buf]);
+      h->pipe2 = true;
+      h->glob_next = h->strip_next;
+      h->strip_next = h->t + 1;
+      h->prev_buf = nlev == 2 ? -1 : h->cur;
+      h->cur = nxt_buf;
+      h->prev_pre = false;
+      h->t += nlev;
+      h->finalized = false;
+      n -= nlev;
+    }
+    return check_hip(hipGetLastError(), "step launch");
+  }
   for (int64_t n = 0; n < nsteps; ++n) {
     const int nxt_buf = 1 - h->cur;
     sweep_any<true, false>(h, h->f[h->cur], h->f[nxt_buf], nullptr, nullptr, nullptr, (long long)(h->t + 1));
+    h->prev_buf = h->cur;
     h->cur = nxt_buf;
     h->prev_pre = false;
     h->t += 1;
@@ -1652,6 +2077,7 @@ int batch_layout(lbsep_channel* const* chans, int n, BatchLayout& B) {
       if (chans[k] == chans[i]) return fail(LBSEP_EINVAL, "a channel appears twice in the batch");
     if (chans[i]->p.dtype != chans[0]->p.dtype) return fail(LBSEP_EINVAL, "all channels of a batch share one dtype");
     if (chans[i]->stream != chans[0]->stream) return fail(LBSEP_EINVAL, "all channels of a batch share one stream");
+    if (chans[i]->L.two) return fail(LBSEP_EINVAL, "batch members step one level per launch (fused_steps != 2)");
     const long long nb = (long long)chans[i]->L.lead + 8LL * chans[i]->L.chunk;
     if (B.blocks + nb > (1LL << 30)) return fail(LBSEP_EINVAL, "batch grid too large");
     B.blocks += (int)nb;
@@ -1809,6 +2235,7 @@ int lbsep_batch_step(lbsep_batch* b, int64_t nsteps) {
     c->cur = (c->cur + (int)(nsteps & 1)) & 1;
     if (nsteps > 0) {
       c->prev_pre = false;
+      c->prev_buf = 1 - c->cur;
       c->finalized = false;
     }
     b->t_expect[i] = c->t;

@@ -40,7 +40,7 @@ class Params(ctypes.Structure):
         ("theta", c_double), ("kn_out", c_double),
         ("dbb_r", c_double), ("accom", c_double), ("tau_bgk", c_double),
         ("flags", c_uint32), ("dtype", c_int32), ("hist_cap", c_int32), ("tile_mode", c_int32),
-        ("tile_rows", c_int32),
+        ("tile_rows", c_int32), ("fused_steps", c_int32),
     ]
 
 
@@ -107,11 +107,11 @@ def _check(rc: int):
 
 
 def make_params(nx, ny, m_a, m_b, cl_in, cl_out, theta, kn_out, dbb_r, accom=1.0, tau_bgk=0.0,
-                flags=0, dtype="f64", hist_cap=4096, tile_mode=TILE_AUTO, tile_rows=0) -> Params:
+                flags=0, dtype="f64", hist_cap=4096, tile_mode=TILE_AUTO, tile_rows=0, fused_steps=0) -> Params:
     return Params(int(nx), int(ny), float(m_a), float(m_b), float(cl_in), float(cl_out), float(theta),
                   float(kn_out), float(dbb_r), float(accom), float(tau_bgk), int(flags),
                   _DTYPES[dtype] if isinstance(dtype, str) else int(dtype), int(hist_cap), int(tile_mode),
-                  int(tile_rows))
+                  int(tile_rows), int(fused_steps))
 
 
 def workspace_bytes(params: Params) -> int:

@@ -1,0 +1,120 @@
+"""Two time levels per launch (fused_steps = 2) against single-level launches.
+
+Each node of a two-level launch goes through the same arithmetic as in two
+single-level sweeps (the first level kept in LDS in the storage type, kappa
+of Eq. (rho2) summed in the same order), so the states must agree bitwise;
+CL, the C_l profile and the history come from column sums grouped by other
+tiles and agree to rounding. Readouts and checkpoints right after a
+two-level launch recompute the level before; they must agree bitwise too.
+The FP64 two-level path is also checked against the oracle directly."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import binary_lbm as O
+from paper_1603_08221_amd import lbsep
+from paper_1603_08221_amd.workloads import CONFIGS, HE_AR, NE_AR, Workload
+
+from gpu_helpers import assert_argmin, assert_cl, assert_moments, oracle_params, r_of
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+# (nx, ny): one tile; ragged tiles in x and y; several tiles; more than 64 rows
+# (several end blocks in the single-level sweep); the smallest channel (both
+# ends in one tile)
+SHAPES = [(80, 8), (150, 13), (517, 24), (200, 70), (6, 7)]
+
+
+def _params(w, fused, dtype, hist_cap=512):
+    return lbsep.make_params(w.nx, w.ny, w.m_a, w.m_b, w.cl_in, w.cl_out, w.theta, w.kn_out, r_of(w),
+                             dtype=dtype, hist_cap=hist_cap, fused_steps=fused)
+
+
+def _pair(w, dtype):
+    return lbsep.Channel(_params(w, 1, dtype)), lbsep.Channel(_params(w, 2, dtype))
+
+
+def _agree(a, b, what, dtype="f64"):
+    assert a.t == b.t, what
+    if dtype == "f16":
+        # the compiler may fuse the last float FMA of the collision with the
+        # conversion to binary16 on one code path and not the other: the runs
+        # then agree to the FP16 error level only
+        torch.testing.assert_close(b.get_post_collision(), a.get_post_collision(), rtol=0, atol=2e-4)
+        torch.testing.assert_close(b.get_populations(), a.get_populations(), rtol=0, atol=2e-4)
+        assert abs(a.read_cl()["cl"] - b.read_cl()["cl"]) < 5e-3, what
+        return
+    assert torch.equal(a.get_post_collision(), b.get_post_collision()), f"{what}: post-collision state"
+    assert torch.equal(a.get_populations(), b.get_populations()), f"{what}: pre-collision populations"
+    ca, cb = a.read_cl(profile=True), b.read_cl(profile=True)
+    # CL = (C_in - min C_l) / C_in: rounding of C_l is absolute, ~1e-16
+    assert abs(ca["cl"] - cb["cl"]) <= 1e-12 * abs(ca["cl"]) + 1e-14, what
+    np.testing.assert_allclose(cb["profile"], ca["profile"], rtol=1e-13, atol=0, err_msg=what)
+    assert_argmin(cb["x_min"], ca["profile"], 1e-12)
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=[f"{s[0]}x{s[1]}" for s in SHAPES])
+@pytest.mark.parametrize("dtype", ["f64", "f32", "f16"])
+def test_two_levels_per_launch_match_single_levels(dtype, shape):
+    w = Workload("fused", shape[0], shape[1], *NE_AR, 0.3, 0.6, 2.5, 0.08, 0)
+    a, b = _pair(w, dtype)
+    _agree(a, b, "initial state", dtype)
+    for n in (2, 1, 3, 6, 40):  # odd counts end with a single-level launch
+        a.step(n)
+        b.step(n)
+        _agree(a, b, f"t = {a.t}", dtype)
+    if dtype == "f16":
+        return
+    t0 = max(1, a.t - 50)
+    ha, hb = a.read_history(t0, a.t - t0 + 1), b.read_history(t0, b.t - t0 + 1)
+    np.testing.assert_array_equal(ha[:, 0], hb[:, 0])
+    np.testing.assert_allclose(hb[:, 1:3], ha[:, 1:3], rtol=1e-11, atol=1e-14)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_checkpoint_after_a_two_level_launch_resumes_bitwise(dtype):
+    w = CONFIGS["he_ar_8x80"].with_(nx=130, ny=20)
+    a = lbsep.Channel(_params(w, 2, dtype))
+    a.step(10)  # ends on a two-level launch
+    snap, t = a.get_state(), a.t
+    a.step(8)
+    b = lbsep.Channel(_params(w, 2, dtype))
+    b.set_state(snap, t)
+    b.step(8)
+    assert torch.equal(a.get_post_collision(), b.get_post_collision())
+    assert a.read_cl()["cl"] == b.read_cl()["cl"]
+    # the same checkpoint resumed by single-level launches: same states
+    c = lbsep.Channel(_params(w, 1, dtype))
+    c.set_state(snap, t)
+    c.step(8)
+    assert torch.equal(a.get_post_collision(), c.get_post_collision())
+
+
+def test_moments_after_a_two_level_launch():
+    w = CONFIGS["he_ar_8x80"].with_(nx=100, ny=12)
+    a, b = _pair(w, "f64")
+    a.step(12)
+    b.step(12)
+    np.testing.assert_array_equal(a.read_moments(), b.read_moments())
+    np.testing.assert_array_equal(a.read_volume_flow(), b.read_volume_flow())
+
+
+def test_fp64_two_level_path_against_the_oracle():
+    w = CONFIGS["he_ar_8x80"]
+    r = r_of(w)
+    ch = lbsep.Channel(_params(w, 2, "f64", hist_cap=4096))
+    ch.step(2000)
+    p = oracle_params(w, r)
+    f, _ = O.run(p, 2000)
+    assert_moments(ch.read_moments(), O.moment_fields(f, p), TOL64, "fused, 2000 steps")
+    assert_cl(ch.read_cl()["cl"], O.diagnostics(f, p).cl, 0.0, 1e-12)
+
+
+def test_two_level_channels_do_not_join_a_batch():
+    w = CONFIGS["he_ar_8x80"]
+    a = lbsep.Channel(_params(w, 1, "f32"))
+    b = lbsep.Channel(_params(w, 2, "f32"))
+    with pytest.raises(lbsep.LbsepError, match="fused_steps"):
+        lbsep.Batch([a, b])
