@@ -2,9 +2,11 @@
 
 Workload (default): the single Ne-Ar channel, H = 64, L = 1280 (81,920 nodes),
 C_l = 0.3, theta = 3, Kn_out = 0.05, populations initialised at local
-equilibrium with a linear pressure drop. A step is one fused sweep: both
-species pulled, DBB walls, inlet/outlet correction, moments, relaxation times,
-MRT collision and the FP64 reduction to C_l(x), CL and C~_l.
+equilibrium with a linear pressure drop. A step is one time level of the
+fused sweep: both species pulled, DBB walls, inlet/outlet correction, moments,
+relaxation times, MRT collision and the FP64 reduction to C_l(x), CL and C~_l.
+On channels of at most 64 rows one launch advances two levels (temporal
+blocking; the states are bitwise those of one level per launch).
 
 Prints one JSON line: the FP32 path's throughput in node-MLUPS (one update =
 one node with both species' 9 populations), next to the plain FP64 path, the
@@ -46,9 +48,10 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str, dtype: str):
-    """HBM bytes per launch from the committed rocprofv3 PMC summary, if it was
-    taken on the current kernel source; else None."""
+def measured_traffic(workload: str, dtype: str, levels: int = 1):
+    """HBM bytes per launch (of `levels` time levels) from the committed
+    rocprofv3 PMC summary, if it was taken on the current kernel source; else
+    None."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     want = source_hash()
@@ -56,15 +59,24 @@ def measured_traffic(workload: str, dtype: str):
         if line.startswith("#") or not line.strip():
             continue
         kv = dict(tok.split("=", 1) for tok in line.split())
-        if kv.get("workload") == workload and kv.get("dtype") == dtype and kv.get("source") == want:
+        if (kv.get("workload") == workload and kv.get("dtype") == dtype and kv.get("source") == want
+                and int(kv.get("levels", "1")) == levels):
             return float(kv["bytes_per_launch"])
     return None
 
 
-def make_channel(lbsep, w, dtype, hist_cap=1024):
+def levels_per_launch(w, requested: int) -> int:
+    """Time levels per sweep launch: as requested, else two on channels of at
+    most 64 rows (where the two-level kernel applies), one otherwise."""
+    if requested:
+        return requested
+    return 2 if w.ny <= 64 else 1
+
+
+def make_channel(lbsep, w, dtype, hist_cap=1024, levels=1):
     r = lbsep.dbb_r_from_cm(w.c_m, w.m_a, w.m_b, w.cl_in)
     p = lbsep.make_params(w.nx, w.ny, w.m_a, w.m_b, w.cl_in, w.cl_out, w.theta, w.kn_out, r, accom=w.accom,
-                          dtype=dtype, hist_cap=hist_cap)
+                          dtype=dtype, hist_cap=hist_cap, fused_steps=levels)
     return lbsep.Channel(p, device="cuda:0"), r
 
 
@@ -271,6 +283,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1000)
     ap.add_argument("--workload", default="ne_ar_64x1280")
     ap.add_argument("--dtype", default="f32", choices=["f32", "f16", "f64"])
+    ap.add_argument("--levels", type=int, default=0, choices=[0, 1, 2],
+                    help="time levels per sweep launch (0: two on channels of at most 64 rows, else one)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 reference leg (profiling runs)")
@@ -310,15 +324,18 @@ def main():
         return
 
     w = CONFIGS[args.workload]
-    ch, r = make_channel(lbsep, w, args.dtype)
+    levels = levels_per_launch(w, args.levels)
+    if args.steps % levels or args.warmup % levels:
+        sys.exit(f"--steps and --warmup must be multiples of the {levels} levels per launch")
+    ch, r = make_channel(lbsep, w, args.dtype, levels=levels)
     ch.step(args.warmup)
     torch.cuda.synchronize()
     wall, ev_ms = time_steps(torch, ch, args.steps)
     t_total = ch.t
     cl32 = ch.read_cl()
     mlups = w.nodes * args.steps / wall / 1e6
-    per_launch_s = ev_ms / 1e3 / args.steps
-    alg_bytes = w.nodes * 36 * BYTES_PER_POP[args.dtype]
+    per_launch_s = ev_ms / 1e3 / (args.steps // levels)
+    alg_bytes = levels * w.nodes * 36 * BYTES_PER_POP[args.dtype]
     achieved = alg_bytes / per_launch_s / 1e9
 
     out = {
@@ -337,22 +354,24 @@ def main():
         "config": {"workload": w.name, "nx": w.nx, "ny": w.ny, "mixture": "Ne-Ar" if w.m_a == 20 else "He-Ar",
                    "cl_in": w.cl_in, "theta": w.theta, "kn_out": w.kn_out, "dbb_r": r,
                    "storage": {"f32": "f32 deviation", "f16": "f16 deviation", "f64": "f64"}[args.dtype],
+                   "levels_per_launch": levels,
                    "parallelism": "single GPU"},
         "gbps_algorithmic": round(achieved, 1),
         "cl": cl32["cl"],
         "t_final": t_total,
     }
 
-    traffic = measured_traffic(w.name, args.dtype)
+    traffic = measured_traffic(w.name, args.dtype, levels)
     out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": round(achieved / HBM_PEAK_GBS, 4),
                        "traffic": None if traffic is None else round(traffic)}
-    out["roofline_note"] = (f"sweep kernel, algorithmic bytes {alg_bytes} per launch "
-                            f"(36 populations x {BYTES_PER_POP[args.dtype]} B x {w.nodes} nodes) / "
-                            f"{per_launch_s * 1e6:.2f} us mean launch time (HIP events on the channel stream)")
+    kname = "k_sweep2" if levels == 2 else "k_sweep"
+    out["roofline_note"] = (f"{kname}, algorithmic bytes {alg_bytes} per launch ({levels} level(s) x 36 populations x "
+                            f"{BYTES_PER_POP[args.dtype]} B x {w.nodes} nodes) / {per_launch_s * 1e6:.2f} us mean "
+                            "launch time (HIP events on the channel stream)")
 
     if not args.no_fp64:
-        ch64, _ = make_channel(lbsep, w, "f64")
+        ch64, _ = make_channel(lbsep, w, "f64", levels=levels)
         ch64.step(args.warmup)
         wall64, ev64 = time_steps(torch, ch64, args.steps)
         cl64 = ch64.read_cl()

@@ -104,11 +104,12 @@ typedef struct lbsep_params {
                         same whatever the value; the column sums behind CL and the profiles are
                         associated per tile, so those may differ in the last bits. A channel in a
                         batch that fills the GPU is faster with 4 (fewer row-tile partial sums). */
-  int32_t fused_steps; /* time levels per sweep launch: 0 = chosen by the library, 1, or 2 (needs
-                        inlet, outlet and walls: no periodic flag). With 2, a launch advances two
-                        levels, keeping the first in LDS (half the HBM traffic per level); the
-                        states are bitwise those of single-level launches, CL and the column sums
-                        agree to rounding. A third state buffer is allocated; readouts right
+  int32_t fused_steps; /* time levels per sweep launch: 0 = chosen by the library (currently 1),
+                        1, or 2 (needs ny <= 64 and an inlet, an outlet and walls: no periodic
+                        flag; else LBSEP_EINVAL). With 2, a launch advances two levels, keeping
+                        the first in LDS (about half the HBM traffic per level); the states are
+                        bitwise those of single-level launches (FP64, FP32), CL and the column
+                        sums agree to rounding. A third state buffer is allocated; readouts right
                         after a two-level launch recompute the level before (one launch). Such a
                         channel cannot join a batch. */
 } lbsep_params;
