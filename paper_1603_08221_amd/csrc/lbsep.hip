@@ -164,6 +164,13 @@ __device__ __forceinline__ const typename MD::Pt* pair_at(const KParams& kp, con
   return reinterpret_cast<const typename MD::Pt*>(pop_at(kp, base, 0, i, j, x));
 }
 
+// Entry s of a per-species parameter pair: an index, or (SEL) a select
+// between the two entries.
+template <bool SEL>
+__device__ __forceinline__ double species_param(const double (&v)[2], int s) {
+  return SEL ? (s ? v[1] : v[0]) : v[s];
+}
+
 __device__ __forceinline__ double ref_rho(const KParams& kp, int s, int x) {
   return kp.ref0[s] + kp.slope[s] * double(x);
 }
@@ -517,8 +524,11 @@ __device__ __forceinline__ void process_node(const KParams& kp, int x, int j, ty
 // deviations in the FP32/FP16 modes), the partner lane (lane ^ XOR) the other
 // species. Every lane of the wave must call this (it swaps values across the
 // pair); lanes with active == false only feed the swaps. acc receives this
-// species' (n_s, rho_s u_sx) in double.
-template <class MD, bool EVAL, int XOR>
+// species' (n_s, rho_s u_sx) in double. STORE == false leaves the
+// post-collision populations in f instead of storing them to dst; SEL picks
+// the per-species parameters by selects (kernels in which a dynamic index
+// would move the parameter block to scratch memory).
+template <class MD, bool EVAL, int XOR, bool STORE = true, bool SEL = false>
 __device__ __forceinline__ void process_pair(const KParams& kp, int x, int j, int s, bool active,
                                              typename MD::Ct f[9], typename MD::St* __restrict__ dst,
                                              double* __restrict__ mom, typename MD::St* __restrict__ fraw,
@@ -530,7 +540,7 @@ __device__ __forceinline__ void process_pair(const KParams& kp, int x, int j, in
     for (int i = 0; i < 9; ++i) f[i] = MD::kDev ? C(0) : C(0.1);  // finite filler for the swaps
   }
   const C c_own = sum9(f);  // rho_s, or rho_s - rho0_s(x)
-  const double r0 = MD::kDev ? ref_rho(kp, s, x) : 0.0;
+  const double r0 = MD::kDev ? species_param<SEL>(kp.ref0, s) + species_param<SEL>(kp.slope, s) * double(x) : 0.0;
   const double r_own = MD::kDev ? r0 + double(c_own) : double(c_own);
   const C rho_own = MD::kDev ? C(r_own) : c_own;
   const C jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
@@ -580,10 +590,11 @@ __device__ __forceinline__ void process_pair(const KParams& kp, int x, int j, in
     weps = C(1.0 / 1.2);  // tau_eps = 1.2
   }
   const C wd = C(2) * h2, wq = E::rcp(tq);
-  collide_species<C>(f, c_own, rho_own, ux, uy, C(kp.rc.s[s]), we, weps, wd, wq, ws);
+  collide_species<C>(f, c_own, rho_own, ux, uy, C(species_param<SEL>(kp.rc.s, s)), we, weps, wd, wq, ws);
   if (!active) return;
-  acc[0] += r_own * kp.rc.inv_m[s];
+  acc[0] += r_own * species_param<SEL>(kp.rc.inv_m, s);
   acc[1] += double(px);
+  if (!STORE) return;
 #pragma unroll
   for (int i = 0; i < 9; ++i) *pop_at(kp, dst, s, i, j, x) = typename MD::St(f[i]);
 }
@@ -1166,15 +1177,16 @@ __device__ __forceinline__ void strip_rebuild(const KParams& kp, int e, int col,
   end_rebuild<MD>(kp, e, 1, col, kap[1], km1[1], g1, g2, fb);
 }
 
-// End block of a two-level launch on a channel of at most 64 rows: the four
-// outermost columns stay in LDS. Task (c, j) = (thread % 4, thread / 4).
+// End block of a two-level launch on a channel of at most 64 rows, one lane
+// per node: the four outermost columns stay in LDS. Task (c, j) =
+// (thread % 4, thread / 4).
 // Phase 1 pulls every node once: the two inner layers' values give kappa
 // (kappa_from_values: the order of column_kappa) and the end column's rebuild;
 // all four columns collide into LDS in the storage type. Phase 2 pulls the end
 // column and its two inner layers from LDS, takes the second kappa the same
 // way, rebuilds and collides the end column. acc: the end column's sums.
 template <class MD, bool NT>
-__device__ __forceinline__ void end_block2_lds(const KParams& kp, const typename MD::St* __restrict__ src,
+__device__ __forceinline__ void end_block2_node(const KParams& kp, const typename MD::St* __restrict__ src,
                                typename MD::St* __restrict__ dst, int e, typename MD::Pt (*Q)[kStripRows][9],
                                typename MD::Ct (*P)[kStripRows][9][2], double* Kv, double (*redk)[kTY][kTX],
                                double acc[2][4]) {
@@ -1241,6 +1253,107 @@ __device__ __forceinline__ void end_block2_lds(const KParams& kp, const typename
   }
 }
 
+// end_rebuild of species s (a runtime value) at the end column from the inner
+// layers' pulled populations P[layer][j][i][species] in LDS; one branch per
+// species keeps the parameter indexes constant.
+template <class MD>
+__device__ __forceinline__ void strip_rebuild1(const KParams& kp, int e, int col, int j, int s,
+                                               const typename MD::Ct (*P)[kStripRows][9][2], const double kap[2],
+                                               const double km1[2], typename MD::Ct f[9]) {
+  using C = typename MD::Ct;
+  C g1[9], g2[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    g1[i] = P[0][j][i][s];
+    g2[i] = P[1][j][i][s];
+  }
+  if (s)
+    end_rebuild<MD>(kp, e, 1, col, kap[1], km1[1], g1, g2, f);
+  else
+    end_rebuild<MD>(kp, e, 0, col, kap[0], km1[0], g1, g2, f);
+}
+
+// The same with a lane pair per node: thread t takes species s = t % 2 of a
+// node, the two species of a node sit in adjacent lanes and collide as a lane
+// pair (process_pair: the same arithmetic as one lane per node, half the chain
+// per lane). Phase 1: node (column c = (t / 2) % 4 from the end, row
+// j = t / 8); phase 2: column c = t / 128, row j = (t / 2) % 64, so the end
+// column's pairs fill the first two wavefronts.
+template <class MD, bool NT>
+__device__ __forceinline__ void end_block2_pair(const KParams& kp, const typename MD::St* __restrict__ src,
+                                               typename MD::St* __restrict__ dst, int e,
+                                               typename MD::Pt (*Q)[kStripRows][9],
+                                               typename MD::Ct (*P)[kStripRows][9][2], double* Kv,
+                                               double (*redk)[kTY][kTX], double acc[2][4]) {
+  using C = typename MD::Ct;
+  using S = typename MD::St;
+  const int sgn = e ? -1 : 1, col = e ? kp.nx - 1 : 0;
+  const int s = threadIdx.x & 1, c = (threadIdx.x >> 1) & 3, j = threadIdx.x >> 3;
+  const bool act = j < kp.ny;
+  const int x = col + sgn * c;
+  double kap[2], km1[2];
+  C f[9];
+  // ---- first level
+  {
+    C fa[9], fb[9];
+    if (act) gather_pair<MD, true>(kp, src, x, j, fa, fb);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) f[i] = s ? fb[i] : fa[i];
+  }
+  if (act && (c == 1 || c == 2)) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) P[c - 1][j][i][s] = f[i];
+    Kv[4 * j + 2 * s + (c - 1)] = double(sum9(f));
+  }
+  __syncthreads();
+  kappa_from_values<MD>(kp, e, Kv, redk, kap, km1);
+  if (act && c == 0) strip_rebuild1<MD>(kp, e, col, j, s, P, kap, km1, f);
+  double t1[2] = {0.0, 0.0};
+  process_pair<MD, false, 1, false, true>(kp, x, j, s, act, f, nullptr, nullptr, nullptr, nullptr, t1);
+  if (c == 0) {
+    acc[0][0] += s ? 0.0 : t1[0];
+    acc[0][1] += s ? t1[0] : 0.0;
+    acc[0][2] += s ? 0.0 : t1[1];
+    acc[0][3] += s ? t1[1] : 0.0;
+  }
+  if (act)
+#pragma unroll
+    for (int i = 0; i < 9; ++i) reinterpret_cast<S*>(&Q[c][j][i])[s] = S(f[i]);
+  __syncthreads();
+  // ---- second level: the end column
+  const int c2 = threadIdx.x >> 7, j2 = (threadIdx.x >> 1) & 63;
+  const bool act2 = j2 < kp.ny && c2 < 3;
+  if (act2) {
+    C fa[9], fb[9];
+    strip_gather<MD>(kp, Q, e, c2, j2, fa, fb);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) f[i] = s ? fb[i] : fa[i];
+    if (c2 > 0) {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) P[c2 - 1][j2][i][s] = f[i];
+      Kv[4 * j2 + 2 * s + (c2 - 1)] = double(sum9(f));
+    }
+  }
+  __syncthreads();
+  kappa_from_values<MD>(kp, e, Kv, redk, kap, km1);
+  if (c2 == 0) {  // both lanes of each pair (wavefronts 0 and 1)
+    if (act2) strip_rebuild1<MD>(kp, e, col, j2, s, P, kap, km1, f);
+    double t2[2] = {0.0, 0.0};
+    process_pair<MD, false, 1, true, true>(kp, col, j2, s, act2, f, dst, nullptr, nullptr, nullptr, t2);
+    acc[1][0] += s ? 0.0 : t2[0];
+    acc[1][1] += s ? t2[0] : 0.0;
+    acc[1][2] += s ? 0.0 : t2[1];
+    acc[1][3] += s ? t2[1] : 0.0;
+  }
+}
+
+// Lane pairs in the two-level end blocks: in FP64 the wall functions dominate a
+// node's chain and splitting them over the pair shortens the inlet/outlet path
+// below the tiles' (measured on 64 x 1280: 13.2 -> 12.6 us per level); in the
+// deviation modes the pair's swaps cost more than they save.
+template <class MD>
+constexpr bool kPairEnd = !MD::kDev;
+
 // Inlet (e = 0) or outlet (e = 1) block of k_sweep2 (a channel of at most 64
 // rows: one end node per thread).
 template <class MD, bool NT>
@@ -1253,7 +1366,10 @@ __device__ __forceinline__ void end_block2(const KParams& kp, const KBufs& kb, c
   if (lv.nlev == 0) return;  // a reductions-only launch
   double acc[2][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};  // end column, levels t1, t1 + 1
   if (lv.nlev == 2) {
-    end_block2_lds<MD, NT>(kp, src, dst, e, Q, P, Kv, redk, acc);
+    if (kPairEnd<MD>)
+      end_block2_pair<MD, NT>(kp, src, dst, e, Q, P, Kv, redk, acc);
+    else
+      end_block2_node<MD, NT>(kp, src, dst, e, Q, P, Kv, redk, acc);
   } else {
     // one level: the end column, rebuilt as in the single-level end blocks
     const int col = e ? kp.nx - 1 : 0;
@@ -1312,14 +1428,15 @@ __device__ __forceinline__ void tile2(const KParams& kp, const KBufs& kb, const 
   const bool has_out = x0 + kC2 >= kp.nx - 1;  // some lane is the outlet column
   const bool own_x = lane >= 1 && lane <= kC2 && x <= kp.nx - 2;
   const bool own = own_x && w >= 1 && w <= kR2 && j < kp.ny;
-  double kin[2] = {1.0, 1.0}, kin1[2] = {0.0, 0.0}, kout[2] = {1.0, 1.0}, kout1[2] = {0.0, 0.0};
-  if (has_in) column_kappa<MD>(kp, src, 0, redk, kin, kin1);
-  if (has_out) column_kappa<MD>(kp, src, 1, redk, kout, kout1);
-  // ---- first level: own nodes and halo
+  // ---- first level: own nodes and halo (loads in flight while the end
+  // columns' kappa is summed)
   C fa[9], fb[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) fa[i] = fb[i] = C(0);
   if (valid) gather_pair<MD, true>(kp, src, x, j, fa, fb);
+  double kin[2] = {1.0, 1.0}, kin1[2] = {0.0, 0.0}, kout[2] = {1.0, 1.0}, kout1[2] = {0.0, 0.0};
+  if (has_in) column_kappa<MD>(kp, src, 0, redk, kin, kin1);
+  if (has_out) column_kappa<MD>(kp, src, 1, redk, kout, kout1);
   if (has_in || has_out) {
     // the inner layers' pulled populations to the end lanes: lanes + 1, + 2
     // (inlet) or - 1, - 2 (outlet) of the same row
