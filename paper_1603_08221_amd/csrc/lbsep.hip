@@ -186,8 +186,9 @@ __device__ __forceinline__ T sum9(const T f[9]) {
 // !PULL: read in place (src already holds a pre-collision state).
 // On the inlet/outlet columns the directions that would come from outside the
 // channel are loaded from the node itself (kept in range) and replaced by the
-// caller.
-template <class MD, bool PULL>
+// caller. SEL: the streaming correction by a select between the species (see
+// species_param).
+template <class MD, bool PULL, bool SEL = false>
 __device__ __forceinline__ void gather1(const KParams& kp, const typename MD::St* __restrict__ src, int s, int x,
                                         int j, typename MD::Ct f[9]) {
   using C = typename MD::Ct;
@@ -221,7 +222,7 @@ __device__ __forceinline__ void gather1(const KParams& kp, const typename MD::St
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     f[i] = C(*pop_at(kp, src, s, i, sy[i], sx[i]));
-    if (MD::kDev && (i == 1 || i == 3 || i >= 5)) f[i] += C(kp.corr[s][i]);
+    if (MD::kDev && (i == 1 || i == 3 || i >= 5)) f[i] += C(SEL ? (s ? kp.corr[1][i] : kp.corr[0][i]) : kp.corr[s][i]);
   }
   if (bot || top) {
     // Eqs. (bot)/(bot2): the populations that would come from outside the
@@ -964,20 +965,20 @@ __global__ void k_batch_advance(long long* counter, long long n) {
 // phase 0 reduces the strips of level t (blocks 0 .. nxt-1) and finishes level
 // t - 1 (block nxt); phase 1 finishes level t.
 // ---- two time levels per launch ---------------------------------------------
-// k_sweep2 advances the state by nlev = 1 or 2 levels in one launch. A tile of
-// kW2 wavefronts x 64 lanes computes the first level on its rows and columns
-// plus a one-node halo (wavefront w: row 6 by - 1 + w; lane l: column
-// 62 bx + l), keeps those post-collision pairs in LDS in the storage type (the
-// values the next pull would read back from memory), and computes the second
-// level on the 6 x 62 nodes it owns from LDS alone. The inlet and outlet
-// columns couple every row through kappa (Eq. (rho2)): one block per end
-// computes the first level on its four outermost columns for all rows (at most
-// 64: the columns stay in LDS), takes kappa of the second level from there,
-// and computes the end column's second level; a tile whose halo holds an end
-// column computes that column's first level itself from the same kappa (the
-// same summation order as the single-level end blocks). Every node therefore
-// goes through the same arithmetic as in two single-level sweeps: the states
-// are bitwise those. The lead blocks reduce the row-tile partials of earlier
+// k_sweep2 advances the state by nlev = 1 or 2 levels in one launch, on a
+// channel of at most 64 rows. A tile of kW2 wavefronts x 64 lanes computes the
+// first level on its rows and columns plus a one-node halo (wavefront w: row
+// 6 by - 1 + w; lane l: column 2 + 62 bx + l), keeps those post-collision
+// pairs in LDS in the storage type (the values the next pull would read back
+// from memory), and computes the second level on the 6 x 62 nodes it owns
+// from LDS alone. The inlet and outlet columns couple every row through kappa
+// (Eq. (rho2)): one block per end computes the first level on its four
+// outermost columns for all rows (in LDS), takes kappa of the second level
+// from there, and computes the second level of its three outermost columns.
+// The tiles own the columns between, so that none of them needs kappa. kappa
+// is summed in the order of the single-level end blocks, so every node goes
+// through the same arithmetic as in two single-level sweeps: the states are
+// bitwise those. The lead blocks reduce the row-tile partials of earlier
 // levels (level lists from the host, four slots by level mod 4).
 constexpr int kW2 = 8;            // wavefronts per block
 constexpr int kT2 = kW2 * kTX;    // threads per block
@@ -1027,37 +1028,10 @@ __device__ __forceinline__ void kappa_from_sums(const KParams& kp, int e, double
   __syncthreads();  // red is reused by the caller
 }
 
-// kappa of end e from the two inner layers of state src, summed in the order
-// of the single-level end blocks (a channel of at most 64 rows): thread
-// L < 256 adds item L = 4 row + 2 species + layer, then block_sum. Every
-// thread of the block must call it (barriers).
-template <class MD>
-__device__ __forceinline__ void column_kappa(const KParams& kp, const typename MD::St* __restrict__ src, int e,
-                                             double (*red)[kTY][kTX], double kap[2], double km1[2]) {
-  using C = typename MD::Ct;
-  const int l1 = e ? kp.nx - 2 : 1, l2 = e ? kp.nx - 3 : 2;
-  double sums[2] = {0.0, 0.0};
-  const int it = threadIdx.x;
-  if (it < 4 * kp.ny) {
-    const int jj = it >> 2, ss = (it >> 1) & 1, ll = it & 1;
-    const int x = ll ? l2 : l1;
-    C h[9];
-    // the species as a literal in each branch (constant parameter indexes)
-    if (ss)
-      gather1<MD, true>(kp, src, 1, x, jj, h);
-    else
-      gather1<MD, true>(kp, src, 0, x, jj, h);
-    const double v = double(sum9(h));
-    if (ss)
-      sums[1] += ll ? -v : 2.0 * v;
-    else
-      sums[0] += ll ? -v : 2.0 * v;
-  }
-  kappa_from_sums<MD>(kp, e, red, sums, kap, km1);
-}
-
-// The same kappa from the values v[it] = rho of the pulled layer populations,
-// it = 4 row + 2 species + layer, already in LDS.
+// kappa of end e from the values v[it] = rho of the pulled populations of the
+// two inner layers, it = 4 row + 2 species + layer, in LDS, summed in the
+// order of the single-level end blocks: thread L < 256 adds item L, then
+// kappa_from_sums. Every thread of the block must call it (barriers).
 template <class MD>
 __device__ __forceinline__ void kappa_from_values(const KParams& kp, int e, const double* v, double (*red)[kTY][kTX],
                                                   double kap[2], double km1[2]) {
@@ -1106,21 +1080,6 @@ __device__ __forceinline__ double wave_column_sum(const double (*red)[kW2][kTX],
   double v = 0.0;
   for (int w = w0; w <= w1; ++w) v += red[q][w][lane];
   return v;
-}
-
-// Rebuilt pre-collision populations of species s at row j of the end column of
-// end e, pulled from state src (the end-block arithmetic of the single-level
-// sweep: the node and its two inner layers, then end_rebuild).
-template <class MD>
-__device__ __forceinline__ void end_node(const KParams& kp, const typename MD::St* __restrict__ src, int e, int s,
-                                         double kap, double km1, int j, typename MD::Ct f[9]) {
-  using C = typename MD::Ct;
-  const int col = e ? kp.nx - 1 : 0, l1 = e ? kp.nx - 2 : 1, l2 = e ? kp.nx - 3 : 2;
-  C g1[9], g2[9];
-  gather1<MD, true>(kp, src, s, col, j, f);
-  gather1<MD, true>(kp, src, s, l1, j, g1);
-  gather1<MD, true>(kp, src, s, l2, j, g2);
-  end_rebuild<MD>(kp, e, s, col, kap, km1, g1, g2, f);
 }
 
 // The end strip of a channel of at most 64 rows in LDS: column c (0 = the end
@@ -1177,25 +1136,36 @@ __device__ __forceinline__ void strip_rebuild(const KParams& kp, int e, int col,
   end_rebuild<MD>(kp, e, 1, col, kap[1], km1[1], g1, g2, fb);
 }
 
+// Columns of each end a two-level launch gives to its end block: the end
+// column and the next two (counted inwards). The tiles own the columns
+// between, so that no tile touches an end column or needs kappa.
+constexpr int kEndCols = 3;
+
+// Per-node sums of an end block, by level, column, quantity (n_a, n_b,
+// rho_a u_ax, rho_b u_bx) and row; kept in LDS until the block reduces them.
+typedef double EndSums[2][kEndCols][4][kStripRows];
+
 // End block of a two-level launch on a channel of at most 64 rows, one lane
-// per node: the four outermost columns stay in LDS. Task (c, j) =
-// (thread % 4, thread / 4).
-// Phase 1 pulls every node once: the two inner layers' values give kappa
-// (kappa_from_values: the order of column_kappa) and the end column's rebuild;
-// all four columns collide into LDS in the storage type. Phase 2 pulls the end
-// column and its two inner layers from LDS, takes the second kappa the same
-// way, rebuilds and collides the end column. acc: the end column's sums.
+// per node: task (c, j) = (thread % 4, thread / 4); the four outermost columns
+// of the first level stay in LDS. Phase 1 pulls every node once: the two inner
+// layers' values give kappa (kappa_from_values) and the end column's rebuild;
+// the four columns collide into LDS in the storage type (nlev = 1: columns 0
+// to 2 are stored to dst instead). Phase 2 pulls columns 0 to 2 from LDS,
+// takes the second kappa the same way, rebuilds the end column and collides
+// and stores the three columns. sums1 / sums2: the node's sums per level.
 template <class MD, bool NT>
 __device__ __forceinline__ void end_block2_node(const KParams& kp, const typename MD::St* __restrict__ src,
-                               typename MD::St* __restrict__ dst, int e, typename MD::Pt (*Q)[kStripRows][9],
-                               typename MD::Ct (*P)[kStripRows][9][2], double* Kv, double (*redk)[kTY][kTX],
-                               double acc[2][4]) {
+                                                typename MD::St* __restrict__ dst, int e, int nlev,
+                                                typename MD::Pt (*Q)[kStripRows][9],
+                                                typename MD::Ct (*P)[kStripRows][9][2], double* Kv,
+                                                double (*redk)[kTY][kTX], EndSums& V) {
   using C = typename MD::Ct;
   const int sgn = e ? -1 : 1, col = e ? kp.nx - 1 : 0;
   const int c = threadIdx.x & 3, j = threadIdx.x >> 2;
   const bool act = j < kp.ny;
   const int x = col + sgn * c;
   double kap[2], km1[2];
+  double sums1[4] = {0.0, 0.0, 0.0, 0.0}, sums2[4] = {0.0, 0.0, 0.0, 0.0};
   // ---- first level
   C fa[9], fb[9];
   if (act) gather_pair<MD, true>(kp, src, x, j, fa, fb);
@@ -1212,45 +1182,51 @@ __device__ __forceinline__ void end_block2_node(const KParams& kp, const typenam
   kappa_from_values<MD>(kp, e, Kv, redk, kap, km1);
   if (act) {
     if (c == 0) strip_rebuild<MD>(kp, e, col, j, P, kap, km1, fa, fb);
-    double tmp[4] = {0.0, 0.0, 0.0, 0.0};
-    const NodeState<C> st = node_moments<MD, false>(kp, x, j, fa, fb, nullptr, nullptr, nullptr, tmp);
-    if (c == 0)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) acc[0][q] += tmp[q];
+    const NodeState<C> st = node_moments<MD, false>(kp, x, j, fa, fb, nullptr, nullptr, nullptr, sums1);
     node_collide_only<MD>(kp, fa, fb, st);
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      typename MD::Pt v;
-      v[0] = typename MD::St(fa[i]);
-      v[1] = typename MD::St(fb[i]);
-      Q[c][j][i] = v;
-    }
-  }
-  __syncthreads();
-  // ---- second level: the end column
-  if (act && c < 3) {
-    strip_gather<MD>(kp, Q, e, c, j, fa, fb);
-    if (c > 0) {
+    if (nlev == 2) {
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
-        P[c - 1][j][i][0] = fa[i];
-        P[c - 1][j][i][1] = fb[i];
+        typename MD::Pt v;
+        v[0] = typename MD::St(fa[i]);
+        v[1] = typename MD::St(fb[i]);
+        Q[c][j][i] = v;
       }
-      Kv[4 * j + (c - 1)] = double(sum9(fa));
-      Kv[4 * j + 2 + (c - 1)] = double(sum9(fb));
+    } else if (c < kEndCols) {
+      node_store<MD, NT>(kp, x, j, fa, fb, dst);
     }
   }
-  __syncthreads();
-  kappa_from_values<MD>(kp, e, Kv, redk, kap, km1);
-  if (act && c == 0) {
-    strip_rebuild<MD>(kp, e, col, j, P, kap, km1, fa, fb);
-    double tmp[4] = {0.0, 0.0, 0.0, 0.0};
-    const NodeState<C> st = node_moments<MD, false>(kp, col, j, fa, fb, nullptr, nullptr, nullptr, tmp);
+  if (nlev == 2) {
+    __syncthreads();
+    // ---- second level: columns 0 to 2
+    if (act && c < kEndCols) {
+      strip_gather<MD>(kp, Q, e, c, j, fa, fb);
+      if (c > 0) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) acc[1][q] += tmp[q];
-    node_collide_only<MD>(kp, fa, fb, st);
-    node_store<MD, NT>(kp, col, j, fa, fb, dst);
+        for (int i = 0; i < 9; ++i) {
+          P[c - 1][j][i][0] = fa[i];
+          P[c - 1][j][i][1] = fb[i];
+        }
+        Kv[4 * j + (c - 1)] = double(sum9(fa));
+        Kv[4 * j + 2 + (c - 1)] = double(sum9(fb));
+      }
+    }
+    __syncthreads();
+    kappa_from_values<MD>(kp, e, Kv, redk, kap, km1);
+    if (act && c < kEndCols) {
+      if (c == 0) strip_rebuild<MD>(kp, e, col, j, P, kap, km1, fa, fb);
+      const NodeState<C> st = node_moments<MD, false>(kp, x, j, fa, fb, nullptr, nullptr, nullptr, sums2);
+      node_collide_only<MD>(kp, fa, fb, st);
+      node_store<MD, NT>(kp, x, j, fa, fb, dst);
+    }
   }
+  // kappa_from_values ends with a barrier: V (in the reduction scratch) is free
+  if (act && c < kEndCols)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      V[0][c][q][j] = sums1[q];
+      V[1][c][q][j] = sums2[q];
+    }
 }
 
 // end_rebuild of species s (a runtime value) at the end column from the inner
@@ -1277,14 +1253,13 @@ __device__ __forceinline__ void strip_rebuild1(const KParams& kp, int e, int col
 // node, the two species of a node sit in adjacent lanes and collide as a lane
 // pair (process_pair: the same arithmetic as one lane per node, half the chain
 // per lane). Phase 1: node (column c = (t / 2) % 4 from the end, row
-// j = t / 8); phase 2: column c = t / 128, row j = (t / 2) % 64, so the end
-// column's pairs fill the first two wavefronts.
+// j = t / 8); phase 2: column c = t / 128, row j = (t / 2) % 64.
 template <class MD, bool NT>
 __device__ __forceinline__ void end_block2_pair(const KParams& kp, const typename MD::St* __restrict__ src,
-                                               typename MD::St* __restrict__ dst, int e,
-                                               typename MD::Pt (*Q)[kStripRows][9],
-                                               typename MD::Ct (*P)[kStripRows][9][2], double* Kv,
-                                               double (*redk)[kTY][kTX], double acc[2][4]) {
+                                                typename MD::St* __restrict__ dst, int e, int nlev,
+                                                typename MD::Pt (*Q)[kStripRows][9],
+                                                typename MD::Ct (*P)[kStripRows][9][2], double* Kv,
+                                                double (*redk)[kTY][kTX], EndSums& V) {
   using C = typename MD::Ct;
   using S = typename MD::St;
   const int sgn = e ? -1 : 1, col = e ? kp.nx - 1 : 0;
@@ -1292,6 +1267,7 @@ __device__ __forceinline__ void end_block2_pair(const KParams& kp, const typenam
   const bool act = j < kp.ny;
   const int x = col + sgn * c;
   double kap[2], km1[2];
+  double sums1[2] = {0.0, 0.0}, sums2[2] = {0.0, 0.0};
   C f[9];
   // ---- first level
   {
@@ -1308,109 +1284,106 @@ __device__ __forceinline__ void end_block2_pair(const KParams& kp, const typenam
   __syncthreads();
   kappa_from_values<MD>(kp, e, Kv, redk, kap, km1);
   if (act && c == 0) strip_rebuild1<MD>(kp, e, col, j, s, P, kap, km1, f);
-  double t1[2] = {0.0, 0.0};
-  process_pair<MD, false, 1, false, true>(kp, x, j, s, act, f, nullptr, nullptr, nullptr, nullptr, t1);
-  if (c == 0) {
-    acc[0][0] += s ? 0.0 : t1[0];
-    acc[0][1] += s ? t1[0] : 0.0;
-    acc[0][2] += s ? 0.0 : t1[1];
-    acc[0][3] += s ? t1[1] : 0.0;
+  process_pair<MD, false, 1, false, true>(kp, x, j, s, act, f, nullptr, nullptr, nullptr, nullptr, sums1);
+  if (nlev == 2) {
+    if (act)
+#pragma unroll
+      for (int i = 0; i < 9; ++i) reinterpret_cast<S*>(&Q[c][j][i])[s] = S(f[i]);
+  } else if (act && c < kEndCols) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) *pop_at(kp, dst, s, i, j, x) = S(f[i]);
   }
-  if (act)
-#pragma unroll
-    for (int i = 0; i < 9; ++i) reinterpret_cast<S*>(&Q[c][j][i])[s] = S(f[i]);
-  __syncthreads();
-  // ---- second level: the end column
   const int c2 = threadIdx.x >> 7, j2 = (threadIdx.x >> 1) & 63;
-  const bool act2 = j2 < kp.ny && c2 < 3;
-  if (act2) {
-    C fa[9], fb[9];
-    strip_gather<MD>(kp, Q, e, c2, j2, fa, fb);
+  const bool act2 = j2 < kp.ny && c2 < kEndCols;
+  if (nlev == 2) {
+    __syncthreads();
+    // ---- second level: columns 0 to 2
+    if (act2) {
+      C fa[9], fb[9];
+      strip_gather<MD>(kp, Q, e, c2, j2, fa, fb);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) f[i] = s ? fb[i] : fa[i];
-    if (c2 > 0) {
+      for (int i = 0; i < 9; ++i) f[i] = s ? fb[i] : fa[i];
+      if (c2 > 0) {
 #pragma unroll
-      for (int i = 0; i < 9; ++i) P[c2 - 1][j2][i][s] = f[i];
-      Kv[4 * j2 + 2 * s + (c2 - 1)] = double(sum9(f));
+        for (int i = 0; i < 9; ++i) P[c2 - 1][j2][i][s] = f[i];
+        Kv[4 * j2 + 2 * s + (c2 - 1)] = double(sum9(f));
+      }
+    }
+    __syncthreads();
+    kappa_from_values<MD>(kp, e, Kv, redk, kap, km1);
+    if (c2 < kEndCols) {  // both lanes of each pair (wavefronts 0 to 5)
+      if (act2 && c2 == 0) strip_rebuild1<MD>(kp, e, col, j2, s, P, kap, km1, f);
+      process_pair<MD, false, 1, true, true>(kp, col + sgn * c2, j2, s, act2, f, dst, nullptr, nullptr, nullptr,
+                                             sums2);
     }
   }
-  __syncthreads();
-  kappa_from_values<MD>(kp, e, Kv, redk, kap, km1);
-  if (c2 == 0) {  // both lanes of each pair (wavefronts 0 and 1)
-    if (act2) strip_rebuild1<MD>(kp, e, col, j2, s, P, kap, km1, f);
-    double t2[2] = {0.0, 0.0};
-    process_pair<MD, false, 1, true, true>(kp, col, j2, s, act2, f, dst, nullptr, nullptr, nullptr, t2);
-    acc[1][0] += s ? 0.0 : t2[0];
-    acc[1][1] += s ? t2[0] : 0.0;
-    acc[1][2] += s ? 0.0 : t2[1];
-    acc[1][3] += s ? t2[1] : 0.0;
+  // kappa_from_values ends with a barrier: V (in the reduction scratch) is free
+  if (act && c < kEndCols) {
+    V[0][c][s][j] = sums1[0];
+    V[0][c][2 + s][j] = sums1[1];
+  }
+  if (nlev == 2 && act2) {
+    V[1][c2][s][j2] = sums2[0];
+    V[1][c2][2 + s][j2] = sums2[1];
   }
 }
 
 // Lane pairs in the two-level end blocks: in FP64 the wall functions dominate a
 // node's chain and splitting them over the pair shortens the inlet/outlet path
-// below the tiles' (measured on 64 x 1280: 13.2 -> 12.6 us per level); in the
-// deviation modes the pair's swaps cost more than they save.
+// (measured on 64 x 1280); in the deviation modes the pair's swaps cost more
+// than they save.
 template <class MD>
 constexpr bool kPairEnd = !MD::kDev;
 
 // Inlet (e = 0) or outlet (e = 1) block of k_sweep2 (a channel of at most 64
-// rows: one end node per thread).
+// rows): columns 0 to 2 from the end at every level the launch computes, then
+// their sums over the rows (one wavefront per sum, fixed order): the end
+// column's to the end sums (end block 0 of the level's slot, zeros to the
+// rest), the other two columns' to row tile 0 of the partials (zeros to the
+// other row tiles).
 template <class MD, bool NT>
 __device__ __forceinline__ void end_block2(const KParams& kp, const KBufs& kb, const Lv2& lv,
                                            const typename MD::St* __restrict__ src, typename MD::St* __restrict__ dst,
                                            int e, double (*red)[kW2][kTX], double (*redk)[kTY][kTX],
                                            typename MD::Pt (*Q)[kStripRows][9], typename MD::Ct (*P)[kStripRows][9][2],
                                            double* Kv) {
-  using C = typename MD::Ct;
   if (lv.nlev == 0) return;  // a reductions-only launch
-  double acc[2][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};  // end column, levels t1, t1 + 1
-  if (lv.nlev == 2) {
-    if (kPairEnd<MD>)
-      end_block2_pair<MD, NT>(kp, src, dst, e, Q, P, Kv, redk, acc);
-    else
-      end_block2_node<MD, NT>(kp, src, dst, e, Q, P, Kv, redk, acc);
-  } else {
-    // one level: the end column, rebuilt as in the single-level end blocks
-    const int col = e ? kp.nx - 1 : 0;
-    double kap[2], km1[2];
-    column_kappa<MD>(kp, src, e, redk, kap, km1);
-    const int j = threadIdx.x;
-    if (j < kp.ny) {
-      C fa[9], fb[9];
-      end_node<MD>(kp, src, e, 0, kap[0], km1[0], j, fa);
-      end_node<MD>(kp, src, e, 1, kap[1], km1[1], j, fb);
-      const NodeState<C> st = node_moments<MD, false>(kp, col, j, fa, fb, nullptr, nullptr, nullptr, acc[0]);
-      node_collide_only<MD>(kp, fa, fb, st);
-      node_store<MD, NT>(kp, col, j, fa, fb, dst);
-    }
-  }
+  static_assert(sizeof(EndSums) <= sizeof(double) * 4 * kW2 * kTX, "the end sums fit the reduction scratch");
+  EndSums& V = *reinterpret_cast<EndSums*>(&red[0][0][0]);
+  if (kPairEnd<MD>)
+    end_block2_pair<MD, NT>(kp, src, dst, e, lv.nlev, Q, P, Kv, redk, V);
+  else
+    end_block2_node<MD, NT>(kp, src, dst, e, lv.nlev, Q, P, Kv, redk, V);
   if (!lv.reduce) return;  // uniform over the block
-  // end sums: per lane over the wavefronts, then over the lanes (fixed order);
-  // the whole column goes to end block 0 of the level's slot, zeros to the rest
+  __syncthreads();
   const int lane = threadIdx.x & (kTX - 1), w = threadIdx.x / kTX;
-  for (int lev = 0; lev < lv.nlev; ++lev) {
+  const int sgn = e ? -1 : 1, col = e ? kp.nx - 1 : 0;
+  for (int k = w; k < lv.nlev * kEndCols * 4; k += kW2) {  // wave-uniform
+    const int lev = k / (kEndCols * 4), c = (k / 4) % kEndCols, q = k % 4;
+    double v = lane < kp.ny ? V[lev][c][q][lane] : 0.0;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) red[q][w][lane] = acc[lev][q];
-    __syncthreads();
-    if (w < 4) {
-      double v = wave_column_sum(red, w, lane, 0, kW2 - 1);
-#pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
-      const long long level = lv.t1 + lev;
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+    const long long level = lv.t1 + lev;
+    if (c == 0) {
       double* es = kb.endsum + ((long long)(level & 3) * 2 + e) * kMaxEnd * 4;
-      if (lane == 0) es[w] = v;
-      for (int blk = 1 + lane; blk < kp.nend; blk += kTX) es[blk * 4 + w] = 0.0;
+      if (lane == 0) es[q] = v;
+      for (int blk = 1 + lane; blk < kp.nend; blk += kTX) es[blk * 4 + q] = 0.0;
+    } else {
+      double* pt = kb.partials + (level & 3) * lv.part_stride + (long long)q * lv.nrt * kp.pitch + col + sgn * c;
+      if (lane == 0) pt[0] = v;
+      for (int by = 1 + lane; by < lv.nrt; by += kTX) pt[(long long)by * kp.pitch] = 0.0;
     }
-    __syncthreads();
   }
 }
 
-// Tile of k_sweep2 (see above).
+// Tile of k_sweep2 (see above): owns columns 3 .. nx - 4 of its rows; its
+// halo columns (2 and nx - 3 at the ends) are ordinary interior nodes, so no
+// tile needs kappa. Lanes beyond the owned range compute values no owned node
+// reads.
 template <class MD, bool NT>
-__device__ __forceinline__ void tile2(const KParams& kp, const KBufs& kb, const Lv2& lv, const typename MD::St* __restrict__ src,
-                      typename MD::St* __restrict__ dst, int b, typename MD::Pt (*lds)[9][kTX],
-                      double (*red)[kW2][kTX], double (*redk)[kTY][kTX]) {
+__device__ __forceinline__ void tile2(const KParams& kp, const KBufs& kb, const Lv2& lv,
+                                      const typename MD::St* __restrict__ src, typename MD::St* __restrict__ dst,
+                                      int b, typename MD::Pt (*lds)[9][kTX], double (*red)[kW2][kTX]) {
   using C = typename MD::Ct;
   const int xcd = b & 7;
   const int k = (b - lv.lead) >> 3;
@@ -1419,50 +1392,18 @@ __device__ __forceinline__ void tile2(const KParams& kp, const KBufs& kb, const 
   const int by = lin / lv.ntx, bx = lin - by * lv.ntx;
   const int lane = threadIdx.x & (kTX - 1);
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kTX);
-  const int x0 = 1 + kC2 * bx;
+  const int x0 = kEndCols + kC2 * bx;  // first owned column
   const int x = x0 - 1 + lane;
   const int j = by * kR2 - 1 + w;
   const bool in_j = j >= 0 && j < kp.ny;
   const bool valid = x < kp.nx && in_j;
-  const bool has_in = bx == 0;                 // lane 0 is the inlet column
-  const bool has_out = x0 + kC2 >= kp.nx - 1;  // some lane is the outlet column
-  const bool own_x = lane >= 1 && lane <= kC2 && x <= kp.nx - 2;
+  const bool own_x = lane >= 1 && lane <= kC2 && x <= kp.nx - 1 - kEndCols;
   const bool own = own_x && w >= 1 && w <= kR2 && j < kp.ny;
-  // ---- first level: own nodes and halo (loads in flight while the end
-  // columns' kappa is summed)
+  // ---- first level: own nodes and halo
   C fa[9], fb[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) fa[i] = fb[i] = C(0);
   if (valid) gather_pair<MD, true>(kp, src, x, j, fa, fb);
-  double kin[2] = {1.0, 1.0}, kin1[2] = {0.0, 0.0}, kout[2] = {1.0, 1.0}, kout1[2] = {0.0, 0.0};
-  if (has_in) column_kappa<MD>(kp, src, 0, redk, kin, kin1);
-  if (has_out) column_kappa<MD>(kp, src, 1, redk, kout, kout1);
-  if (has_in || has_out) {
-    // the inner layers' pulled populations to the end lanes: lanes + 1, + 2
-    // (inlet) or - 1, - 2 (outlet) of the same row
-    const bool is_in = has_in && lane == 0 && in_j;
-    const bool is_out = has_out && x == kp.nx - 1 && in_j;
-    // species by species: the inner layers' pulled values first, for both
-    C g1[2][9], g2[2][9];
-#pragma unroll
-    for (int s = 0; s < 2; ++s)
-#pragma unroll
-      for (int i = 0; i < 9; ++i) {
-        const C v = s ? fb[i] : fa[i];
-        const C d1 = __shfl_down(v, 1), d2 = __shfl_down(v, 2);
-        const C u1 = __shfl_up(v, 1), u2 = __shfl_up(v, 2);
-        g1[s][i] = is_out ? u1 : d1;
-        g2[s][i] = is_out ? u2 : d2;
-      }
-    if (is_in) {
-      end_rebuild<MD>(kp, 0, 0, 0, kin[0], kin1[0], g1[0], g2[0], fa);
-      end_rebuild<MD>(kp, 0, 1, 0, kin[1], kin1[1], g1[1], g2[1], fb);
-    }
-    if (is_out) {
-      end_rebuild<MD>(kp, 1, 0, kp.nx - 1, kout[0], kout1[0], g1[0], g2[0], fa);
-      end_rebuild<MD>(kp, 1, 1, kp.nx - 1, kout[1], kout1[1], g1[1], g2[1], fb);
-    }
-  }
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   if (valid) {
     double tmp[4] = {0.0, 0.0, 0.0, 0.0};
@@ -1549,7 +1490,7 @@ __global__ __launch_bounds__(kT2) void k_sweep2(KParams kp, KBufs kb, Lv2 lv, co
     }
     return;
   }
-  tile2<MD, NT>(kp, kb, lv, src, dst, b, lds, red, redk);
+  tile2<MD, NT>(kp, kb, lv, src, dst, b, lds, red);
 }
 
 __global__ __launch_bounds__(kThreads) void k_finalize(KParams kp, KBufs kb, long long t, long long t_first,
@@ -1779,7 +1720,8 @@ Layout make_layout(const lbsep_params* p) {
   L.big = !L.split && L.state_buf > (128ull << 20);
   // two levels per launch: tiles own 62 columns x 6 rows of the interior
   L.two = p->fused_steps == 2;
-  L.ntx2 = (p->nx - 2 + kC2 - 1) / kC2;
+  // tiles own columns kEndCols .. nx - 1 - kEndCols; the end blocks the rest
+  L.ntx2 = std::max(0, (p->nx - 2 * kEndCols + kC2 - 1) / kC2);
   L.nrt2 = (p->ny + kR2 - 1) / kR2;
   L.tiles2 = L.ntx2 * L.nrt2;
   L.chunk2 = (L.tiles2 + 7) / 8;
