@@ -22,8 +22,10 @@ pytestmark = pytest.mark.gpu
 TOL64 = 1e-12
 
 # (nx, ny): one tile; ragged tiles in x and y; several tiles; the most rows
-# two-level launches take (64); the smallest channel (both ends in one tile)
-SHAPES = [(80, 8), (150, 13), (517, 24), (200, 64), (6, 7)]
+# two-level launches take (64); the smallest channel (no tiles: the end blocks
+# own every column); one tile column; nine columns (the two ends' LDS strips
+# overlap); two rows (both walls)
+SHAPES = [(80, 8), (150, 13), (517, 24), (200, 64), (6, 7), (7, 5), (9, 11), (70, 2)]
 
 
 def _params(w, fused, dtype, hist_cap=512):
