@@ -1337,10 +1337,11 @@ constexpr bool kPairEnd = !MD::kDev;
 
 // Inlet (e = 0) or outlet (e = 1) block of k_sweep2 (a channel of at most 64
 // rows): columns 0 to 2 from the end at every level the launch computes, then
-// their sums over the rows (one wavefront per sum, fixed order): the end
-// column's to the end sums (end block 0 of the level's slot, zeros to the
-// rest), the other two columns' to row tile 0 of the partials (zeros to the
-// other row tiles).
+// their sums over the rows: the end column's to the end sums (end block 0 of
+// the level's slot, zeros to the rest), the other two columns' to row tile 0
+// of the partials (zeros to the other row tiles). The zeros go out first (no
+// reduction of this launch reads these levels' slots); each sum is a fixed
+// two-stage order (eight rows per thread, then the eight partial sums).
 template <class MD, bool NT>
 __device__ __forceinline__ void end_block2(const KParams& kp, const KBufs& kb, const Lv2& lv,
                                            const typename MD::St* __restrict__ src, typename MD::St* __restrict__ dst,
@@ -1349,6 +1350,22 @@ __device__ __forceinline__ void end_block2(const KParams& kp, const KBufs& kb, c
                                            double* Kv) {
   if (lv.nlev == 0) return;  // a reductions-only launch
   static_assert(sizeof(EndSums) <= sizeof(double) * 4 * kW2 * kTX, "the end sums fit the reduction scratch");
+  const int sgn = e ? -1 : 1, col = e ? kp.nx - 1 : 0;
+  const int t = threadIdx.x;
+  if (lv.reduce) {
+    const int nzp = 2 * 4 * (lv.nrt - 1), nze = 4 * (kp.nend - 1);  // per level
+    for (int z = t; z < lv.nlev * (nzp + nze); z += kT2) {
+      const int lev = z / (nzp + nze), r = z - lev * (nzp + nze);
+      const long long level = lv.t1 + lev;
+      if (r < nzp) {  // column 1 + r / (4 (nrt - 1)), quantity, row tile >= 1
+        const int c = 1 + r / (4 * (lv.nrt - 1)), q = (r / (lv.nrt - 1)) % 4, by = 1 + r % (lv.nrt - 1);
+        kb.partials[(level & 3) * lv.part_stride + ((long long)q * lv.nrt + by) * kp.pitch + col + sgn * c] = 0.0;
+      } else {  // end block >= 1
+        const int q = (r - nzp) % 4, blk = 1 + (r - nzp) / 4;
+        kb.endsum[(((level & 3) * 2 + e) * kMaxEnd + blk) * 4 + q] = 0.0;
+      }
+    }
+  }
   EndSums& V = *reinterpret_cast<EndSums*>(&red[0][0][0]);
   if (kPairEnd<MD>)
     end_block2_pair<MD, NT>(kp, src, dst, e, lv.nlev, Q, P, Kv, redk, V);
@@ -1356,23 +1373,30 @@ __device__ __forceinline__ void end_block2(const KParams& kp, const KBufs& kb, c
     end_block2_node<MD, NT>(kp, src, dst, e, lv.nlev, Q, P, Kv, redk, V);
   if (!lv.reduce) return;  // uniform over the block
   __syncthreads();
-  const int lane = threadIdx.x & (kTX - 1), w = threadIdx.x / kTX;
-  const int sgn = e ? -1 : 1, col = e ? kp.nx - 1 : 0;
-  for (int k = w; k < lv.nlev * kEndCols * 4; k += kW2) {  // wave-uniform
-    const int lev = k / (kEndCols * 4), c = (k / 4) % kEndCols, q = k % 4;
-    double v = lane < kp.ny ? V[lev][c][q][lane] : 0.0;
+  // sum k = (level, column, quantity): thread 8 k + g adds rows 8 g .. 8 g + 7
+  // into Kv (free once kappa is taken), then thread k adds the eight
+  const int nsum = lv.nlev * kEndCols * 4;
+  static_assert(2 * kEndCols * 4 * 8 <= 4 * kStripRows, "the partial sums fit Kv");
+  if (t < 8 * nsum) {
+    const int k = t >> 3, g = t & 7;
+    const double* v = V[k / (kEndCols * 4)][(k / 4) % kEndCols][k % 4];
+    double a = 0.0;
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+    for (int r = 0; r < 8; ++r)
+      if (8 * g + r < kp.ny) a += v[8 * g + r];
+    Kv[t] = a;
+  }
+  __syncthreads();
+  if (t < nsum) {
+    double a = 0.0;
+#pragma unroll
+    for (int g = 0; g < 8; ++g) a += Kv[8 * t + g];
+    const int lev = t / (kEndCols * 4), c = (t / 4) % kEndCols, q = t % 4;
     const long long level = lv.t1 + lev;
-    if (c == 0) {
-      double* es = kb.endsum + ((long long)(level & 3) * 2 + e) * kMaxEnd * 4;
-      if (lane == 0) es[q] = v;
-      for (int blk = 1 + lane; blk < kp.nend; blk += kTX) es[blk * 4 + q] = 0.0;
-    } else {
-      double* pt = kb.partials + (level & 3) * lv.part_stride + (long long)q * lv.nrt * kp.pitch + col + sgn * c;
-      if (lane == 0) pt[0] = v;
-      for (int by = 1 + lane; by < lv.nrt; by += kTX) pt[(long long)by * kp.pitch] = 0.0;
-    }
+    if (c == 0)
+      kb.endsum[(((level & 3) * 2 + e) * kMaxEnd) * 4 + q] = a;
+    else
+      kb.partials[(level & 3) * lv.part_stride + (long long)q * lv.nrt * kp.pitch + col + sgn * c] = a;
   }
 }
 
