@@ -546,9 +546,9 @@ __device__ __forceinline__ void process_pair(const KParams& kp, int x, int j, in
   const C rho_own = MD::kDev ? C(r_own) : c_own;
   const C jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
   const C jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
-  const C rho_oth = __shfl_xor(rho_own, XOR);
-  const C jx_oth = __shfl_xor(jx, XOR);
-  const C jy_oth = __shfl_xor(jy, XOR);
+  const C rho_oth = lane_xor(rho_own, XOR);
+  const C jx_oth = lane_xor(jx, XOR);
+  const C jy_oth = lane_xor(jy, XOR);
   const C rho_a = s ? rho_oth : rho_own;
   const C rho_b = s ? rho_own : rho_oth;
   const C jxa = s ? jx_oth : jx, jxb = s ? jx : jx_oth;
@@ -660,10 +660,10 @@ __device__ __forceinline__ void strip_reduce(const KParams& kp, const KBufs& kb,
     // wavefront tree reductions: min (ties -> smaller x), sum, max
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
-      const double ocl = __shfl_xor(cl, off);
-      const double oarg = __shfl_xor(arg, off);
-      const double odev = __shfl_xor(dev, off);
-      const double obad = __shfl_xor(bad, off);
+      const double ocl = lane_xor(cl, off);
+      const double oarg = lane_xor(arg, off);
+      const double odev = lane_xor(dev, off);
+      const double obad = lane_xor(bad, off);
       if (ocl < cl || (ocl == cl && oarg < arg)) {
         cl = ocl;
         arg = oarg;
@@ -697,10 +697,10 @@ __device__ __forceinline__ void global_reduce(const KParams& kp, const KBufs& kb
   }
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {
-    const double ocl = __shfl_xor(cl, off);
-    const double oarg = __shfl_xor(arg, off);
-    const double odev = __shfl_xor(dev, off);
-    const double obad = __shfl_xor(bad, off);
+    const double ocl = lane_xor(cl, off);
+    const double oarg = lane_xor(arg, off);
+    const double odev = lane_xor(dev, off);
+    const double obad = lane_xor(bad, off);
     if (ocl < cl || (ocl == cl && oarg < arg)) {
       cl = ocl;
       arg = oarg;
@@ -733,7 +733,7 @@ __device__ __forceinline__ void block_sum(double (*red)[kTY][kTX], const double*
   if (k < nv) {
     s = ((red[k][0][tx] + red[k][1][tx]) + red[k][2][tx]) + red[k][3][tx];
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
+    for (int off = 32; off >= 1; off >>= 1) s += lane_xor(s, off);
   }
   __syncthreads();
   if (k < nv && tx == 0) red[k][0][0] = s;
@@ -821,7 +821,7 @@ __device__ __forceinline__ void sweep_block(const KParams& kp, const KBufs& kb,
       // layer-1 values to the layer-0 lane of the same (row, species)
       C g2[9];
 #pragma unroll
-      for (int i = 0; i < 9; ++i) g2[i] = __shfl_xor(g[i], 1);
+      for (int i = 0; i < 9; ++i) g2[i] = lane_xor(g[i], 1);
       if (active && layer == 0) end_rebuild<MD>(kp, e, s, col, kap, km1, g, g2, f);
     } else {
       if (active && layer == 0) gather1<MD, false>(kp, src, s, col, j, f);

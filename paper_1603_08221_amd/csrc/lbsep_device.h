@@ -218,6 +218,20 @@ __device__ __forceinline__ void relaxation_times(const RelaxConsts& c, int j, T 
                    tau_q);
 }
 
+// The value v of lane (this lane ^ m). For m = 1 and m = 2 a DPP quad
+// permutation moves it in the vector ALU; other masks go through ds_bpermute
+// (__shfl_xor), a trip through the LDS crossbar. Both are exact moves. The
+// partner lane must be active.
+__device__ __forceinline__ int lane_xor(int v, int m) {
+  if (m == 1) return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true);  // quad_perm [1, 0, 3, 2]
+  if (m == 2) return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true);  // quad_perm [2, 3, 0, 1]
+  return __shfl_xor(v, m);
+}
+__device__ __forceinline__ float lane_xor(float v, int m) { return __int_as_float(lane_xor(__float_as_int(v), m)); }
+__device__ __forceinline__ double lane_xor(double v, int m) {
+  return __hiloint2double(lane_xor(__double2hiint(v), m), lane_xor(__double2loint(v), m));
+}
+
 // A lane pair per node (one lane per species, partner at lane ^ XOR): both
 // lanes hold the node's species densities; the seven evaluations are split
 // four / three between the lanes and the results swapped, so both lanes end
@@ -246,9 +260,9 @@ __device__ __forceinline__ void relaxation_times_pair(const RelaxConsts& c, int 
   if (s == 0) p3 = wall_psi_only(g.xa * ab);
   const T X = T(0.5) * (p0 + p1);           // lane a: Psi(y; l), lane b: Psi(y; l_b)
   const T Y = s ? p2 : T(0.5) * (p2 + p3);  // lane a: Psi(y; l_a), lane b: psi(H/l)
-  const T Xo = __shfl_xor(X, XOR);
-  const T Yo = __shfl_xor(Y, XOR);
-  const T Zo = __shfl_xor(h2, XOR);
+  const T Xo = lane_xor(X, XOR);
+  const T Yo = lane_xor(Y, XOR);
+  const T Zo = lane_xor(h2, XOR);
   const T pw = s ? Y : Yo;
   const T hw = s ? h2 : Zo;
   taus_from_psi<T>(c, g, s ? Xo : X, s ? Yo : Y, s ? X : Xo, T(0.5) * g.k * g.lam * pw, g.k * (T(1) - hw), tau_s,
