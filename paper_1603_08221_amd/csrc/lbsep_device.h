@@ -219,12 +219,17 @@ __device__ __forceinline__ void relaxation_times(const RelaxConsts& c, int j, T 
 }
 
 // The value v of lane (this lane ^ m). For m = 1 and m = 2 a DPP quad
-// permutation moves it in the vector ALU; other masks go through ds_bpermute
-// (__shfl_xor), a trip through the LDS crossbar. Both are exact moves. The
-// partner lane must be active.
+// permutation moves it in the vector ALU, for m = 32 v_permlane32_swap (its
+// first result holds the lower half twice, its second the upper half twice);
+// other masks go through ds_bpermute (__shfl_xor), a trip through the LDS
+// crossbar. All are exact moves. The partner lane must be active.
 __device__ __forceinline__ int lane_xor(int v, int m) {
   if (m == 1) return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true);  // quad_perm [1, 0, 3, 2]
   if (m == 2) return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true);  // quad_perm [2, 3, 0, 1]
+  if (m == 32) {
+    const auto r = __builtin_amdgcn_permlane32_swap((unsigned)v, (unsigned)v, false, false);
+    return (int)(__lane_id() < 32 ? r[1] : r[0]);
+  }
   return __shfl_xor(v, m);
 }
 __device__ __forceinline__ float lane_xor(float v, int m) { return __int_as_float(lane_xor(__float_as_int(v), m)); }
