@@ -992,11 +992,11 @@ struct Lv2 {
   int tiles, chunk;        // ntx * nrt, ceil(tiles / 8)
   int lead;                // lead blocks (multiple of 8) before the first tile
   long long part_stride;   // elements of one partials slot: 4 * nrt * pitch
-  long long t1;        // first level this launch computes (current level + 1)
-  int nlev;            // levels computed: 1 or 2
-  int reduce;          // write row-tile partials and end sums (0: a replay)
-  long long strip[2];  // levels to strip-reduce, -1 = none
-  long long glob[2];   // levels to reduce to a record, -1 = none
+  long long t1;            // first level this launch computes (current level + 1)
+  int nlev;                // levels computed: 1 or 2
+  int reduce;              // write row-tile partials and end sums (0: a replay)
+  long long strip[2];      // levels to strip-reduce, -1 = none
+  long long glob[2];       // levels to reduce to a record, -1 = none
 };
 
 // kappa of Eq. (rho2) for end e from each thread's two column sums

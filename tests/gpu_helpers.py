@@ -13,7 +13,7 @@ def oracle_params(w, r, **modes):
                     kn_out=w.kn_out, dbb_r=r, accom=w.accom, **modes)
 
 
-def channel(w, r, dtype="f64", tau_bgk=None, hist_cap=4096, tile_mode=0, tile_rows=0, **modes):
+def channel(w, r, dtype="f64", tau_bgk=None, hist_cap=4096, tile_mode=0, tile_rows=0, fused_steps=0, **modes):
     flags = 0
     for k, v in modes.items():
         if v:
@@ -22,7 +22,7 @@ def channel(w, r, dtype="f64", tau_bgk=None, hist_cap=4096, tile_mode=0, tile_ro
         flags |= lbsep.BGK_TEST
     p = lbsep.make_params(w.nx, w.ny, w.m_a, w.m_b, w.cl_in, w.cl_out, w.theta, w.kn_out, r, accom=w.accom,
                           tau_bgk=tau_bgk or 0.0, flags=flags, dtype=dtype, hist_cap=hist_cap,
-                          tile_mode=tile_mode, tile_rows=tile_rows)
+                          tile_mode=tile_mode, tile_rows=tile_rows, fused_steps=fused_steps)
     return lbsep.Channel(p, device="cuda:0")
 
 

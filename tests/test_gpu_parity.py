@@ -25,9 +25,9 @@ TOL32 = 1e-5
 CL64 = 1e-12
 
 
-def _run_both(w, steps, dtype="f64", **modes):
+def _run_both(w, steps, dtype="f64", levels=0, **modes):
     r = r_of(w)
-    ch = channel(w, r, dtype=dtype, **modes)
+    ch = channel(w, r, dtype=dtype, fused_steps=levels, **modes)
     ch.step(steps)
     mom = ch.read_moments()
     cl = ch.read_cl(profile=True)
@@ -99,13 +99,15 @@ def test_fp32_he_ar_8x80():
     assert abs(cl["cl"] - d.cl) < TOL32
 
 
+@pytest.mark.parametrize("levels", [1, 2])
 @pytest.mark.parametrize("dtype,tol", [("f64", TOL64), ("f32", TOL32)])
-def test_full_size_ne_ar_64x1280(dtype, tol):
-    """The benchmark's channel at its real size and launch configuration."""
+def test_full_size_ne_ar_64x1280(dtype, tol, levels):
+    """The benchmark's channel at its real size, one and two time levels per
+    launch (bench.py times two)."""
     w = CONFIGS["ne_ar_64x1280"]
     steps = 40
-    print(f"[case] {dtype} {w.name} {steps} steps", flush=True)
-    ch, mom, cl, ref, d = _run_both(w, steps, dtype=dtype)
+    print(f"[case] {dtype} {w.name} {steps} steps, {levels} level(s) per launch", flush=True)
+    ch, mom, cl, ref, d = _run_both(w, steps, dtype=dtype, levels=levels)
     assert_moments(mom, ref, tol, w.name)
     assert abs(cl["cl"] - d.cl) <= (CL64 if dtype == "f64" else tol)
 
