@@ -74,6 +74,31 @@ def test_two_levels_per_launch_match_single_levels(dtype, shape):
     np.testing.assert_allclose(hb[:, 1:3], ha[:, 1:3], rtol=1e-11, atol=1e-14)
 
 
+VARIANTS = {
+    # the wall function off (constant relaxation times from the mean free path)
+    "mfp_off": dict(flags=lbsep.MFP_OFF),
+    # single-relaxation-time test mode
+    "bgk": dict(flags=lbsep.BGK_TEST, tau_bgk=0.9),
+    # unequal inlet and outlet concentrations, partial accommodation
+    "cl_in_ne_cl_out": dict(cl_out=0.45, accom=0.7),
+}
+
+
+@pytest.mark.parametrize("variant", sorted(VARIANTS))
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_two_levels_per_launch_with_model_variants(dtype, variant):
+    kw = dict(VARIANTS[variant])
+    w = Workload("fused", 90, 12, *HE_AR, 0.3, kw.pop("cl_out", 0.6), 2.0, 0.1, 0)
+    mk = lambda fused: lbsep.Channel(lbsep.make_params(w.nx, w.ny, w.m_a, w.m_b, w.cl_in, w.cl_out, w.theta,
+                                                       w.kn_out, r_of(w), dtype=dtype, hist_cap=512,
+                                                       fused_steps=fused, **kw))
+    a, b = mk(1), mk(2)
+    for n in (4, 7):
+        a.step(n)
+        b.step(n)
+        _agree(a, b, f"{variant}, t = {a.t}", dtype)
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_checkpoint_after_a_two_level_launch_resumes_bitwise(dtype):
     w = CONFIGS["he_ar_8x80"].with_(nx=130, ny=20)
