@@ -442,7 +442,8 @@ __device__ void block_sum2(double& u, double& v, double (*sh)[kAT / 64]) {
 // closure's dependence on them) and the rho_bc partials part[e][s][0..1].
 // Two passes over the column: the sums S = sum_j rho'(j) and
 // kappa-bar = sum_j A(j) rho'(j) / rho_node(j) (neither needs kappa), then the
-// per-row adjoints.
+// per-row adjoints. With at most 256 rows each thread keeps its row's pulled
+// populations in registers between the passes.
 __global__ __launch_bounds__(kAT) void k_adj_ends(AdjParams ap, const double* __restrict__ fpost,
                                                   const double* __restrict__ lam_next, double* __restrict__ lamP,
                                                   double* __restrict__ part) {
@@ -453,13 +454,15 @@ __global__ __launch_bounds__(kAT) void k_adj_ends(AdjParams ap, const double* __
   const int ny = ap.ny;
   double* out = lamP + (long long)(e * 2 + s) * 3 * 9 * ny;  // [c][i][j]
   auto unknown = [&](int i) { return e == 0 ? kCx[i] == 1 : kCx[i] == -1; };
-  // pass 1: S and kappa-bar
-  double accS = 0.0, accK = 0.0;
-  for (int j = threadIdx.x; j < ny; j += kAT) {
-    double g0[9], g1[9], g2[9];
+  // row j's pulled populations of the end column and the two inner layers
+  auto load = [&](int j, double g0[9], double g1[9], double g2[9]) {
     pulled(ap, fpost, s, col, j, g0);
     pulled(ap, fpost, s, l1, j, g1);
     pulled(ap, fpost, s, l2, j, g2);
+  };
+  // pass 1 of row j: its shares of S and kappa-bar
+  auto shares = [&](int j, const double g0[9], const double g1[9], const double g2[9], double& accS,
+                    double& accK) {
     double r1 = 0, r2 = 0, rn = 0, A = 0;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
@@ -472,16 +475,11 @@ __global__ __launch_bounds__(kAT) void k_adj_ends(AdjParams ap, const double* __
     const double rp = 2.0 * r1 - r2;
     accS += rp;
     accK += A * rp / rn;
-  }
-  block_sum2(accS, accK, sh);
-  const double S = accS, kbar = accK;
-  const double kappa = double(ny) * ap.rho_bc[e][s] / S;
-  // pass 2: per-row adjoints
-  for (int j = threadIdx.x; j < ny; j += kAT) {
-    double g0[9], g1[9], g2[9], gh[9], lE[9];
-    pulled(ap, fpost, s, col, j, g0);
-    pulled(ap, fpost, s, l1, j, g1);
-    pulled(ap, fpost, s, l2, j, g2);
+  };
+  // pass 2 of row j: the adjoints of the three columns' pulled populations
+  auto adjoints = [&](int j, const double g0[9], const double g1[9], const double g2[9], double kappa, double S,
+                      double kbar) {
+    double gh[9], lE[9];
     double r1 = 0, r2 = 0, rn = 0, A = 0;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
@@ -510,10 +508,37 @@ __global__ __launch_bounds__(kAT) void k_adj_ends(AdjParams ap, const double* __
       out[(1 * 9 + i) * ny + j] = b1;
       out[(2 * 9 + i) * ny + j] = b2;
     }
+  };
+  double accS = 0.0, accK = 0.0;
+  if (ny <= kAT) {
+    // one row per thread: the pulled values stay in registers for pass 2
+    const int j = threadIdx.x;
+    double g0[9], g1[9], g2[9];
+    if (j < ny) {
+      load(j, g0, g1, g2);
+      shares(j, g0, g1, g2, accS, accK);
+    }
+    block_sum2(accS, accK, sh);
+    const double kappa = double(ny) * ap.rho_bc[e][s] / accS;
+    if (j < ny) adjoints(j, g0, g1, g2, kappa, accS, accK);
+  } else {
+    for (int j = threadIdx.x; j < ny; j += kAT) {
+      double g0[9], g1[9], g2[9];
+      load(j, g0, g1, g2);
+      shares(j, g0, g1, g2, accS, accK);
+    }
+    block_sum2(accS, accK, sh);
+    const double kappa = double(ny) * ap.rho_bc[e][s] / accS;
+    for (int j = threadIdx.x; j < ny; j += kAT) {
+      double g0[9], g1[9], g2[9];
+      load(j, g0, g1, g2);
+      adjoints(j, g0, g1, g2, kappa, accS, accK);
+    }
   }
   if (threadIdx.x == 0) {
     // d J / d rho_bc = kappa-bar N / S; only the inlet densities depend on (theta, C_in)
-    const double brho = kbar * double(ny) / S;
+    const double kappa_bar = accK, S = accS;
+    const double brho = kappa_bar * double(ny) / S;
     part[(e * 2 + s) * 2 + 0] = e == 0 ? brho * ap.drho_in[0][s] : 0.0;
     part[(e * 2 + s) * 2 + 1] = e == 0 ? brho * ap.drho_in[1][s] : 0.0;
   }
