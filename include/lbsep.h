@@ -142,6 +142,17 @@ int lbsep_init(const lbsep_params* params, void* dev_ws, size_t ws_bytes, void* 
  * (Eqs. (C), (CL), (Clline)) recorded for that step. Enqueues only. */
 int lbsep_step(lbsep_channel* ch, int64_t nsteps);
 
+/* One step as lbsep_step (same state, same record) that also writes, in
+ * double and the dense layout of lbsep_get_populations (2 * 9 * ny * nx
+ * doubles each, caller-owned device memory), the new level's pre-collision
+ * populations f(t+1) to dev_pre and its post-collision populations
+ * C(f(t+1)) to dev_post: what lbsep_get_populations and
+ * lbsep_get_post_collision would return after the step, from the sweep
+ * itself. For the recomputation of the adjoint's segments. Needs an FP64
+ * channel with one level per launch (fused_steps 0 or 1): LBSEP_EINVAL
+ * otherwise, or when a pointer is NULL. Enqueues only. */
+int lbsep_step_record(lbsep_channel* ch, double* dev_pre, double* dev_post);
+
 /* Current time level t (number of steps since the initial/loaded state plus its t). */
 int64_t lbsep_time(const lbsep_channel* ch);
 

@@ -87,6 +87,7 @@ def cl_gradient(params: lbsep.Params, nsteps: int, checkpoint_every: int = 500, 
     tensor[3])."""
     ch = lbsep.Channel(params, device=device)
     adj = Adjoint(ch)
+    record = params.dtype == lbsep.F64 and params.fused_steps != 2
     ckpt = {0: ch.get_state()}
     t = 0
     while t < nsteps:
@@ -102,10 +103,16 @@ def cl_gradient(params: lbsep.Params, nsteps: int, checkpoint_every: int = 500, 
     for t0 in reversed(starts):
         t1 = min(t0 + checkpoint_every, nsteps)
         ch.set_state(ckpt[t0], t0)
-        seg = []
-        for _ in range(t0, t1):
-            seg.append((ch.get_populations(), ch.get_post_collision()))
-            ch.step(1)
+        # the segment's (f(t), C(f(t))) for t = t0 .. t1 - 1: the restored level
+        # read out, the following levels written by the steps themselves
+        # (recording steps, FP64 one level per launch) or read out after them
+        seg = [(ch.get_populations(), ch.get_post_collision())]
+        for _ in range(t0 + 1, t1):
+            if record:
+                seg.append(ch.step_record())
+            else:
+                ch.step(1)
+                seg.append((ch.get_populations(), ch.get_post_collision()))
         for k in range(len(seg) - 1, -1, -1):
             adj.step(seg[k][0], lam, out=spare, f_post=seg[k][1])
             lam, spare = spare, lam

@@ -507,16 +507,38 @@ __device__ __forceinline__ void node_store(const KParams& kp, int x, int j, cons
   }
 }
 
-// node_moments, then (STEP) the collision and the store.
-template <class MD, bool EVAL, bool NT = false>
+// Species s of node (x, j) to the dense FP64 array out[2][9][ny][nx] (a
+// recording step of an FP64 channel: the populations themselves).
+template <class MD>
+__device__ __forceinline__ void dense_out(const KParams& kp, int x, int j, int s, const typename MD::Ct f[9],
+                                          double* __restrict__ out) {
+  static_assert(!MD::kDev, "recording steps hold plain populations");
+  const long long n = (long long)kp.nx * kp.ny, o = (long long)j * kp.nx + x;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) out[(9 * s + i) * n + o] = double(f[i]);
+}
+
+// node_moments, then (STEP) the collision and the store. REC (a recording
+// step): ffull receives the pulled populations and fpost the post-collision
+// ones, both dense.
+template <class MD, bool EVAL, bool NT = false, bool REC = false>
 __device__ __forceinline__ void process_node(const KParams& kp, int x, int j, typename MD::Ct fa[9],
                                              typename MD::Ct fb[9], typename MD::St* __restrict__ dst,
                                              double* __restrict__ mom, typename MD::St* __restrict__ fraw,
-                                             double* __restrict__ ffull, double acc[4]) {
+                                             double* __restrict__ ffull, double acc[4],
+                                             double* __restrict__ fpost = nullptr) {
   const NodeState<typename MD::Ct> st = node_moments<MD, EVAL>(kp, x, j, fa, fb, mom, fraw, ffull, acc);
   if (!EVAL) {
+    if constexpr (REC) {
+      dense_out<MD>(kp, x, j, 0, fa, ffull);
+      dense_out<MD>(kp, x, j, 1, fb, ffull);
+    }
     node_collide_only<MD>(kp, fa, fb, st);
     node_store<MD, NT>(kp, x, j, fa, fb, dst);
+    if constexpr (REC) {
+      dense_out<MD>(kp, x, j, 0, fa, fpost);
+      dense_out<MD>(kp, x, j, 1, fb, fpost);
+    }
   }
 }
 
@@ -528,12 +550,13 @@ __device__ __forceinline__ void process_node(const KParams& kp, int x, int j, ty
 // species' (n_s, rho_s u_sx) in double. STORE == false leaves the
 // post-collision populations in f instead of storing them to dst; SEL picks
 // the per-species parameters by selects (kernels in which a dynamic index
-// would move the parameter block to scratch memory).
-template <class MD, bool EVAL, int XOR, bool STORE = true, bool SEL = false>
+// would move the parameter block to scratch memory); REC as in process_node.
+template <class MD, bool EVAL, int XOR, bool STORE = true, bool SEL = false, bool REC = false>
 __device__ __forceinline__ void process_pair(const KParams& kp, int x, int j, int s, bool active,
                                              typename MD::Ct f[9], typename MD::St* __restrict__ dst,
                                              double* __restrict__ mom, typename MD::St* __restrict__ fraw,
-                                             double* __restrict__ ffull, double acc[2]) {
+                                             double* __restrict__ ffull, double acc[2],
+                                             double* __restrict__ fpost = nullptr) {
   using C = typename MD::Ct;
   using E = E1Traits<C>;
   if (!active) {
@@ -591,8 +614,12 @@ __device__ __forceinline__ void process_pair(const KParams& kp, int x, int j, in
     weps = C(1.0 / 1.2);  // tau_eps = 1.2
   }
   const C wd = C(2) * h2, wq = E::rcp(tq);
+  if constexpr (REC) {
+    if (active) dense_out<MD>(kp, x, j, s, f, ffull);
+  }
   collide_species<C>(f, c_own, rho_own, ux, uy, C(species_param<SEL>(kp.rc.s, s)), we, weps, wd, wq, ws);
   if (!active) return;
+  if constexpr (REC) dense_out<MD>(kp, x, j, s, f, fpost);
   acc[0] += r_own * species_param<SEL>(kp.rc.inv_m, s);
   acc[1] += double(px);
   if (!STORE) return;
@@ -742,7 +769,7 @@ __device__ __forceinline__ void block_sum(double (*red)[kTY][kTX], const double*
 
 // One block of the fused sweep of a channel, block index b of the channel's
 // own grid (lead blocks, then XCD-interleaved tiles).
-template <class MD, bool PULL, bool EVAL, bool SPLIT, bool NT>
+template <class MD, bool PULL, bool EVAL, bool SPLIT, bool NT, bool REC = false>
 __device__ __forceinline__ void sweep_block(const KParams& kp, const KBufs& kb,
                                             const typename MD::St* __restrict__ src, typename MD::St* __restrict__ dst,
                                             double* __restrict__ mom, typename MD::St* __restrict__ fraw,
@@ -827,7 +854,8 @@ __device__ __forceinline__ void sweep_block(const KParams& kp, const KBufs& kb,
       if (active && layer == 0) gather1<MD, false>(kp, src, s, col, j, f);
     }
     double acc2[2] = {0.0, 0.0};
-    process_pair<MD, EVAL, 2>(kp, col, j, s, active && layer == 0, f, dst, mom, fraw, ffull, acc2);
+    process_pair<MD, EVAL, 2, true, false, REC>(kp, col, j, s, active && layer == 0, f, dst, mom, fraw, ffull, acc2,
+                                                reinterpret_cast<double*>(fraw));
     if (EVAL) return;
     const double acc[4] = {s ? 0.0 : acc2[0], s ? acc2[0] : 0.0, s ? 0.0 : acc2[1], s ? acc2[1] : 0.0};
     block_sum(red, acc, 4);
@@ -867,7 +895,8 @@ __device__ __forceinline__ void sweep_block(const KParams& kp, const KBufs& kb,
       if (j < kp.ny) {  // wave-uniform
         C f[9];
         if (xin) gather1<MD, PULL>(kp, src, s, x, j, f);
-        process_pair<MD, EVAL, 32>(kp, x, j, s, xin, f, dst, mom, fraw, ffull, acc);
+        process_pair<MD, EVAL, 32, true, false, REC>(kp, x, j, s, xin, f, dst, mom, fraw, ffull, acc,
+                                                     reinterpret_cast<double*>(fraw));
       }
     }
     if (EVAL) return;
@@ -894,7 +923,7 @@ __device__ __forceinline__ void sweep_block(const KParams& kp, const KBufs& kb,
       if (xin && j < kp.ny) {
         C fa[9], fb[9];
         gather_pair<MD, PULL>(kp, src, x, j, fa, fb);
-        process_node<MD, EVAL, NT>(kp, x, j, fa, fb, dst, mom, fraw, ffull, acc);
+        process_node<MD, EVAL, NT, REC>(kp, x, j, fa, fb, dst, mom, fraw, ffull, acc, reinterpret_cast<double*>(fraw));
       }
     }
     if (EVAL) return;
@@ -909,14 +938,17 @@ __device__ __forceinline__ void sweep_block(const KParams& kp, const KBufs& kb,
   }
 }
 
-template <class MD, bool PULL, bool EVAL, bool SPLIT, bool NT>
+// REC (a recording step of an FP64 channel): besides the step, ffull receives
+// the pulled (pre-collision) populations and fraw the post-collision ones,
+// both dense [2][9][ny][nx].
+template <class MD, bool PULL, bool EVAL, bool SPLIT, bool NT, bool REC = false>
 __global__ __launch_bounds__(kThreads) void k_sweep(KParams kp, KBufs kb, const typename MD::St* __restrict__ src,
                                                     typename MD::St* __restrict__ dst, double* __restrict__ mom,
                                                     typename MD::St* __restrict__ fraw,
                                                     double* __restrict__ ffull, long long t,
                                                     long long t_first) {
   __shared__ double red[4][kTY][kTX];
-  sweep_block<MD, PULL, EVAL, SPLIT, NT>(kp, kb, src, dst, mom, fraw, ffull, t, t_first, (int)blockIdx.x, red);
+  sweep_block<MD, PULL, EVAL, SPLIT, NT, REC>(kp, kb, src, dst, mom, fraw, ffull, t, t_first, (int)blockIdx.x, red);
 }
 
 // A batch of channels swept by one launch: entry i holds channel i's constants,
@@ -2145,6 +2177,32 @@ int lbsep_step(lbsep_channel* h, int64_t nsteps) {
 }
 
 int64_t lbsep_time(const lbsep_channel* h) { return h ? h->t : -1; }
+
+int lbsep_step_record(lbsep_channel* h, double* dev_pre, double* dev_post) {
+  if (!h) return fail(LBSEP_EINVAL, "channel is NULL");
+  if (!dev_pre || !dev_post) return fail(LBSEP_EINVAL, "dev_pre and dev_post must be device pointers");
+  if (h->p.dtype != LBSEP_F64) return fail(LBSEP_EINVAL, "lbsep_step_record needs an FP64 channel");
+  if (h->L.two) return fail(LBSEP_EINVAL, "lbsep_step_record needs one level per launch (fused_steps 0 or 1)");
+  const int nxt_buf = 1 - h->cur;
+  const int grid = h->L.lead + 8 * h->L.chunk;
+  const double* src = static_cast<const double*>(h->f[h->cur]);
+  double* dst = static_cast<double*>(h->f[nxt_buf]);
+  // the recording variant: ffull <- pulled populations, fraw <- post-collision
+  if (h->L.split)
+    hipLaunchKernelGGL((k_sweep<ModeF64, true, false, true, false, true>), dim3(grid), dim3(kThreads), 0, h->stream,
+                       h->kp, h->kb, src, dst, nullptr, dev_post, dev_pre, (long long)(h->t + 1),
+                       (long long)h->t_first);
+  else
+    hipLaunchKernelGGL((k_sweep<ModeF64, true, false, false, false, true>), dim3(grid), dim3(kThreads), 0,
+                       h->stream, h->kp, h->kb, src, dst, nullptr, dev_post, dev_pre, (long long)(h->t + 1),
+                       (long long)h->t_first);
+  h->prev_buf = h->cur;
+  h->cur = nxt_buf;
+  h->prev_pre = false;
+  h->t += 1;
+  h->finalized = false;
+  return check_hip(hipGetLastError(), "step launch");
+}
 
 int lbsep_read_cl(lbsep_channel* h, double* cl, double* cl_tilde, int32_t* x_min, double* profile) {
   if (!h) return fail(LBSEP_EINVAL, "channel is NULL");

@@ -72,6 +72,7 @@ def load():
         "lbsep_set_state": (c_int, [c_void_p, c_void_p, c_int64]),
         "lbsep_get_populations": (c_int, [c_void_p, c_void_p]),
         "lbsep_get_post_collision": (c_int, [c_void_p, c_void_p]),
+        "lbsep_step_record": (c_int, [c_void_p, c_void_p, c_void_p]),
         "lbsep_set_populations": (c_int, [c_void_p, c_void_p, c_int64]),
         "lbsep_dbb_r_from_cm": (c_double, [c_double, c_double, c_double, c_double]),
         "lbsep_wall_function": (c_int, [c_void_p, c_void_p, c_void_p, c_int64, c_int32, c_void_p]),
@@ -179,6 +180,22 @@ class Channel:
     # -- stepping ------------------------------------------------------------
     def step(self, nsteps: int = 1):
         _check(load().lbsep_step(self._h, int(nsteps)))
+
+    def step_record(self, pre: torch.Tensor | None = None, post: torch.Tensor | None = None):
+        """One step that also returns the new level's pre- and post-collision
+        populations (float64 [2, 9, ny, nx]; FP64 channels with one level per
+        launch)."""
+        if pre is None:
+            pre = torch.empty((2, 9, self.ny, self.nx), dtype=torch.float64, device=self.device)
+        if post is None:
+            post = torch.empty_like(pre)
+        for a in (pre, post):
+            if a.dtype != torch.float64 or a.shape != (2, 9, self.ny, self.nx) or not a.is_contiguous():
+                raise LbsepError("step_record outputs must be contiguous float64 [2, 9, ny, nx]")
+        _check(load().lbsep_step_record(self._h, c_void_p(pre.data_ptr()), c_void_p(post.data_ptr())))
+        self._hand_over(pre)
+        self._hand_over(post)
+        return pre, post
 
     @property
     def t(self) -> int:

@@ -61,6 +61,36 @@ def test_post_collision_state_is_the_collision_of_the_populations(dtype, tol):
     assert _rel(got, ref) <= tol
 
 
+@pytest.mark.parametrize("shape,tile_mode", [((90, 12), lbsep.TILE_NODE), ((90, 12), lbsep.TILE_SPLIT),
+                                             ((70, 130), lbsep.TILE_AUTO)],
+                         ids=["node", "pair", "three-end-blocks"])
+def test_recording_step_writes_what_the_readouts_return(shape, tile_mode):
+    """A recording step's pre- and post-collision outputs are bitwise the
+    readouts after a plain step from the same state, and the two channels
+    stay bitwise equal."""
+    w = SMALL.with_(nx=shape[0], ny=shape[1])
+    r = r_of(w)
+    a, b = channel(w, r, tile_mode=tile_mode), channel(w, r, tile_mode=tile_mode)
+    a.step(9)
+    b.step(9)
+    for _ in range(3):
+        pre, post = a.step_record()
+        b.step(1)
+        assert torch.equal(pre, b.get_populations())
+        assert torch.equal(post, b.get_post_collision())
+        assert torch.equal(a.get_state(), b.get_state())
+    assert a.read_cl()["cl"] == b.read_cl()["cl"]
+
+
+def test_recording_step_needs_fp64_single_level():
+    w = SMALL
+    r = r_of(w)
+    with pytest.raises(lbsep.LbsepError, match="FP64"):
+        channel(w, r, dtype="f32").step_record()
+    with pytest.raises(lbsep.LbsepError, match="one level per launch"):
+        channel(w, r, fused_steps=2).step_record()
+
+
 def test_adjoint_step_with_the_forward_post_collision_state():
     """lam(t) and the parameter partials with f_post from the forward agree with
     the step that recomputes C(f_t) itself (same map, two FP64 evaluations)."""
