@@ -61,16 +61,18 @@ def test_post_collision_state_is_the_collision_of_the_populations(dtype, tol):
     assert _rel(got, ref) <= tol
 
 
-@pytest.mark.parametrize("shape,tile_mode", [((90, 12), lbsep.TILE_NODE), ((90, 12), lbsep.TILE_SPLIT),
-                                             ((70, 130), lbsep.TILE_AUTO)],
-                         ids=["node", "pair", "three-end-blocks"])
-def test_recording_step_writes_what_the_readouts_return(shape, tile_mode):
+@pytest.mark.parametrize("shape,tile_mode,modes", [((90, 12), lbsep.TILE_NODE, {}),
+                                                   ((90, 12), lbsep.TILE_SPLIT, {}),
+                                                   ((70, 130), lbsep.TILE_AUTO, {}),
+                                                   ((48, 10), lbsep.TILE_AUTO, {"periodic_x": True})],
+                         ids=["node", "pair", "three-end-blocks", "periodic-x"])
+def test_recording_step_writes_what_the_readouts_return(shape, tile_mode, modes):
     """A recording step's pre- and post-collision outputs are bitwise the
     readouts after a plain step from the same state, and the two channels
     stay bitwise equal."""
     w = SMALL.with_(nx=shape[0], ny=shape[1])
     r = r_of(w)
-    a, b = channel(w, r, tile_mode=tile_mode), channel(w, r, tile_mode=tile_mode)
+    a, b = channel(w, r, tile_mode=tile_mode, **modes), channel(w, r, tile_mode=tile_mode, **modes)
     a.step(9)
     b.step(9)
     for _ in range(3):
