@@ -186,9 +186,8 @@ __device__ __forceinline__ T sum9(const T f[9]) {
 // !PULL: read in place (src already holds a pre-collision state).
 // On the inlet/outlet columns the directions that would come from outside the
 // channel are loaded from the node itself (kept in range) and replaced by the
-// caller. SEL: the streaming correction by a select between the species (see
-// species_param).
-template <class MD, bool PULL, bool SEL = false>
+// caller.
+template <class MD, bool PULL>
 __device__ __forceinline__ void gather1(const KParams& kp, const typename MD::St* __restrict__ src, int s, int x,
                                         int j, typename MD::Ct f[9]) {
   using C = typename MD::Ct;
@@ -222,7 +221,7 @@ __device__ __forceinline__ void gather1(const KParams& kp, const typename MD::St
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     f[i] = C(*pop_at(kp, src, s, i, sy[i], sx[i]));
-    if (MD::kDev && (i == 1 || i == 3 || i >= 5)) f[i] += C(SEL ? (s ? kp.corr[1][i] : kp.corr[0][i]) : kp.corr[s][i]);
+    if (MD::kDev && (i == 1 || i == 3 || i >= 5)) f[i] += C(kp.corr[s][i]);
   }
   if (bot || top) {
     // Eqs. (bot)/(bot2): the populations that would come from outside the
