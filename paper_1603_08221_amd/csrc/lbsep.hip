@@ -1444,7 +1444,9 @@ __device__ __forceinline__ void tile2(const KParams& kp, const KBufs& kb, const 
   const int k = (b - lv.lead) >> 3;
   const int lin = xcd * lv.chunk + k;
   if (lin >= lv.tiles) return;  // uniform over the block
-  const int by = lin / lv.ntx, bx = lin - by * lv.ntx;
+  // column strips in order: an XCD's tiles share their halo rows in its L2, and
+  // the first and last strips sit on the XCDs of the inlet and outlet blocks
+  const int bx = lin / lv.nrt, by = lin - bx * lv.nrt;
   const int lane = threadIdx.x & (kTX - 1);
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kTX);
   const int x0 = kEndCols + kC2 * bx;  // first owned column
@@ -1523,13 +1525,16 @@ __global__ __launch_bounds__(kT2) void k_sweep2(KParams kp, KBufs kb, Lv2 lv, co
   double (*redk)[kTY][kTX] = reinterpret_cast<double (*)[kTY][kTX]>(&red[0][0][0]);
   const int b = blockIdx.x;
   if (b < lv.lead) {
-    if (b < 2) {
+    // the inlet block is block 0 (XCD 0, with the first column strips), the
+    // outlet block block 7 (XCD 7, with the last ones); the other lead blocks
+    // reduce, in order
+    if (b == 0 || b == 7) {
       if (!(kp.flags & LBSEP_PERIODIC_X))
-        end_block2<MD, NT>(kp, kb, lv, src, dst, b, red, redk,
+        end_block2<MD, NT>(kp, kb, lv, src, dst, b == 7, red, redk,
                            reinterpret_cast<typename MD::Pt (*)[kStripRows][9]>(&lds[0][0][0]), pulled, kv);
       return;
     }
-    const int r = b - 2;
+    const int r = b < 7 ? b - 1 : b - 2;
     if (r < kp.nxt) {
       // strip reductions in two 256-thread groups, task = (level, strip)
       const int g = threadIdx.x / kThreads;
