@@ -740,7 +740,7 @@ __device__ __forceinline__ void global_reduce(const KParams& kp, const KBufs& kb
     h[1] = (kp.cl_in - cl) / kp.cl_in;        // Eq. (CL)
     h[2] = dev / (double(kp.nx) * kp.cl_in);  // Eq. (Clline)
     h[3] = arg;
-    if (bad != 0.0) kb.status[0] |= 1u;       // single writer per launch
+    if (bad != 0.0) kb.status[0] |= 1u;       // one writing wavefront per launch
   }
 }
 
@@ -1545,8 +1545,11 @@ __global__ __launch_bounds__(kT2) void k_sweep2(KParams kp, KBufs kb, Lv2 lv, co
       strip_reduce(kp, kb, bx, level, int(level & 3), lv.nrt, lv.part_stride, redk + 4 * g,
                    threadIdx.x & (kThreads - 1), level >= 0, last);
     } else if (r == kp.nxt) {
-      const int w = threadIdx.x / kTX;
-      if (w < 2 && lv.glob[w] >= 0) global_reduce(kp, kb, lv.glob[w], int(lv.glob[w] & 3));
+      // the records of up to two levels by one wavefront, in level order: a
+      // history ring of one slot keeps the later one
+      if (threadIdx.x < kTX)
+        for (int k = 0; k < 2; ++k)
+          if (lv.glob[k] >= 0) global_reduce(kp, kb, lv.glob[k], int(lv.glob[k] & 3));
     }
     return;
   }

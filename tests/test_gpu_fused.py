@@ -118,6 +118,25 @@ def test_checkpoint_after_a_two_level_launch_resumes_bitwise(dtype):
     assert torch.equal(a.get_post_collision(), c.get_post_collision())
 
 
+@pytest.mark.parametrize("hist_cap", [1, 3, 4])
+def test_history_ring_wraps_inside_two_level_launches(hist_cap):
+    """A history ring shorter than a launch's two records: the last hist_cap
+    records agree with single-level launches, older levels are out of range."""
+    w = CONFIGS["he_ar_8x80"].with_(nx=120, ny=10)
+    a = lbsep.Channel(_params(w, 1, "f64", hist_cap=hist_cap))
+    b = lbsep.Channel(_params(w, 2, "f64", hist_cap=hist_cap))
+    for n in (5, 6, 3):
+        a.step(n)
+        b.step(n)
+        t0 = a.t - hist_cap + 1
+        ha, hb = a.read_history(t0, hist_cap), b.read_history(t0, hist_cap)
+        np.testing.assert_array_equal(hb[:, 0], ha[:, 0])
+        np.testing.assert_array_equal(hb[:, 3], ha[:, 3])
+        np.testing.assert_allclose(hb[:, 1:3], ha[:, 1:3], rtol=1e-11, atol=1e-14)
+        with pytest.raises(lbsep.LbsepError):
+            b.read_history(t0 - 1, 1)
+
+
 def test_moments_after_a_two_level_launch():
     w = CONFIGS["he_ar_8x80"].with_(nx=100, ny=12)
     a, b = _pair(w, "f64")
