@@ -137,6 +137,24 @@ def test_history_ring_wraps_inside_two_level_launches(hist_cap):
             b.read_history(t0 - 1, 1)
 
 
+def test_set_populations_restarts_the_two_level_pipeline():
+    """Physical populations loaded into a two-level channel mid-run continue
+    bitwise like a single-level channel loaded with the same populations."""
+    w = CONFIGS["he_ar_8x80"].with_(nx=110, ny=14)
+    src = lbsep.Channel(_params(w, 1, "f64"))
+    src.step(13)
+    f, t = src.get_populations(), src.t
+    a = lbsep.Channel(_params(w, 1, "f64"))
+    b = lbsep.Channel(_params(w, 2, "f64"))
+    b.step(6)  # mid-run: levels pending in the two-level pipeline
+    a.set_populations(f, t)
+    b.set_populations(f, t)
+    for n in (2, 5):
+        a.step(n)
+        b.step(n)
+        _agree(a, b, f"after set_populations, t = {a.t}")
+
+
 def test_moments_after_a_two_level_launch():
     w = CONFIGS["he_ar_8x80"].with_(nx=100, ny=12)
     a, b = _pair(w, "f64")
