@@ -48,10 +48,10 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str, dtype: str, levels: int = 1):
+def measured_traffic(workload: str, dtype: str, levels: int = 1, tiles: str = None):
     """HBM bytes per launch (of `levels` time levels) from the committed
-    rocprofv3 PMC summary, if it was taken on the current kernel source; else
-    None."""
+    rocprofv3 PMC summary, if it was taken on the current kernel source (and,
+    for a batch, with the same tile assignment `tiles`); else None."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     want = source_hash()
@@ -60,7 +60,7 @@ def measured_traffic(workload: str, dtype: str, levels: int = 1):
             continue
         kv = dict(tok.split("=", 1) for tok in line.split())
         if (kv.get("workload") == workload and kv.get("dtype") == dtype and kv.get("source") == want
-                and int(kv.get("levels", "1")) == levels):
+                and int(kv.get("levels", "1")) == levels and kv.get("tiles") == tiles):
             return float(kv["bytes_per_launch"])
     return None
 
@@ -140,7 +140,7 @@ def batch_leg(torch, lbsep, dtype: str, steps: int):
             "frac_of_hbm_peak": round(alg / per / 1e9 / HBM_PEAK_GBS, 4), "tiles": tuned["name"],
             "tuning_ms_per_step": {k: round(v, 4) for k, v in tuned["timings"].items()},
             "graph_steps": 100, "diverged_members": diverged,
-            "traffic": (lambda v: None if v is None else round(v))(measured_traffic("sweep_table_64", dtype)),
+            "traffic": (lambda v: None if v is None else round(v))(measured_traffic("sweep_table_64", dtype, tiles=tuned["name"])),
             "t_final": chans[0].t}
 
 
