@@ -1762,11 +1762,12 @@ Layout make_layout(const lbsep_params* p) {
     L.split = (long long)p->nx * p->ny <= (1LL << 16);
   const int cols = L.split ? 32 : 64;
   L.ntx = (p->nx + cols - 1) / cols;
-  // rows per thread: as asked, else the largest of 4, 2, 1 that still gives
-  // >= 2048 tiles (a channel alone needs the parallelism; in a batch that fills
-  // the GPU, 4 rows cut the row-tile partial sums to a quarter). FP32 stops at
-  // 2: measured 2.4-7% faster than 4 on 2.9M-21M-node channels, where FP16 and
-  // FP64 are as fast or faster with 4.
+  // rows per thread: as asked, else 4 if that still gives >= 2048 tiles, 2 if
+  // >= 512, else 1 (a channel alone needs the parallelism; in a batch that
+  // fills the GPU, more rows cut the row-tile partial sums). FP32 stops at 2:
+  // measured 2.4-7% faster than 4 on 2.9M-21M-node channels, where FP16 and
+  // FP64 are as fast or faster with 4. Two rows at 640-1440 tiles: 1-3.4%
+  // faster than one in every dtype; at 360 tiles FP64 loses a fifth.
   L.rpt = 1;
   if (p->tile_rows > 0) {
     L.rpt = p->tile_rows;
@@ -1774,7 +1775,7 @@ Layout make_layout(const lbsep_params* p) {
     for (int r : {4, 2}) {
       if (r == 4 && p->dtype == LBSEP_F32) continue;
       const int nrt = (p->ny + kTY * r - 1) / (kTY * r);
-      if ((long long)L.ntx * nrt >= 2048) {
+      if ((long long)L.ntx * nrt >= (r == 4 ? 2048 : 512)) {
         L.rpt = r;
         break;
       }
