@@ -1896,16 +1896,12 @@ void sweep_any(lbsep_channel* h, const void* src, void* dst, double* mom, void* 
 template <class MD>
 void launch_sweep2_md(lbsep_channel* h, const Lv2& lv, int grid, const void* src, void* dst) {
   using S = typename MD::St;
-  if (h->L.big)
-    hipLaunchKernelGGL((k_sweep2<MD, true>), dim3(grid), dim3(kT2), 0, h->stream,
-                       reinterpret_cast<const KParams*>(h->ws + h->L.consts),
-                       reinterpret_cast<const KBufs*>(h->ws + h->L.consts + align_up(sizeof(KParams), 256)), lv,
-                       static_cast<const S*>(src), static_cast<S*>(dst));
-  else
-    hipLaunchKernelGGL((k_sweep2<MD, false>), dim3(grid), dim3(kT2), 0, h->stream,
-                       reinterpret_cast<const KParams*>(h->ws + h->L.consts),
-                       reinterpret_cast<const KBufs*>(h->ws + h->L.consts + align_up(sizeof(KParams), 256)), lv,
-                       static_cast<const S*>(src), static_cast<S*>(dst));
+  // non-temporal state stores at every size, also where the state fits the
+  // caches (64x1280: FP64 11.50 vs 11.76 us per level, FP32 5.38 vs 5.42)
+  hipLaunchKernelGGL((k_sweep2<MD, true>), dim3(grid), dim3(kT2), 0, h->stream,
+                     reinterpret_cast<const KParams*>(h->ws + h->L.consts),
+                     reinterpret_cast<const KBufs*>(h->ws + h->L.consts + align_up(sizeof(KParams), 256)), lv,
+                     static_cast<const S*>(src), static_cast<S*>(dst));
 }
 
 // k_sweep2 over the whole grid, or (nlev == 0) its lead blocks only.
