@@ -101,11 +101,10 @@ typedef struct lbsep_params {
   int32_t tile_mode; /* LBSEP_TILE_AUTO / _SPLIT / _NODE: how nodes map to lanes (same results)  */
   int32_t tile_rows; /* rows each wavefront of a tile walks: 0 = chosen from the size (4 if that
                         leaves >= 2048 tiles, except for LBSEP_F32; 2 if >= 512; else 1),
-                        else 1, 2 or 4. The states are the
-                        same whatever the value; the column sums behind CL and the profiles are
-                        associated per tile, so those may differ in the last bits. A channel in a
-                        batch that fills the GPU can be faster with 2 or 4 (fewer row-tile
-                        partial sums). */
+                        else 1, 2 or 4. The states are the same whatever the value; the column
+                        sums behind CL and the profiles are associated per tile, so those may
+                        differ in the last bits. A channel in a batch that fills the GPU can be
+                        faster with 2 or 4 (fewer row-tile partial sums). */
   int32_t fused_steps; /* time levels per sweep launch: 0 = chosen by the library (currently 1),
                         1, or 2 (needs ny <= 64 and an inlet, an outlet and walls: no periodic
                         flag; else LBSEP_EINVAL). With 2, a launch advances two levels, keeping
