@@ -112,7 +112,10 @@ typedef struct lbsep_params {
                         bitwise those of single-level launches (FP64, FP32), CL and the column
                         sums agree to rounding. A third state buffer is allocated; readouts right
                         after a two-level launch recompute the level before (one launch). Such a
-                        channel cannot join a batch. */
+                        channel cannot join a batch. Measured per level on 64-row channels:
+                        faster in FP32 at every length (64x1280 5.3 vs 7.4 us, 64x81920 120 vs
+                        150 us); in FP64 only on short ones (64x1280 11.6 vs 13.6 us; from
+                        2560 columns on slower, 64x20480 137 vs 89 us). */
 } lbsep_params;
 
 typedef struct lbsep_channel lbsep_channel;
