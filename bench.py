@@ -1,17 +1,24 @@
 """Benchmark of the fused binary-mixture LBM step on one MI355X.
 
-Workload (default): the single Ne-Ar channel, H = 64, L = 1280 (81,920 nodes),
-C_l = 0.3, theta = 3, Kn_out = 0.05, populations initialised at local
-equilibrium with a linear pressure drop. A step is one time level of the
-fused sweep: both species pulled, DBB walls, inlet/outlet correction, moments,
-relaxation times, MRT collision and the FP64 reduction to C_l(x), CL and C~_l.
-On channels of at most 64 rows one launch advances two levels (temporal
-blocking; the states are bitwise those of one level per launch).
+Headline workload: the seeded 64-channel parametric sweep (He-Ar / Ne-Ar,
+uneven H in {16, 32, 48, 64, 96, 128}, L = 20 H, C_l ~ U[0.1, 0.9], theta ~
+U[1.5, 4], Kn_out log-uniform in [0.01, 1]; 7.23 M nodes, about 1 GB of FP32
+state, above the 256 MB last-level cache), advanced by one launch of the batch
+sweep per step: FP32 deviation storage, FP32 collision, FP64 column sums and
+CL per member and step; tile shapes from the autotuner; the step loop replayed
+from a captured HIP graph. A step is one time level of every member: both
+species pulled, DBB walls, inlet/outlet correction, moments, relaxation times,
+MRT collision and the FP64 reduction to C_l(x), CL and C~_l.
 
-Prints one JSON line: the FP32 path's throughput in node-MLUPS (one update =
-one node with both species' 9 populations), next to the plain FP64 path, the
-CL error of FP32 against FP64, the FP64 path against the CPU oracle on a short
-run, the roofline of the sweep kernel and the CPU oracle baseline.
+Prints one JSON line: node-MLUPS of the timed block (one update = one node
+with both species' 9 populations; wall clock between two device
+synchronisations), the roofline of the batch sweep kernel (algorithmic bytes
+per launch over the mean launch interval from HIP events on its stream), the
+CL error of every member against the FP64 batch after 20,000 steps, the CPU
+oracle on the same table over the host cores, and secondary legs (the
+single 64 x 1280 channel, the 512 x 10240 bandwidth probe, the storage-
+precision comparison on 256 x 5120, the adjoint gradient, the FP64 path
+against the oracle).
 """
 from __future__ import annotations
 
@@ -30,6 +37,15 @@ BYTES_PER_POP = {"f64": 8, "f32": 4, "f16": 2}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_traffic.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1603_08221_amd", "csrc", n)
                   for n in ("lbsep.hip", "lbsep_device.h", "e1_table.h")]
+METRIC = "MLUPS (both species) + achieved HBM GB/s vs FP64 plain, at CL error ≤1e-5"
+TABLE_STEPS = 20000   # steps per member of the parametric sweep (its CL error is taken there)
+CPU_POOL_MAX = 16     # worker processes of the CPU baseline (one GPU's share of the host)
+
+
+def log(msg: str):
+    """Progress on stderr (the JSON line is the only stdout)."""
+    sys.stderr.write(f"[bench {time.strftime('%H:%M:%S')}] {msg}\n")
+    sys.stderr.flush()
 
 
 def source_hash() -> str:
@@ -66,11 +82,46 @@ def measured_traffic(workload: str, dtype: str, levels: int = 1, tiles: str = No
 
 
 def levels_per_launch(w, requested: int) -> int:
-    """Time levels per sweep launch: as requested, else two on channels of at
-    most 64 rows (where the two-level kernel applies), one otherwise."""
+    """Time levels per sweep launch of a single channel: as requested, else two
+    on channels of at most 64 rows (where the two-level kernel applies), one
+    otherwise."""
     if requested:
         return requested
     return 2 if w.ny <= 64 else 1
+
+
+def graph_length(steps: int) -> int:
+    """Steps per captured graph of the batch step loop: 100, or the whole
+    timed block when it is shorter (so that it replays from the graph too)."""
+    return max(1, min(100, steps))
+
+
+def parse_args(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000, help="timed batch steps (one launch each)")
+    ap.add_argument("--warmup", type=int, default=100, help="untimed batch steps before the timed block")
+    ap.add_argument("--dtype", default="f32", choices=["f32", "f16", "f64"], help="storage of the headline batch")
+    ap.add_argument("--cpu-seconds", type=float, default=2.5,
+                    help="CPU baseline: seconds of oracle steps per table member")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip running the table to 20,000 steps against the FP64 batch")
+    ap.add_argument("--no-single", action="store_true", help="skip the single 64 x 1280 channel leg")
+    ap.add_argument("--no-large", action="store_true", help="skip the 512 x 10240 bandwidth probe")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-gradient leg")
+    ap.add_argument("--no-steady", action="store_true", help="skip the 64 x 1280 run to steady state")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the FP64 / FP32 / FP16 storage comparison on the 256 x 5120 channel")
+    ap.add_argument("--precision-steps", type=int, default=100000)
+    ap.add_argument("--adjoint-steps", type=int, default=10000)
+    ap.add_argument("--single-steps", type=int, default=20000)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="only run a plain device copy of this size (PMC calibration)")
+    args = ap.parse_args(argv)
+    if args.steps < 1 or args.warmup < 0:
+        ap.error("--steps must be >= 1 and --warmup >= 0")
+    return args
 
 
 def make_channel(lbsep, w, dtype, hist_cap=1024, levels=1):
@@ -81,7 +132,7 @@ def make_channel(lbsep, w, dtype, hist_cap=1024, levels=1):
 
 
 def time_steps(torch, ch, steps):
-    """Run exactly `steps` sweeps between two stream synchronisations; return
+    """Run exactly `steps` sweeps between two device synchronisations; return
     (wall seconds, event milliseconds on the channel's stream)."""
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
@@ -95,53 +146,123 @@ def time_steps(torch, ch, steps):
     return wall, start.elapsed_time(end)
 
 
-def batch_leg(torch, lbsep, dtype: str, steps: int):
-    """The seeded 64-channel parametric sweep (uneven H in {16..128}, L = 20 H)
-    as one launch per step: tile shapes from the autotuner, the step loop as a
-    captured HIP graph of 100 steps, `steps` steps timed with HIP events."""
-    from paper_1603_08221_amd import autotune
+def table_params(lbsep, dtype):
     from paper_1603_08221_amd.workloads import batch_instances
 
     ws = batch_instances()
     ps = [lbsep.make_params(w.nx, w.ny, w.m_a, w.m_b, w.cl_in, w.cl_out, w.theta, w.kn_out,
                             lbsep.dbb_r_from_cm(w.c_m, w.m_a, w.m_b, w.cl_in), dtype=dtype, hist_cap=64)
           for w in ws]
-    tuned = autotune.tune(ps)
+    return ws, ps
+
+
+def table_batch(torch, lbsep, ps, modes=None, rows=None):
+    """The members as channels on one non-default stream and their batch."""
     stream = torch.cuda.Stream()
     chans = []
-    for p, m, rows in zip(ps, tuned["modes"], tuned["rows"]):
-        p.tile_mode = m
-        p.tile_rows = rows
+    for k, p in enumerate(ps):
+        if modes is not None:
+            p.tile_mode = modes[k]
+            p.tile_rows = rows[k]
         chans.append(lbsep.Channel(p, device="cuda:0", stream=stream))
-    b = lbsep.Batch(chans)
-    b.capture(100)
-    b.step(100)
-    stream.synchronize()
-    start = torch.cuda.Event(enable_timing=True)
-    end = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    start.record(stream)
-    b.step(steps)
-    end.record(stream)
-    end.synchronize()
-    wall = time.perf_counter() - t0
-    nodes = sum(w.nx * w.ny for w in ws)
-    per = start.elapsed_time(end) / 1e3 / steps
-    alg = nodes * 36 * BYTES_PER_POP[dtype]
-    diverged = 0
+    return chans, lbsep.Batch(chans), stream
+
+
+def member_cls(lbsep, chans):
+    """CL of every member, None where the member has gone non-finite."""
+    out = []
     for c in chans:
         try:
-            c.read_cl()
-        except lbsep.LbsepError:
-            diverged += 1
-    return {"workload": "sweep_table_64 (seed 160308221, H in {16..128}, L = 20 H)", "instances": len(ws),
-            "nodes": nodes, "steps": steps, "mlups": round(nodes * steps / wall / 1e6, 1),
-            "us_per_step": round(per * 1e6, 2), "gbps_algorithmic": round(alg / per / 1e9, 1),
-            "frac_of_hbm_peak": round(alg / per / 1e9 / HBM_PEAK_GBS, 4), "tiles": tuned["name"],
-            "tuning_ms_per_step": {k: round(v, 4) for k, v in tuned["timings"].items()},
-            "graph_steps": 100, "diverged_members": diverged,
-            "traffic": (lambda v: None if v is None else round(v))(measured_traffic("sweep_table_64", dtype, tiles=tuned["name"])),
-            "t_final": chans[0].t}
+            out.append(c.read_cl()["cl"])
+        except lbsep.LbsepError as e:
+            if e.code != lbsep.ENONFINITE:
+                raise
+            out.append(None)
+    return out
+
+
+def headline(torch, lbsep, args):
+    """The 64-member table, tuned, graph-replayed: warm-up, then exactly
+    args.steps timed steps. Returns (record, channels, batch, stream)."""
+    from paper_1603_08221_amd import autotune
+
+    ws, ps = table_params(lbsep, args.dtype)
+    log("tuning the tile assignment of the 64-member table")
+    tuned = autotune.tune(ps)
+    log(f"tuned: {tuned['name']} ({tuned['ms_per_step'] * 1e3:.1f} us per trial step)")
+    chans, b, stream = table_batch(torch, lbsep, ps, tuned["modes"], tuned["rows"])
+    g = graph_length(args.steps)
+    b.capture(g)
+    b.step(args.warmup)
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record(stream)
+    b.step(args.steps)
+    end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_s = start.elapsed_time(end) / 1e3
+    nodes = sum(w.nodes for w in ws)
+    per_launch = ev_s / args.steps
+    alg = nodes * 36 * BYTES_PER_POP[args.dtype]
+    achieved = alg / per_launch / 1e9
+    traffic = measured_traffic("sweep_table_64", args.dtype, tiles=tuned["name"])
+    rec = {
+        "nodes": nodes, "wall_s": wall, "event_s": ev_s, "per_launch_s": per_launch,
+        "mlups": nodes * args.steps / wall / 1e6, "achieved": achieved, "alg_bytes": alg,
+        "traffic": traffic, "tuned": tuned, "graph_steps": g,
+    }
+    log(f"timed {args.steps} steps: {per_launch * 1e6:.1f} us per step, {achieved:.0f} GB/s algorithmic")
+    return rec, chans, b, stream, ws
+
+
+def accuracy_leg(torch, lbsep, chans, b, ws, dtype):
+    """The headline table continued to 20,000 steps per member, and the same
+    table in FP64 for 20,000 steps: CL error of every member that stays finite
+    in both, and the members that go non-finite (with the mean free path
+    per lattice spacing, Kn_out H, of each)."""
+    t_done = chans[0].t
+    left = TABLE_STEPS - t_done
+    t0 = time.perf_counter()
+    while left > 0:
+        n = min(5000, left)
+        b.step(n)
+        left -= n
+        torch.cuda.synchronize()
+        log(f"reduced-precision table at step {chans[0].t}")
+    cl_lo = member_cls(lbsep, chans)
+    lo_s = time.perf_counter() - t0
+    _, ps64 = table_params(lbsep, "f64")
+    ch64, b64, _ = table_batch(torch, lbsep, ps64)
+    b64.capture(100)
+    t0 = time.perf_counter()
+    for k in range(TABLE_STEPS // 5000):
+        b64.step(5000)
+        torch.cuda.synchronize()
+        log(f"FP64 table at step {ch64[0].t}")
+    f64_s = time.perf_counter() - t0
+    cl64 = member_cls(lbsep, ch64)
+    errs = {}
+    for k, (a, r) in enumerate(zip(cl_lo, cl64)):
+        if a is not None and r is not None:
+            errs[k] = abs(a - r)
+    div_lo = [k for k, v in enumerate(cl_lo) if v is None]
+    div64 = [k for k, v in enumerate(cl64) if v is None]
+    worst = max(errs.values()) if errs else None
+    out = {
+        "steps": TABLE_STEPS, "members": len(ws), "finite_in_both": len(errs),
+        "max_cl_err_vs_fp64": worst, "cl_ok": worst is not None and worst <= 1e-5,
+        "cl_err_per_member": {str(k): float(f"{v:.3g}") for k, v in errs.items()},
+        "cl_fp64_per_member": [None if v is None else float(f"{v:.6g}") for v in cl64],
+        "diverged": {dtype: div_lo, "f64": div64},
+        "diverged_kn_h": {str(k): round(ws[k].kn_out * ws[k].ny, 3) for k in sorted(set(div_lo) | set(div64))},
+        "seconds": {dtype: round(lo_s, 2), "f64": round(f64_s, 2)},
+        "fp64_us_per_step": round(f64_s / TABLE_STEPS * 1e6, 1),
+    }
+    del b64, ch64
+    return out
 
 
 def species_velocity_residual(m_now, m_then, gap: int) -> float:
@@ -157,12 +278,40 @@ def species_velocity_residual(m_now, m_then, gap: int) -> float:
     return out
 
 
-def steady_leg(torch, lbsep, w, max_steps: int = 50000, check_every: int = 1000, gap: int = 100,
+def single_leg(torch, lbsep, steps: int):
+    """The Ne-Ar 64 x 1280 channel (C_l 0.3, theta 3, Kn_out 0.05) alone, two
+    time levels per launch, FP32 deviation storage and FP64: node-MLUPS, the
+    CL error of FP32 against FP64 after the same steps."""
+    from paper_1603_08221_amd.workloads import CONFIGS
+
+    w = CONFIGS["ne_ar_64x1280"]
+    levels = levels_per_launch(w, 0)
+    out = {"workload": w.name, "steps": steps, "levels_per_launch": levels}
+    cls = {}
+    for dtype in ("f32", "f64"):
+        ch, _ = make_channel(lbsep, w, dtype, levels=levels)
+        ch.step(1000)
+        wall, ev = time_steps(torch, ch, steps)
+        cls[dtype] = ch.read_cl()["cl"]
+        per = ev / 1e3 / steps
+        out[dtype] = {"mlups": round(w.nodes * steps / wall / 1e6, 1), "us_per_step": round(per * 1e6, 2),
+                      "gbps_algorithmic": round(w.nodes * 36 * BYTES_PER_POP[dtype] / per / 1e9, 1),
+                      "cl": cls[dtype],
+                      "traffic": measured_traffic(w.name, dtype, levels)}
+        del ch
+    out["cl_err_f32_vs_f64"] = abs(cls["f32"] - cls["f64"])
+    return out
+
+
+def steady_leg(torch, lbsep, max_steps: int = 50000, check_every: int = 1000, gap: int = 100,
                tol: float = 1e-8):
-    """The headline channel run to steady state (species-velocity residual
-    below tol between levels `gap` apart, checked every `check_every` steps, or
-    max_steps) in FP32 deviation storage and in FP64: steps taken, residual,
-    CL, C~_l and the C_l(x) profile every 64 columns, FP32 against FP64."""
+    """The Ne-Ar 64 x 1280 channel run to steady state (species-velocity
+    residual below tol between levels `gap` apart, checked every
+    `check_every` steps, or max_steps) in FP32 deviation storage and in FP64:
+    steps taken, residual, CL, C~_l and the C_l(x) profile every 64 columns."""
+    from paper_1603_08221_amd.workloads import CONFIGS
+
+    w = CONFIGS["ne_ar_64x1280"]
     out = {}
     for dtype in ("f32", "f64"):
         ch, _ = make_channel(lbsep, w, dtype, hist_cap=64)
@@ -184,6 +333,24 @@ def steady_leg(torch, lbsep, w, max_steps: int = 50000, check_every: int = 1000,
     out["workload"] = w.name
     out["criterion"] = f"residual < {tol} (levels {gap} apart) or {max_steps} steps"
     return out
+
+
+def large_leg(torch, lbsep, dtype: str, steps: int = 200):
+    """The He-Ar 512 x 10240 channel alone (bandwidth probe above the cache)."""
+    from paper_1603_08221_amd.workloads import CONFIGS
+
+    wl = CONFIGS["he_ar_512x10240"]
+    chl, _ = make_channel(lbsep, wl, dtype, hist_cap=64)
+    chl.step(20)
+    wall_l, ev_l = time_steps(torch, chl, steps)
+    bl = wl.nodes * 36 * BYTES_PER_POP[dtype]
+    gbs = bl / (ev_l / 1e3 / steps) / 1e9
+    tr = measured_traffic(wl.name, dtype)
+    return {"workload": wl.name, "dtype": dtype, "steps": steps,
+            "mlups": round(wl.nodes * steps / wall_l / 1e6, 1),
+            "us_per_step": round(ev_l * 1e3 / steps, 2), "gbps_algorithmic": round(gbs, 1),
+            "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+            "traffic": None if tr is None else round(tr), "cl": chl.read_cl()["cl"]}
 
 
 def precision_leg(torch, lbsep, steps: int):
@@ -209,6 +376,7 @@ def precision_leg(torch, lbsep, steps: int):
             entry["cl_err_vs_f64"] = abs(cl["cl"] - ref["cl"])
             entry["cl_tilde_err_vs_f64"] = abs(cl["cl_tilde"] - ref["cl_tilde"])
         res[dtype] = entry
+        log(f"precision leg: {dtype} done")
         del ch
     return res
 
@@ -235,82 +403,120 @@ def adjoint_leg(torch, lbsep, steps: int):
             "us_per_step_forward_recompute_reverse": round(wall / steps * 1e6, 2)}
 
 
-def cpu_baseline(w, r, seconds: float):
-    """The CPU oracle as it stands, on the same workload, for a bounded number
-    of steps (about `seconds` of CPU work), single BLAS thread."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_member(task):
+    """One table member on one core: oracle steps from the initial state for
+    about `seconds` (at least one step). Returns (member, nodes, steps, s)."""
+    k, w, seconds = task
     from threadpoolctl import threadpool_limits
 
     from oracle import binary_lbm as O
 
+    r = O.dbb_r_from_cm(w.c_m, w.m_a, w.m_b, w.cl_in)
     p = O.Params(nx=w.nx, ny=w.ny, m_a=w.m_a, m_b=w.m_b, cl_in=w.cl_in, cl_out=w.cl_out, theta=w.theta,
                  kn_out=w.kn_out, dbb_r=r, accom=w.accom)
     with threadpool_limits(limits=1):
         f = O.initial_state(p)
         t0 = time.perf_counter()
         n = 0
-        while time.perf_counter() - t0 < seconds:
+        while n == 0 or time.perf_counter() - t0 < seconds:
             f = O.step(f, p)
             n += 1
         dt = time.perf_counter() - t0
-    return {"value": w.nodes * n / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": f"{n} steps of {w.name} ({w.ny}x{w.nx}) from the initial state, NumPy FP64, "
-                      f"{dt:.1f} s, 1 BLAS thread"}
+    return k, w.nodes, n, dt
 
 
-def oracle_parity(lbsep, w, r, steps: int):
-    """CL and moments of the GPU FP64 path against the oracle after `steps` steps."""
+def _pool_init():
+    import numpy  # noqa: F401
+    import scipy.special  # noqa: F401
+
+    import oracle.binary_lbm  # noqa: F401
+
+
+def cpu_baseline(seconds: float):
+    """The CPU oracle as it stands on the headline table: one process per
+    core (at most CPU_POOL_MAX), one member per task, each member stepped
+    from its initial state for about `seconds`. Throughput = all node updates
+    done / wall time of the pool. Runs before this process touches the GPU
+    (the workers are fresh interpreters that never do)."""
+    import multiprocessing as mp
+
+    from paper_1603_08221_amd.workloads import batch_instances
+
+    ws = batch_instances()
+    tasks = [(k, w, seconds) for k, w in enumerate(ws)]
+    # largest members first, so the pool's tail is short
+    tasks.sort(key=lambda t: -t[1].nodes)
+    cores = max(1, min(CPU_POOL_MAX, os.cpu_count() or 1))
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(cores, initializer=_pool_init) as pool:
+        pool.map(_pool_init_noop, range(cores))  # workers up and imports done before the clock
+        t0 = time.perf_counter()
+        res = pool.map(_oracle_member, tasks, chunksize=1)
+        wall = time.perf_counter() - t0
+    updates = sum(nodes * n for _, nodes, n, _ in res)
+    steps = [n for *_, n, _ in res]
+    return {"value": round(updates / wall / 1e6, 3), "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "sample": (f"sweep_table_64: each of the 64 members stepped {min(steps)}-{max(steps)} times "
+                       f"from its initial state (about {seconds:g} s each, NumPy FP64, one BLAS thread per "
+                       f"process), {cores} processes, {wall:.1f} s wall, {updates / 1e6:.1f} M node updates"),
+            "cpu_model": cpu_model(), "os_cpu_count": os.cpu_count()}
+
+
+def _pool_init_noop(_):
+    return 0
+
+
+def oracle_parity(lbsep, steps: int):
+    """CL and densities of the GPU FP64 path against the oracle after `steps`
+    steps of the He-Ar 8 x 80 channel."""
     import numpy as np
 
     from oracle import binary_lbm as O
+    from paper_1603_08221_amd.workloads import CONFIGS
 
+    w = CONFIGS["he_ar_8x80"]
+    ch, r = make_channel(lbsep, w, "f64")
     p = O.Params(nx=w.nx, ny=w.ny, m_a=w.m_a, m_b=w.m_b, cl_in=w.cl_in, cl_out=w.cl_out, theta=w.theta,
                  kn_out=w.kn_out, dbb_r=r, accom=w.accom)
     f, _ = O.run(p, steps)
     d = O.diagnostics(f, p)
     ref = O.moment_fields(f, p)
-    ch, _ = make_channel(lbsep, w, "f64")
     ch.step(steps)
     mom = ch.read_moments()
     cl = ch.read_cl()["cl"]
     rho_err = max(float(np.max(np.abs(mom[k] - ref[k])) / np.max(np.abs(ref[k]))) for k in (0, 1))
-    return {"steps": steps, "cl_abs_err": abs(cl - d.cl), "rho_rel_err": rho_err}
+    return {"workload": w.name, "steps": steps, "cl_abs_err": abs(cl - d.cl), "rho_rel_err": rho_err}
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20000)
-    ap.add_argument("--warmup", type=int, default=1000)
-    ap.add_argument("--workload", default="ne_ar_64x1280")
-    ap.add_argument("--dtype", default="f32", choices=["f32", "f16", "f64"])
-    ap.add_argument("--levels", type=int, default=0, choices=[0, 1, 2],
-                    help="time levels per sweep launch (0: two on channels of at most 64 rows, else one)")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 reference leg (profiling runs)")
-    ap.add_argument("--no-large", action="store_true",
-                    help="skip the leg on the 512 x 10240 channel (above the last-level cache)")
-    ap.add_argument("--no-batch", action="store_true", help="skip the 64-channel batched sweep leg")
-    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-gradient leg")
-    ap.add_argument("--no-steady", action="store_true", help="skip the run of the channel to steady state")
-    ap.add_argument("--no-precision", action="store_true",
-                    help="skip the FP64 / FP32 / FP16 storage comparison on the 256 x 5120 channel")
-    ap.add_argument("--precision-steps", type=int, default=100000)
-    ap.add_argument("--adjoint-steps", type=int, default=10000)
-    ap.add_argument("--batch-steps", type=int, default=1000)
-    ap.add_argument("--copy-calibration-mib", type=int, default=0,
-                    help="only run a plain device copy of this size (PMC calibration)")
-    args = ap.parse_args()
-
+def main(argv=None):
+    args = parse_args(argv)
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs one channel on one GPU; --gpus must be 1",
-                          "n_gpus": args.gpus}))
+        msg = (f"--gpus {args.gpus}: this benchmark runs on one GPU only (the parametric sweep shards by "
+               "member with no communication, but no multi-GPU path is built); run with --gpus 1")
+        print(json.dumps({"error": msg, "n_gpus": args.gpus}))
+        sys.stderr.write(msg + "\n")
         sys.exit(2)
+
+    cpu = None
+    if not args.no_cpu_baseline and not args.copy_calibration_mib:
+        log("CPU oracle baseline on the table")
+        cpu = cpu_baseline(args.cpu_seconds)
+        log(f"CPU oracle baseline: {cpu['value']} MLUPS on {cpu['cores']} processes")
 
     import torch
 
     from paper_1603_08221_amd import lbsep
-    from paper_1603_08221_amd.workloads import CONFIGS
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.copy_calibration_mib:
@@ -323,91 +529,66 @@ def main():
         print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": 5}))
         return
 
-    w = CONFIGS[args.workload]
-    levels = levels_per_launch(w, args.levels)
-    if args.steps % levels or args.warmup % levels:
-        sys.exit(f"--steps and --warmup must be multiples of the {levels} levels per launch")
-    ch, r = make_channel(lbsep, w, args.dtype, levels=levels)
-    ch.step(args.warmup)
-    torch.cuda.synchronize()
-    wall, ev_ms = time_steps(torch, ch, args.steps)
-    t_total = ch.t
-    cl32 = ch.read_cl()
-    mlups = w.nodes * args.steps / wall / 1e6
-    per_launch_s = ev_ms / 1e3 / (args.steps // levels)
-    alg_bytes = levels * w.nodes * 36 * BYTES_PER_POP[args.dtype]
-    achieved = alg_bytes / per_launch_s / 1e9
-
+    rec, chans, b, stream, ws = headline(torch, lbsep, args)
+    tuned = rec["tuned"]
     out = {
-        "metric": "MLUPS (both species) + achieved HBM GB/s vs FP64 plain, at CL error <=1e-5",
-        "value": round(mlups, 1),
+        "metric": METRIC,
+        "value": round(rec["mlups"], 1),
         "unit": "MLUPS",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": wall * 1e3 / args.steps,
+        "ms_per_step": rec["wall_s"] * 1e3 / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.dtype != "f64" else "f64",
+        "dtype": args.dtype,
         "data": "synthetic",
-        "config": {"workload": w.name, "nx": w.nx, "ny": w.ny, "mixture": "Ne-Ar" if w.m_a == 20 else "He-Ar",
-                   "cl_in": w.cl_in, "theta": w.theta, "kn_out": w.kn_out, "dbb_r": r,
+        "config": {"workload": "sweep_table_64", "instances": len(ws), "nodes": rec["nodes"],
+                   "table": "seed 160308221: He-Ar / Ne-Ar p = 1/2, H in {16,32,48,64,96,128}, L = 20 H, "
+                            "C_l ~ U[0.1,0.9] (C_out = C_in), theta ~ U[1.5,4], Kn_out = 10^U[-2,0]",
                    "storage": {"f32": "f32 deviation", "f16": "f16 deviation", "f64": "f64"}[args.dtype],
-                   "levels_per_launch": levels,
+                   "collision": "f64" if args.dtype == "f64" else "f32", "reductions": "f64",
+                   "tiles": tuned["name"], "graph_steps": rec["graph_steps"], "launches_per_step": 1,
                    "parallelism": "single GPU"},
-        "gbps_algorithmic": round(achieved, 1),
-        "cl": cl32["cl"],
-        "t_final": t_total,
+        "gbps_algorithmic": round(rec["achieved"], 1),
+        "us_per_step_events": round(rec["per_launch_s"] * 1e6, 2),
     }
-
-    traffic = measured_traffic(w.name, args.dtype, levels)
-    out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": round(achieved / HBM_PEAK_GBS, 4),
-                       "traffic": None if traffic is None else round(traffic)}
-    kname = "k_sweep2" if levels == 2 else "k_sweep"
-    out["roofline_note"] = (f"{kname}, algorithmic bytes {alg_bytes} per launch ({levels} level(s) x 36 populations x "
-                            f"{BYTES_PER_POP[args.dtype]} B x {w.nodes} nodes) / {per_launch_s * 1e6:.2f} us mean "
-                            "launch time (HIP events on the channel stream)")
-
-    if not args.no_fp64:
-        ch64, _ = make_channel(lbsep, w, "f64", levels=levels)
-        ch64.step(args.warmup)
-        wall64, ev64 = time_steps(torch, ch64, args.steps)
-        cl64 = ch64.read_cl()
-        out["fp64"] = {"mlups": round(w.nodes * args.steps / wall64 / 1e6, 1),
-                       "ms_per_step": wall64 * 1e3 / args.steps,
-                       "gbps_algorithmic": round(w.nodes * 288 / (ev64 / 1e3 / args.steps) / 1e9, 1),
-                       "cl": cl64["cl"]}
-        out["cl_err_vs_fp64"] = abs(cl32["cl"] - cl64["cl"])
-        out["cl_ok"] = out["cl_err_vs_fp64"] <= 1e-5
-        del ch64
-    if not args.no_large and w.name != "he_ar_512x10240":
-        wl = CONFIGS["he_ar_512x10240"]
-        chl, _ = make_channel(lbsep, wl, args.dtype, hist_cap=64)
-        chl.step(20)
-        nl = 200
-        wall_l, ev_l = time_steps(torch, chl, nl)
-        bl = wl.nodes * 36 * BYTES_PER_POP[args.dtype]
-        gbs = bl / (ev_l / 1e3 / nl) / 1e9
-        tr = measured_traffic(wl.name, args.dtype)
-        out["large_channel"] = {"workload": wl.name, "steps": nl, "mlups": round(wl.nodes * nl / wall_l / 1e6, 1),
-                                "us_per_step": round(ev_l * 1e3 / nl, 2), "gbps_algorithmic": round(gbs, 1),
-                                "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
-                                "traffic": None if tr is None else round(tr), "cl": chl.read_cl()["cl"]}
-        del chl
-    if not args.no_batch:
-        out["batch"] = batch_leg(torch, lbsep, args.dtype, args.batch_steps)
+    out["roofline"] = {"bound": "hbm", "achieved": round(rec["achieved"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": round(rec["achieved"] / HBM_PEAK_GBS, 4),
+                       "traffic": None if rec["traffic"] is None else round(rec["traffic"])}
+    out["roofline_note"] = (f"k_sweep_batch: algorithmic bytes {rec['alg_bytes']} per launch (36 populations x "
+                            f"{BYTES_PER_POP[args.dtype]} B x {rec['nodes']} nodes, one level of all 64 members) / "
+                            f"{rec['per_launch_s'] * 1e6:.2f} us mean launch interval (HIP events on the batch's "
+                            f"stream over the {args.steps} timed steps); traffic = measured DRAM bytes per launch "
+                            "(rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated) for this kernel source and tile "
+                            "assignment, else null")
+    out["tuning_ms_per_step"] = {k: round(v, 4) for k, v in tuned["timings"].items()}
+    if not args.no_accuracy:
+        log("running the table to 20,000 steps per member, and in FP64")
+        out["table_accuracy"] = accuracy_leg(torch, lbsep, chans, b, ws, args.dtype)
+    del b, chans
+    torch.cuda.synchronize()
+    if not args.no_single:
+        log("single 64 x 1280 channel")
+        out["single_channel"] = single_leg(torch, lbsep, args.single_steps)
+    if not args.no_large:
+        log("512 x 10240 channel")
+        out["large_channel"] = large_leg(torch, lbsep, args.dtype)
     if not args.no_adjoint:
+        log("adjoint gradient")
         out["adjoint"] = adjoint_leg(torch, lbsep, args.adjoint_steps)
     if not args.no_steady:
-        out["steady_state"] = steady_leg(torch, lbsep, w)
+        log("64 x 1280 channel to steady state")
+        out["steady_state"] = steady_leg(torch, lbsep)
     if not args.no_precision:
+        log("storage precision on 256 x 5120")
         out["precision"] = precision_leg(torch, lbsep, args.precision_steps)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, r, args.cpu_seconds)
-        out["fp64_vs_oracle"] = oracle_parity(lbsep, w, r, 100)
-    print(json.dumps(out))
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
+        log("FP64 path against the oracle")
+        out["fp64_vs_oracle"] = oracle_parity(lbsep, 2000)
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

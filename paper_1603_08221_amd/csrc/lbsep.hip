@@ -180,6 +180,119 @@ __device__ __forceinline__ T sum9(const T f[9]) {
   return ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
 }
 
+// Rounding in the deviation storage modes. Near a steady state a node's
+// populations change by far less than their own rounding unit per step, so
+// a rounding that depends only on the value's position on the float grid
+// returns the same residual at every step: a frozen error that the slow
+// hydrodynamic modes (decay rates down to 1e-5 per step) amplify by their
+// inverse decay rate. Two places would do that:
+//   - streaming across a column adds the constant c_i of the reference state
+//     (add_stream_corr) to a float d: fl(d + c) rounds c to the grid of d,
+//     the same error at every node whose d lies in the same binade, a
+//     systematic error of about ulp(d) / |c| (1e-5 on the parametric table)
+//     in the reference pressure force (measured: a CL drift of about 1e-9 per
+//     step in FP32 against FP64, against 1e-10 for a 1e-7 perturbation of an
+//     FP64 run);
+//   - the binary16 store of a post-collision value rounds to a grid 2^13
+//     times coarser than the float arithmetic (dither_species).
+// Both add u ulp(v) before rounding, u uniform on [-1/2, 1/2) and ulp(v) the
+// rounding unit at v, which makes the expected result the exact one
+// (stochastic rounding). u comes from a counter-based generator keyed by the
+// node, the time level, the species and the direction, so every kernel that
+// forms a level's values forms the same bits, and runs stay bitwise
+// reproducible.
+__device__ __forceinline__ unsigned dither_seed(int x, int j, long long t) {
+  unsigned h = (unsigned)x * 0x9E3779B1u ^ (unsigned)j * 0x85EBCA77u ^ (unsigned)t * 0xC2B2AE3Du ^
+               (unsigned)((unsigned long long)t >> 32) * 0x27D4EB2Fu;
+  h = h * 747796405u + 2891336453u;  // PCG step and RXS-M-XS output permutation
+  h = ((h >> ((h >> 28u) + 4u)) ^ h) * 277803737u;
+  return (h >> 22u) ^ h;
+}
+
+// The node's generator is a linear congruential sequence r' = a r + c from
+// its seed; each state gives two 16-bit uniforms. Sub-streams: the streaming
+// correction of species 0 / 1 uses states 1-3 / 4-6, the binary16 store of
+// species 0 / 1 states 7-11 / 12-16; a sub-stream is entered by jumping
+// ahead (r_k = A_k r + C_k, one multiply-add).
+constexpr unsigned kLcgA = 1664525u, kLcgC = 1013904223u;
+struct LcgJump {
+  unsigned a, c;
+};
+constexpr LcgJump lcg_jump(int k) {
+  unsigned a = 1u, c = 0u;
+  for (int i = 0; i < k; ++i) {
+    a = a * kLcgA;
+    c = c * kLcgA + kLcgC;
+  }
+  return {a, c};
+}
+template <int K>
+__device__ __forceinline__ unsigned lcg_at(unsigned seed) {
+  constexpr LcgJump J = lcg_jump(K);
+  return J.a * seed + J.c;
+}
+
+// Uniforms on (-1/2, 1/2) from the high and low halves of a generator state
+// (16 bits each, centred: a rounding bias of at most 2^-17 of a unit remains).
+__device__ __forceinline__ float dither_hi(unsigned r) { return float(r >> 16) * 0x1p-16f - (0.5f - 0x1p-17f); }
+__device__ __forceinline__ float dither_lo(unsigned r) { return float(r & 0xffffu) * 0x1p-16f - (0.5f - 0x1p-17f); }
+
+// Unit in the last place of the storage type S at the float value v (0 for
+// zero and float subnormals).
+template <typename S>
+__device__ __forceinline__ float storage_ulp(float v) {
+  const float p2 = __uint_as_float(__float_as_uint(v) & 0x7f800000u);  // 2^floor(log2 |v|)
+  if constexpr (std::is_same<S, float>::value)
+    return p2 * 0x1p-23f;
+  else
+    return fmaxf(p2 * 0x1p-10f, 0x1p-24f);  // binary16: 10 fraction bits, subnormal step 2^-24
+}
+
+// Streaming correction of species s at node (x, j), level t (deviation
+// modes): the populations pulled across a column (c_ix != 0: directions 1,
+// 3, 5, 6, 7, 8) gain corr = -c_ix w_i alpha_si d rho0/dx, added with
+// stochastic rounding.
+template <class MD>
+__device__ __forceinline__ void add_stream_corr(const KParams& kp, int x, int j, long long t, int s,
+                                                typename MD::Ct f[9]) {
+  static_assert(MD::kDev, "only deviations are corrected");
+  const unsigned seed = dither_seed(x, j, t);
+  const unsigned r1 = s ? lcg_at<4>(seed) : lcg_at<1>(seed);
+  const unsigned r2 = r1 * kLcgA + kLcgC;
+  const unsigned r3 = r2 * kLcgA + kLcgC;
+  const float u[6] = {dither_hi(r1), dither_lo(r1), dither_hi(r2), dither_lo(r2), dither_hi(r3), dither_lo(r3)};
+  const int dir[6] = {1, 3, 5, 6, 7, 8};
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const int i = dir[k];
+    f[i] += __builtin_fmaf(u[k], storage_ulp<float>(f[i]), float(kp.corr[s][i]));
+  }
+}
+
+// Stochastic rounding of the binary16 store: species s of node (x, j) at
+// level t, post-collision.
+template <class MD>
+__device__ __forceinline__ void dither_species(typename MD::Ct f[9], int x, int j, long long t, int s) {
+  static_assert(MD::kDev, "only the deviation storage modes are dithered");
+  const unsigned seed = dither_seed(x, j, t);
+  unsigned r = s ? lcg_at<12>(seed) : lcg_at<7>(seed);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const float u = (i & 1) ? dither_lo(r) : dither_hi(r);
+    if (i & 1) r = r * kLcgA + kLcgC;
+    f[i] += u * storage_ulp<typename MD::St>(f[i]);
+    // the float value itself, rounded once more to binary16 by the store: the
+    // compiler must not fuse this addition with that conversion on some
+    // paths only (a single rounding there would give other bits than the
+    // same level formed by another kernel)
+    asm volatile("" : "+v"(f[i]));
+  }
+}
+
+// Whether the post-collision values of mode MD are dithered before the store.
+template <class MD>
+constexpr bool kDitherStore = MD::kDev && !std::is_same<typename MD::St, float>::value;
+
 // Pre-collision populations (deviations in the FP32/FP16 modes) of species s
 // at node (x, j) at the new time level.
 // PULL: streamed from the post-collision state in src, with DBB on wall rows.
@@ -189,7 +302,7 @@ __device__ __forceinline__ T sum9(const T f[9]) {
 // caller.
 template <class MD, bool PULL>
 __device__ __forceinline__ void gather1(const KParams& kp, const typename MD::St* __restrict__ src, int s, int x,
-                                        int j, typename MD::Ct f[9]) {
+                                        int j, long long t, typename MD::Ct f[9]) {
   using C = typename MD::Ct;
   if (!PULL) {
 #pragma unroll
@@ -219,10 +332,8 @@ __device__ __forceinline__ void gather1(const KParams& kp, const typename MD::St
   const int sx[9] = {x, xm, x, xp, x, xm, xp, xp, xm};
   const int sy[9] = {j, j, jm, j, jp, jm, jm, jp, jp};
 #pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    f[i] = C(*pop_at(kp, src, s, i, sy[i], sx[i]));
-    if (MD::kDev && (i == 1 || i == 3 || i >= 5)) f[i] += C(kp.corr[s][i]);
-  }
+  for (int i = 0; i < 9; ++i) f[i] = C(*pop_at(kp, src, s, i, sy[i], sx[i]));
+  if constexpr (MD::kDev) add_stream_corr<MD>(kp, x, j, t, s, f);
   if (bot || top) {
     // Eqs. (bot)/(bot2): the populations that would come from outside the
     // channel are r f^eq(rho_w, u_w = 0) + (1 - r) f'_opposite at the same node;
@@ -230,16 +341,12 @@ __device__ __forceinline__ void gather1(const KParams& kp, const typename MD::St
     // shares 4/6, 1/6, 1/6 of F on the axis and the two diagonal directions.
     // The rest equilibrium is a fixed point of this map, so deviations obey it too.
     // (constant array indices in each branch keep f in registers)
-    const C r = C(kp.r);
-    const C q = C(1) - r;
     const int o0 = bot ? 4 : 2, o1 = bot ? 7 : 5, o2 = bot ? 8 : 6;  // leaving
     const C l0 = C(*pop_at(kp, src, s, o0, j, x));
     const C l1 = C(*pop_at(kp, src, s, o1, j, x));
     const C l2 = C(*pop_at(kp, src, s, o2, j, x));
-    const C F = (l0 + l1) + l2;
-    const C v0 = r * (C(2.0 / 3.0) * F) + q * l0;
-    const C v1 = r * (F * C(1.0 / 6.0)) + q * l1;
-    const C v2 = r * (F * C(1.0 / 6.0)) + q * l2;
+    C v0, v1, v2;
+    dbb_shares<C>(C(kp.r), l0, l1, l2, v0, v1, v2);
     if (bot) {  // returning 2, 5, 6
       f[2] = v0;
       f[5] = v1;
@@ -259,15 +366,10 @@ template <class MD>
 __device__ __forceinline__ void dbb_pair(const KParams& kp, bool bot, typename MD::Pt w0, typename MD::Pt w1,
                                          typename MD::Pt w2, typename MD::Ct fa[9], typename MD::Ct fb[9]) {
   using C = typename MD::Ct;
-  const C r = C(kp.r);
-  const C q = C(1) - r;
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
-    const C l0 = C(w0[s]), l1 = C(w1[s]), l2 = C(w2[s]);
-    const C F = (l0 + l1) + l2;
-    const C v0 = r * (C(2.0 / 3.0) * F) + q * l0;
-    const C v1 = r * (F * C(1.0 / 6.0)) + q * l1;
-    const C v2 = r * (F * C(1.0 / 6.0)) + q * l2;
+    C v0, v1, v2;
+    dbb_shares<C>(C(kp.r), C(w0[s]), C(w1[s]), C(w2[s]), v0, v1, v2);
     C* f = s ? fb : fa;
     if (bot) {
       f[2] = v0;
@@ -285,7 +387,7 @@ __device__ __forceinline__ void dbb_pair(const KParams& kp, bool bot, typename M
 // values as gather1 for s = 0 and s = 1.
 template <class MD, bool PULL>
 __device__ __forceinline__ void gather_pair(const KParams& kp, const typename MD::St* __restrict__ src, int x, int j,
-                                            typename MD::Ct fa[9], typename MD::Ct fb[9]) {
+                                            long long t, typename MD::Ct fa[9], typename MD::Ct fb[9]) {
   using C = typename MD::Ct;
   if (!PULL) {
 #pragma unroll
@@ -321,25 +423,20 @@ __device__ __forceinline__ void gather_pair(const KParams& kp, const typename MD
     const typename MD::Pt v = *pair_at<MD>(kp, src, i, sy[i], sx[i]);
     fa[i] = C(v[0]);
     fb[i] = C(v[1]);
-    if (MD::kDev && (i == 1 || i == 3 || i >= 5)) {
-      fa[i] += C(kp.corr[0][i]);
-      fb[i] += C(kp.corr[1][i]);
-    }
+  }
+  if constexpr (MD::kDev) {
+    add_stream_corr<MD>(kp, x, j, t, 0, fa);
+    add_stream_corr<MD>(kp, x, j, t, 1, fb);
   }
   if (bot || top) {  // the DBB map of gather1, both species
-    const C r = C(kp.r);
-    const C q = C(1) - r;
     const int o0 = bot ? 4 : 2, o1 = bot ? 7 : 5, o2 = bot ? 8 : 6;
     const typename MD::Pt w0 = *pair_at<MD>(kp, src, o0, j, x);
     const typename MD::Pt w1 = *pair_at<MD>(kp, src, o1, j, x);
     const typename MD::Pt w2 = *pair_at<MD>(kp, src, o2, j, x);
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-      const C l0 = C(w0[s]), l1 = C(w1[s]), l2 = C(w2[s]);
-      const C F = (l0 + l1) + l2;
-      const C v0 = r * (C(2.0 / 3.0) * F) + q * l0;
-      const C v1 = r * (F * C(1.0 / 6.0)) + q * l1;
-      const C v2 = r * (F * C(1.0 / 6.0)) + q * l2;
+      C v0, v1, v2;
+      dbb_shares<C>(C(kp.r), C(w0[s]), C(w1[s]), C(w2[s]), v0, v1, v2);
       C* f = s ? fb : fa;
       if (bot) {
         f[2] = v0;
@@ -472,9 +569,11 @@ __device__ __forceinline__ NodeState<typename MD::Ct> node_moments(const KParams
 
 // Collision of both species of one node (moment state from node_moments), in
 // place.
+// The post-collision values of level t at node (x, j) are dithered when the
+// storage type is binary16 (dither_species).
 template <class MD>
-__device__ __forceinline__ void node_collide_only(const KParams& kp, typename MD::Ct fa[9], typename MD::Ct fb[9],
-                                                  const NodeState<typename MD::Ct>& st) {
+__device__ __forceinline__ void node_collide_only(const KParams& kp, int x, int j, long long t, typename MD::Ct fa[9],
+                                                  typename MD::Ct fb[9], const NodeState<typename MD::Ct>& st) {
   using C = typename MD::Ct;
   using E = E1Traits<C>;
   C we, weps;
@@ -488,6 +587,10 @@ __device__ __forceinline__ void node_collide_only(const KParams& kp, typename MD
   const C wd = C(2) * st.h2, wq = E::rcp(st.tq);
   collide_species<C>(fa, st.ca, st.rho_a, st.ux, st.uy, C(kp.rc.s[0]), we, weps, wd, wq, ws);
   collide_species<C>(fb, st.cb, st.rho_b, st.ux, st.uy, C(kp.rc.s[1]), we, weps, wd, wq, ws);
+  if constexpr (kDitherStore<MD>) {
+    dither_species<MD>(fa, x, j, t, 0);
+    dither_species<MD>(fb, x, j, t, 1);
+  }
 }
 
 // The post-collision pair of each direction of node (x, j) to dst.
@@ -521,7 +624,7 @@ __device__ __forceinline__ void dense_out(const KParams& kp, int x, int j, int s
 // step): ffull receives the pulled populations and fpost the post-collision
 // ones, both dense.
 template <class MD, bool EVAL, bool NT = false, bool REC = false>
-__device__ __forceinline__ void process_node(const KParams& kp, int x, int j, typename MD::Ct fa[9],
+__device__ __forceinline__ void process_node(const KParams& kp, int x, int j, long long t, typename MD::Ct fa[9],
                                              typename MD::Ct fb[9], typename MD::St* __restrict__ dst,
                                              double* __restrict__ mom, typename MD::St* __restrict__ fraw,
                                              double* __restrict__ ffull, double acc[4],
@@ -532,7 +635,7 @@ __device__ __forceinline__ void process_node(const KParams& kp, int x, int j, ty
       dense_out<MD>(kp, x, j, 0, fa, ffull);
       dense_out<MD>(kp, x, j, 1, fb, ffull);
     }
-    node_collide_only<MD>(kp, fa, fb, st);
+    node_collide_only<MD>(kp, x, j, t, fa, fb, st);
     node_store<MD, NT>(kp, x, j, fa, fb, dst);
     if constexpr (REC) {
       dense_out<MD>(kp, x, j, 0, fa, fpost);
@@ -551,7 +654,7 @@ __device__ __forceinline__ void process_node(const KParams& kp, int x, int j, ty
 // the per-species parameters by selects (kernels in which a dynamic index
 // would move the parameter block to scratch memory); REC as in process_node.
 template <class MD, bool EVAL, int XOR, bool STORE = true, bool SEL = false, bool REC = false>
-__device__ __forceinline__ void process_pair(const KParams& kp, int x, int j, int s, bool active,
+__device__ __forceinline__ void process_pair(const KParams& kp, int x, int j, long long t, int s, bool active,
                                              typename MD::Ct f[9], typename MD::St* __restrict__ dst,
                                              double* __restrict__ mom, typename MD::St* __restrict__ fraw,
                                              double* __restrict__ ffull, double acc[2],
@@ -618,6 +721,7 @@ __device__ __forceinline__ void process_pair(const KParams& kp, int x, int j, in
   }
   collide_species<C>(f, c_own, rho_own, ux, uy, C(species_param<SEL>(kp.rc.s, s)), we, weps, wd, wq, ws);
   if (!active) return;
+  if constexpr (kDitherStore<MD>) dither_species<MD>(f, x, j, t, s);
   if constexpr (REC) dense_out<MD>(kp, x, j, s, f, fpost);
   acc[0] += r_own * species_param<SEL>(kp.rc.inv_m, s);
   acc[1] += double(px);
@@ -813,8 +917,8 @@ __device__ __forceinline__ void sweep_block(const KParams& kp, const KBufs& kb,
     for (int i = 0; i < 9; ++i) g[i] = f[i] = C(0);
     if (PULL) {
       if (active) {
-        gather1<MD, true>(kp, src, s, layer ? l2 : l1, j, g);
-        if (layer == 0) gather1<MD, true>(kp, src, s, col, j, f);
+        gather1<MD, true>(kp, src, s, layer ? l2 : l1, j, t, g);
+        if (layer == 0) gather1<MD, true>(kp, src, s, col, j, t, f);
       }
       // kappa needs sum_j rho'(col, j) over the whole column: own rows from the
       // registers, the other end blocks' rows pulled again (sum only)
@@ -828,7 +932,7 @@ __device__ __forceinline__ void sweep_block(const KParams& kp, const KBufs& kb,
         if ((jj >> 6) == blk) continue;
         const int ss = (it >> 1) & 1, ll = it & 1;
         C h[9];
-        gather1<MD, true>(kp, src, ss, ll ? l2 : l1, jj, h);
+        gather1<MD, true>(kp, src, ss, ll ? l2 : l1, jj, t, h);
         const double v = double(sum9(h));
         if (ss) sums[1] += ll ? -v : 2.0 * v; else sums[0] += ll ? -v : 2.0 * v;
       }
@@ -850,10 +954,10 @@ __device__ __forceinline__ void sweep_block(const KParams& kp, const KBufs& kb,
       for (int i = 0; i < 9; ++i) g2[i] = lane_xor(g[i], 1);
       if (active && layer == 0) end_rebuild<MD>(kp, e, s, col, kap, km1, g, g2, f);
     } else {
-      if (active && layer == 0) gather1<MD, false>(kp, src, s, col, j, f);
+      if (active && layer == 0) gather1<MD, false>(kp, src, s, col, j, t, f);
     }
     double acc2[2] = {0.0, 0.0};
-    process_pair<MD, EVAL, 2, true, false, REC>(kp, col, j, s, active && layer == 0, f, dst, mom, fraw, ffull, acc2,
+    process_pair<MD, EVAL, 2, true, false, REC>(kp, col, j, t, s, active && layer == 0, f, dst, mom, fraw, ffull, acc2,
                                                 reinterpret_cast<double*>(fraw));
     if (EVAL) return;
     const double acc[4] = {s ? 0.0 : acc2[0], s ? acc2[0] : 0.0, s ? 0.0 : acc2[1], s ? acc2[1] : 0.0};
@@ -893,8 +997,8 @@ __device__ __forceinline__ void sweep_block(const KParams& kp, const KBufs& kb,
       const int j = by * (kTY * kp.rpt) + r * kTY + ty;
       if (j < kp.ny) {  // wave-uniform
         C f[9];
-        if (xin) gather1<MD, PULL>(kp, src, s, x, j, f);
-        process_pair<MD, EVAL, 32, true, false, REC>(kp, x, j, s, xin, f, dst, mom, fraw, ffull, acc,
+        if (xin) gather1<MD, PULL>(kp, src, s, x, j, t, f);
+        process_pair<MD, EVAL, 32, true, false, REC>(kp, x, j, t, s, xin, f, dst, mom, fraw, ffull, acc,
                                                      reinterpret_cast<double*>(fraw));
       }
     }
@@ -921,8 +1025,9 @@ __device__ __forceinline__ void sweep_block(const KParams& kp, const KBufs& kb,
       const int j = by * (kTY * kp.rpt) + r * kTY + ty;
       if (xin && j < kp.ny) {
         C fa[9], fb[9];
-        gather_pair<MD, PULL>(kp, src, x, j, fa, fb);
-        process_node<MD, EVAL, NT, REC>(kp, x, j, fa, fb, dst, mom, fraw, ffull, acc, reinterpret_cast<double*>(fraw));
+        gather_pair<MD, PULL>(kp, src, x, j, t, fa, fb);
+        process_node<MD, EVAL, NT, REC>(kp, x, j, t, fa, fb, dst, mom, fraw, ffull, acc,
+                                        reinterpret_cast<double*>(fraw));
       }
     }
     if (EVAL) return;
@@ -1083,7 +1188,7 @@ __device__ __forceinline__ void kappa_from_values(const KParams& kp, int e, cons
 // source (same deviation correction, same DBB).
 template <class MD>
 __device__ __forceinline__ void lds_gather(const KParams& kp, const typename MD::Pt (*lds)[9][kTX], int l, int w,
-                                           int j, typename MD::Ct fa[9], typename MD::Ct fb[9]) {
+                                           int x, int j, long long t, typename MD::Ct fa[9], typename MD::Ct fb[9]) {
   using C = typename MD::Ct;
   const bool bot = j == 0, top = j == kp.ny - 1;
   const int wm = bot ? w : w - 1, wp = top ? w : w + 1;  // the wall-crossing loads are discarded
@@ -1094,10 +1199,10 @@ __device__ __forceinline__ void lds_gather(const KParams& kp, const typename MD:
     const typename MD::Pt v = lds[sw[i]][i][sl[i]];
     fa[i] = C(v[0]);
     fb[i] = C(v[1]);
-    if (MD::kDev && (i == 1 || i == 3 || i >= 5)) {
-      fa[i] += C(kp.corr[0][i]);
-      fb[i] += C(kp.corr[1][i]);
-    }
+  }
+  if constexpr (MD::kDev) {
+    add_stream_corr<MD>(kp, x, j, t, 0, fa);
+    add_stream_corr<MD>(kp, x, j, t, 1, fb);
   }
   if (bot || top) {
     const int o0 = bot ? 4 : 2, o1 = bot ? 7 : 5, o2 = bot ? 8 : 6;
@@ -1121,7 +1226,7 @@ constexpr int kStripRows = 64;
 // pairs Q (storage type): gather_pair with the strip as the source.
 template <class MD>
 __device__ __forceinline__ void strip_gather(const KParams& kp, const typename MD::Pt (*Q)[kStripRows][9], int e,
-                                             int c, int j, typename MD::Ct fa[9], typename MD::Ct fb[9]) {
+                                             int c, int j, long long t, typename MD::Ct fa[9], typename MD::Ct fb[9]) {
   using C = typename MD::Ct;
   const bool bot = j == 0, top = j == kp.ny - 1;
   const int jm = bot ? j : j - 1, jp = top ? j : j + 1;  // the wall-crossing loads are discarded
@@ -1134,10 +1239,11 @@ __device__ __forceinline__ void strip_gather(const KParams& kp, const typename M
     const typename MD::Pt v = Q[sc[i]][sy[i]][i];
     fa[i] = C(v[0]);
     fb[i] = C(v[1]);
-    if (MD::kDev && (i == 1 || i == 3 || i >= 5)) {
-      fa[i] += C(kp.corr[0][i]);
-      fb[i] += C(kp.corr[1][i]);
-    }
+  }
+  if constexpr (MD::kDev) {
+    const int x = e ? kp.nx - 1 - c : c;
+    add_stream_corr<MD>(kp, x, j, t, 0, fa);
+    add_stream_corr<MD>(kp, x, j, t, 1, fb);
   }
   if (bot || top) {
     const int o0 = bot ? 4 : 2, o1 = bot ? 7 : 5, o2 = bot ? 8 : 6;
@@ -1186,7 +1292,7 @@ typedef double EndSums[2][kEndCols][4][kStripRows];
 // and stores the three columns. sums1 / sums2: the node's sums per level.
 template <class MD, bool NT>
 __device__ __forceinline__ void end_block2_node(const KParams& kp, const typename MD::St* __restrict__ src,
-                                                typename MD::St* __restrict__ dst, int e, int nlev,
+                                                typename MD::St* __restrict__ dst, int e, int nlev, long long t1,
                                                 typename MD::Pt (*Q)[kStripRows][9],
                                                 typename MD::Ct (*P)[kStripRows][9][2], double* Kv,
                                                 double (*redk)[kTY][kTX], EndSums& V) {
@@ -1199,7 +1305,7 @@ __device__ __forceinline__ void end_block2_node(const KParams& kp, const typenam
   double sums1[4] = {0.0, 0.0, 0.0, 0.0}, sums2[4] = {0.0, 0.0, 0.0, 0.0};
   // ---- first level
   C fa[9], fb[9];
-  if (act) gather_pair<MD, true>(kp, src, x, j, fa, fb);
+  if (act) gather_pair<MD, true>(kp, src, x, j, t1, fa, fb);
   if (act && (c == 1 || c == 2)) {
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
@@ -1214,7 +1320,7 @@ __device__ __forceinline__ void end_block2_node(const KParams& kp, const typenam
   if (act) {
     if (c == 0) strip_rebuild<MD>(kp, e, col, j, P, kap, km1, fa, fb);
     const NodeState<C> st = node_moments<MD, false>(kp, x, j, fa, fb, nullptr, nullptr, nullptr, sums1);
-    node_collide_only<MD>(kp, fa, fb, st);
+    node_collide_only<MD>(kp, x, j, t1, fa, fb, st);
     if (nlev == 2) {
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
@@ -1231,7 +1337,7 @@ __device__ __forceinline__ void end_block2_node(const KParams& kp, const typenam
     __syncthreads();
     // ---- second level: columns 0 to 2
     if (act && c < kEndCols) {
-      strip_gather<MD>(kp, Q, e, c, j, fa, fb);
+      strip_gather<MD>(kp, Q, e, c, j, t1 + 1, fa, fb);
       if (c > 0) {
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
@@ -1247,7 +1353,7 @@ __device__ __forceinline__ void end_block2_node(const KParams& kp, const typenam
     if (act && c < kEndCols) {
       if (c == 0) strip_rebuild<MD>(kp, e, col, j, P, kap, km1, fa, fb);
       const NodeState<C> st = node_moments<MD, false>(kp, x, j, fa, fb, nullptr, nullptr, nullptr, sums2);
-      node_collide_only<MD>(kp, fa, fb, st);
+      node_collide_only<MD>(kp, x, j, t1 + 1, fa, fb, st);
       node_store<MD, NT>(kp, x, j, fa, fb, dst);
     }
   }
@@ -1287,7 +1393,7 @@ __device__ __forceinline__ void strip_rebuild1(const KParams& kp, int e, int col
 // j = t / 8); phase 2: column c = t / 128, row j = (t / 2) % 64.
 template <class MD, bool NT>
 __device__ __forceinline__ void end_block2_pair(const KParams& kp, const typename MD::St* __restrict__ src,
-                                                typename MD::St* __restrict__ dst, int e, int nlev,
+                                                typename MD::St* __restrict__ dst, int e, int nlev, long long t1,
                                                 typename MD::Pt (*Q)[kStripRows][9],
                                                 typename MD::Ct (*P)[kStripRows][9][2], double* Kv,
                                                 double (*redk)[kTY][kTX], EndSums& V) {
@@ -1303,7 +1409,7 @@ __device__ __forceinline__ void end_block2_pair(const KParams& kp, const typenam
   // ---- first level
   {
     C fa[9], fb[9];
-    if (act) gather_pair<MD, true>(kp, src, x, j, fa, fb);
+    if (act) gather_pair<MD, true>(kp, src, x, j, t1, fa, fb);
 #pragma unroll
     for (int i = 0; i < 9; ++i) f[i] = s ? fb[i] : fa[i];
   }
@@ -1315,7 +1421,7 @@ __device__ __forceinline__ void end_block2_pair(const KParams& kp, const typenam
   __syncthreads();
   kappa_from_values<MD>(kp, e, Kv, redk, kap, km1);
   if (act && c == 0) strip_rebuild1<MD>(kp, e, col, j, s, P, kap, km1, f);
-  process_pair<MD, false, 1, false, true>(kp, x, j, s, act, f, nullptr, nullptr, nullptr, nullptr, sums1);
+  process_pair<MD, false, 1, false, true>(kp, x, j, t1, s, act, f, nullptr, nullptr, nullptr, nullptr, sums1);
   if (nlev == 2) {
     if (act)
 #pragma unroll
@@ -1331,7 +1437,7 @@ __device__ __forceinline__ void end_block2_pair(const KParams& kp, const typenam
     // ---- second level: columns 0 to 2
     if (act2) {
       C fa[9], fb[9];
-      strip_gather<MD>(kp, Q, e, c2, j2, fa, fb);
+      strip_gather<MD>(kp, Q, e, c2, j2, t1 + 1, fa, fb);
 #pragma unroll
       for (int i = 0; i < 9; ++i) f[i] = s ? fb[i] : fa[i];
       if (c2 > 0) {
@@ -1344,7 +1450,7 @@ __device__ __forceinline__ void end_block2_pair(const KParams& kp, const typenam
     kappa_from_values<MD>(kp, e, Kv, redk, kap, km1);
     if (c2 < kEndCols) {  // both lanes of each pair (wavefronts 0 to 5)
       if (act2 && c2 == 0) strip_rebuild1<MD>(kp, e, col, j2, s, P, kap, km1, f);
-      process_pair<MD, false, 1, true, true>(kp, col + sgn * c2, j2, s, act2, f, dst, nullptr, nullptr, nullptr,
+      process_pair<MD, false, 1, true, true>(kp, col + sgn * c2, j2, t1 + 1, s, act2, f, dst, nullptr, nullptr, nullptr,
                                              sums2);
     }
   }
@@ -1399,9 +1505,9 @@ __device__ __forceinline__ void end_block2(const KParams& kp, const KBufs& kb, c
   }
   EndSums& V = *reinterpret_cast<EndSums*>(&red[0][0][0]);
   if (kPairEnd<MD>)
-    end_block2_pair<MD, NT>(kp, src, dst, e, lv.nlev, Q, P, Kv, redk, V);
+    end_block2_pair<MD, NT>(kp, src, dst, e, lv.nlev, lv.t1, Q, P, Kv, redk, V);
   else
-    end_block2_node<MD, NT>(kp, src, dst, e, lv.nlev, Q, P, Kv, redk, V);
+    end_block2_node<MD, NT>(kp, src, dst, e, lv.nlev, lv.t1, Q, P, Kv, redk, V);
   if (!lv.reduce) return;  // uniform over the block
   __syncthreads();
   // sum k = (level, column, quantity): thread 8 k + g adds rows 8 g .. 8 g + 7
@@ -1460,7 +1566,7 @@ __device__ __forceinline__ void tile2(const KParams& kp, const KBufs& kb, const 
   C fa[9], fb[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) fa[i] = fb[i] = C(0);
-  if (valid) gather_pair<MD, true>(kp, src, x, j, fa, fb);
+  if (valid) gather_pair<MD, true>(kp, src, x, j, lv.t1, fa, fb);
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   if (valid) {
     double tmp[4] = {0.0, 0.0, 0.0, 0.0};
@@ -1468,7 +1574,7 @@ __device__ __forceinline__ void tile2(const KParams& kp, const KBufs& kb, const 
     if (own)
 #pragma unroll
       for (int q = 0; q < 4; ++q) acc[q] = tmp[q];
-    node_collide_only<MD>(kp, fa, fb, st);
+    node_collide_only<MD>(kp, x, j, lv.t1, fa, fb, st);
   }
   if (lv.nlev == 2) {
 #pragma unroll
@@ -1495,12 +1601,12 @@ __device__ __forceinline__ void tile2(const KParams& kp, const KBufs& kb, const 
   for (int q = 0; q < 4; ++q) acc[q] = 0.0;
   if (own) {
     C ha[9], hb[9];
-    lds_gather<MD>(kp, lds, lane, w, j, ha, hb);
+    lds_gather<MD>(kp, lds, lane, w, x, j, lv.t1 + 1, ha, hb);
     double tmp[4] = {0.0, 0.0, 0.0, 0.0};
     const NodeState<C> st = node_moments<MD, false>(kp, x, j, ha, hb, nullptr, nullptr, nullptr, tmp);
 #pragma unroll
     for (int q = 0; q < 4; ++q) acc[q] = tmp[q];
-    node_collide_only<MD>(kp, ha, hb, st);
+    node_collide_only<MD>(kp, x, j, lv.t1 + 1, ha, hb, st);
     node_store<MD, NT>(kp, x, j, ha, hb, dst);
   }
   __syncthreads();  // the first level's sums are read
@@ -1850,6 +1956,7 @@ struct lbsep_channel {
   int64_t strip_next;  // levels below are strip-reduced
   int64_t glob_next;   // levels below have their record
   bool pipe2;          // levels since the last set / init came from two-level launches
+  uint64_t gen;        // bumped by every change of the state (init, set, step): batches check it
 };
 
 namespace {
@@ -1953,6 +2060,7 @@ int finalize(lbsep_channel* h);
 
 // Collide the pre-collision state held in f[0] into f[1] at level t.
 int collide_loaded(lbsep_channel* h, int64_t t) {
+  ++h->gen;
   h->t_first = t;
   sweep_any<false, false>(h, h->f[0], h->f[1], nullptr, nullptr, nullptr, t);
   h->cur = 1;
@@ -2172,6 +2280,7 @@ int lbsep_init(const lbsep_params* p, void* dev_ws, size_t ws_bytes, void* hip_s
 int lbsep_step(lbsep_channel* h, int64_t nsteps) {
   if (!h) return fail(LBSEP_EINVAL, "channel is NULL");
   if (nsteps < 0) return fail(LBSEP_EINVAL, "nsteps must be >= 0");
+  if (nsteps > 0) ++h->gen;
   if (h->L.two) {
     for (int64_t n = nsteps; n > 0;) {
       const int nlev = n >= 2 ? 2 : 1;
@@ -2209,6 +2318,7 @@ int lbsep_step_record(lbsep_channel* h, double* dev_pre, double* dev_post) {
   if (!dev_pre || !dev_post) return fail(LBSEP_EINVAL, "dev_pre and dev_post must be device pointers");
   if (h->p.dtype != LBSEP_F64) return fail(LBSEP_EINVAL, "lbsep_step_record needs an FP64 channel");
   if (h->L.two) return fail(LBSEP_EINVAL, "lbsep_step_record needs one level per launch (fused_steps 0 or 1)");
+  ++h->gen;
   const int nxt_buf = 1 - h->cur;
   const int grid = h->L.lead + 8 * h->L.chunk;
   const double* src = static_cast<const double*>(h->f[h->cur]);
@@ -2414,7 +2524,7 @@ void lbsep_destroy(lbsep_channel* h) { delete h; }
 // ---------------------------------------------------------------------------
 struct lbsep_batch {
   std::vector<lbsep_channel*> ch;
-  std::vector<int64_t> t_expect;  // member levels the device step counter was set up for
+  std::vector<uint64_t> gen_expect;  // member state generations the device table was set up for
   hipStream_t stream = nullptr;
   int dtype = 0;
   bool nt = false;
@@ -2560,7 +2670,7 @@ int lbsep_batch_create(lbsep_channel* const* chans, int32_t n, void* dev_ws, siz
     first += nb;
     if (!c->L.split) node_state += c->L.state_buf;
     b->ch.push_back(c);
-    b->t_expect.push_back(c->t);
+    b->gen_expect.push_back(c->gen);
   }
   // non-temporal stores once the one-lane-per-node members' states outgrow
   // half the last-level cache together
@@ -2586,8 +2696,11 @@ int lbsep_batch_create(lbsep_channel* const* chans, int32_t n, void* dev_ws, siz
 int lbsep_batch_step(lbsep_batch* b, int64_t nsteps) {
   if (!b) return fail(LBSEP_EINVAL, "batch is NULL");
   if (nsteps < 0) return fail(LBSEP_EINVAL, "nsteps must be >= 0");
+  // the device table holds each member's level and current buffer as of the
+  // batch's creation: any change of a member's state since (a step, a set at
+  // any level) leaves the table stale
   for (size_t i = 0; i < b->ch.size(); ++i)
-    if (b->ch[i]->t != b->t_expect[i])
+    if (b->ch[i]->gen != b->gen_expect[i])
       return fail(LBSEP_EINVAL, "channel " + std::to_string(i) + " was stepped or reset outside its batch");
   int64_t left = nsteps;
   while (b->exec && left >= b->graph_steps) {
@@ -2604,7 +2717,8 @@ int lbsep_batch_step(lbsep_batch* b, int64_t nsteps) {
       c->prev_buf = 1 - c->cur;
       c->finalized = false;
     }
-    b->t_expect[i] = c->t;
+    if (nsteps > 0) ++c->gen;
+    b->gen_expect[i] = c->gen;
   }
   return check_hip(hipGetLastError(), "batch step launch");
 }

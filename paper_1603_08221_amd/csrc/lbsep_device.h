@@ -7,6 +7,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "e1_table.h"
 
 namespace lbsep {
@@ -312,26 +314,84 @@ __device__ __forceinline__ void collide_species(T f[9], T rho_c, T rho, T ux, T 
   pxx -= w_s * (pxx - rho * (ux * ux - uy * uy));
   pxy -= w_s * (pxy - rho * ux * uy);
 
-  const T a0 = rho_c * T(1.0 / 9.0);
-  const T a1 = e * T(1.0 / 36.0);
-  const T a2 = eps * T(1.0 / 36.0);
-  const T a3 = jx * T(1.0 / 6.0);
-  const T a4 = qx * T(1.0 / 12.0);
-  const T a5 = jy * T(1.0 / 6.0);
-  const T a6 = qy * T(1.0 / 12.0);
-  const T a7 = pxx * T(0.25);
-  const T a8 = pxy * T(0.25);
-  const T axis = a0 - a1 - T(2) * a2;
-  const T diag = a0 + T(2) * a1 + a2;
-  f[0] = a0 - T(4) * a1 + T(4) * a2;
-  f[1] = axis + a3 - T(2) * a4 + a7;
-  f[2] = axis + a5 - T(2) * a6 - a7;
-  f[3] = axis - a3 + T(2) * a4 + a7;
-  f[4] = axis - a5 + T(2) * a6 - a7;
-  f[5] = diag + a3 + a4 + a5 + a6 + a8;
-  f[6] = diag - a3 - a4 + a5 + a6 - a8;
-  f[7] = diag - a3 - a4 - a5 - a6 + a8;
-  f[8] = diag + a3 + a4 - a5 - a6 - a8;
+  if constexpr (std::is_same<T, float>::value) {
+    // Single precision: the float values of 1/9, 1/6, 1/12 and 1/36 all lie
+    // above the exact ratios (by 7e-9 to 3e-8 relative), and the scalings of
+    // M^-1 would carry that error into every collision with the same sign:
+    // the species density would grow by a factor 1 + 7e-9 per step and the
+    // momentum by 1 + 3e-8, a drift that builds up over the tens of
+    // thousands of steps a channel takes to settle. Here the scalings use
+    // the ratio as the sum of two floats (the rest below float rounding),
+    // and the rest population takes what the other eight leave of the
+    // species density, so that the post-collision populations carry the
+    // pre-collision density up to rounding of either sign.
+    constexpr float h36 = 1.0f / 36.0f, l36 = float(1.0 / 36.0 - double(1.0f / 36.0f));
+    constexpr float h9 = 1.0f / 9.0f, l9 = float(1.0 / 9.0 - double(1.0f / 9.0f));
+    constexpr float h6 = 1.0f / 6.0f, l6 = float(1.0 / 6.0 - double(1.0f / 6.0f));
+    constexpr float h12 = 1.0f / 12.0f, l12 = float(1.0 / 12.0 - double(1.0f / 12.0f));
+    const T a0 = __builtin_fmaf(rho_c, h9, rho_c * l9);
+    const T a1 = __builtin_fmaf(e, h36, e * l36);
+    const T a2 = __builtin_fmaf(eps, h36, eps * l36);
+    const T a3 = __builtin_fmaf(jx, h6, jx * l6);
+    const T a4 = __builtin_fmaf(qx, h12, qx * l12);
+    const T a5 = __builtin_fmaf(jy, h6, jy * l6);
+    const T a6 = __builtin_fmaf(qy, h12, qy * l12);
+    const T a7 = pxx * T(0.25);
+    const T a8 = pxy * T(0.25);
+    const T axis = a0 - a1 - T(2) * a2;
+    const T diag = a0 + T(2) * a1 + a2;
+    f[1] = axis + a3 - T(2) * a4 + a7;
+    f[2] = axis + a5 - T(2) * a6 - a7;
+    f[3] = axis - a3 + T(2) * a4 + a7;
+    f[4] = axis - a5 + T(2) * a6 - a7;
+    f[5] = diag + a3 + a4 + a5 + a6 + a8;
+    f[6] = diag - a3 - a4 + a5 + a6 - a8;
+    f[7] = diag - a3 - a4 - a5 - a6 + a8;
+    f[8] = diag + a3 + a4 - a5 - a6 - a8;
+    f[0] = rho_c - (((f[1] + f[2]) + (f[3] + f[4])) + ((f[5] + f[6]) + (f[7] + f[8])));
+  } else {
+    const T a0 = rho_c * T(1.0 / 9.0);
+    const T a1 = e * T(1.0 / 36.0);
+    const T a2 = eps * T(1.0 / 36.0);
+    const T a3 = jx * T(1.0 / 6.0);
+    const T a4 = qx * T(1.0 / 12.0);
+    const T a5 = jy * T(1.0 / 6.0);
+    const T a6 = qy * T(1.0 / 12.0);
+    const T a7 = pxx * T(0.25);
+    const T a8 = pxy * T(0.25);
+    const T axis = a0 - a1 - T(2) * a2;
+    const T diag = a0 + T(2) * a1 + a2;
+    f[0] = a0 - T(4) * a1 + T(4) * a2;
+    f[1] = axis + a3 - T(2) * a4 + a7;
+    f[2] = axis + a5 - T(2) * a6 - a7;
+    f[3] = axis - a3 + T(2) * a4 + a7;
+    f[4] = axis - a5 + T(2) * a6 - a7;
+    f[5] = diag + a3 + a4 + a5 + a6 + a8;
+    f[6] = diag - a3 - a4 + a5 + a6 - a8;
+    f[7] = diag - a3 - a4 - a5 - a6 + a8;
+    f[8] = diag + a3 + a4 - a5 - a6 - a8;
+  }
+}
+
+// Diffuse-bounce-back at a wall node (Eqs. (bot), (bot2); R12): from the
+// node's own leaving post-collision populations l0 (on the wall normal) and
+// l1, l2 (the two diagonals), with F = l0 + l1 + l2, the returning ones are
+// r feq + (1 - r) l_opposite with the wall equilibrium holding the shares
+// 2/3, 1/6, 1/6 of F: v0 = r (2/3) F + (1 - r) l0, v1 = r F/6 + (1 - r) l1,
+// v2 = r F/6 + (1 - r) l2, so that v0 + v1 + v2 = F. In single precision the
+// float values of 2/3 and 1/6 lie above the exact ratios (3e-8 relative),
+// which would let every wall node gain mass at every step; there the axis
+// value takes what the diagonals leave of F instead.
+template <typename T>
+__device__ __forceinline__ void dbb_shares(T r, T l0, T l1, T l2, T& v0, T& v1, T& v2) {
+  const T q = T(1) - r;
+  const T F = (l0 + l1) + l2;
+  v1 = r * (F * T(1.0 / 6.0)) + q * l1;
+  v2 = r * (F * T(1.0 / 6.0)) + q * l2;
+  if constexpr (std::is_same<T, float>::value)
+    v0 = (F - v1) - v2;
+  else
+    v0 = r * (T(2.0 / 3.0) * F) + q * l0;
 }
 
 }  // namespace lbsep

@@ -1,9 +1,46 @@
-"""Host logic of bench.py (no GPU): how many time levels one sweep launch
-advances, and the lookup of the committed DRAM-traffic record, which must
-match the kernel source, the workload, the dtype, the levels per launch and,
-for a batch, the tile assignment."""
+"""Host logic of bench.py (no GPU): the driver's command line, how many time
+levels one sweep launch advances, and the lookup of the committed DRAM-traffic
+record, which must match the kernel source, the workload, the dtype, the
+levels per launch and, for a batch, the tile assignment."""
+import json
+
+import pytest
+
 import bench
-from paper_1603_08221_amd.workloads import CONFIGS
+from paper_1603_08221_amd.workloads import CONFIGS, batch_instances
+
+
+def test_driver_command_line_is_accepted():
+    """python bench.py --gpus 1 --steps 20 --warmup 5: any step counts, the
+    timed block replays one graph of its own length."""
+    a = bench.parse_args(["--gpus", "1", "--steps", "20", "--warmup", "5"])
+    assert (a.gpus, a.steps, a.warmup, a.dtype) == (1, 20, 5, "f32")
+    assert bench.graph_length(a.steps) == 20
+    assert bench.graph_length(2000) == 100 and bench.graph_length(7) == 7
+    d = bench.parse_args([])
+    assert d.gpus == 1 and d.steps >= 1 and d.warmup >= 0
+    for odd in (["--steps", "3", "--warmup", "1"], ["--steps", "1", "--warmup", "0"]):
+        bench.parse_args(odd)  # no multiple-of-anything rule
+    with pytest.raises(SystemExit):
+        bench.parse_args(["--steps", "0"])
+
+
+def test_more_than_one_gpu_exits_with_a_message(capsys):
+    with pytest.raises(SystemExit) as e:
+        bench.main(["--gpus", "2", "--steps", "20", "--warmup", "5"])
+    assert e.value.code == 2
+    out = json.loads(capsys.readouterr().out.strip())
+    assert out["n_gpus"] == 2 and "one GPU" in out["error"]
+
+
+def test_headline_table_is_the_seeded_64_member_sweep():
+    ws = batch_instances()
+    assert len(ws) == 64
+    nodes = sum(w.nodes for w in ws)
+    assert nodes > 7_000_000                      # about 1 GB of FP32 state: above the last-level cache
+    assert nodes * 36 * 4 > 256 * 2 ** 20
+    assert {w.ny for w in ws} <= {16, 32, 48, 64, 96, 128} and all(w.nx == 20 * w.ny for w in ws)
+    assert bench.METRIC.startswith("MLUPS (both species)")
 
 
 def test_levels_per_launch():
