@@ -26,7 +26,9 @@
  *     the last failure on the calling thread is in lbsep_last_error().
  *   - No C++ exception crosses this boundary. The library never allocates
  *     device memory: the caller owns the workspace and every host buffer; the
- *     library owns only the small host-side handle.
+ *     library owns only the small host-side handle (and, for
+ *     lbsep_adjoint_step_noalloc only, one fixed scratch array per GPU that
+ *     is part of its code object).
  *   - Work is enqueued on the HIP stream given to lbsep_init, in order. Calls
  *     marked "synchronises" wait for that stream before returning.
  *   - A handle is not thread-safe; use one handle per thread or serialise.
@@ -294,6 +296,31 @@ size_t lbsep_adjoint_workspace_bytes(const lbsep_params* p);
  * lam_out must not alias f_t, f_post or lam_next. */
 int lbsep_adjoint_step(lbsep_channel* ch, const double* f_t, const double* f_post, const double* lam_next,
                        double* lam_out, double* dparams, void* adj_ws, size_t adj_ws_bytes);
+
+/* Size of the fixed device scratch of lbsep_adjoint_step_noalloc: 8 MiB per GPU. */
+#define LBSEP_FIXED_SCRATCH_BYTES (8u << 20)
+
+/* lbsep_adjoint_step without a workspace, for callers that cannot allocate
+ * device memory at the call (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc). Same reverse step, same kernels,
+ * same results as lbsep_adjoint_step; its scratch (the closure's adjoints on
+ * the end columns, the per-block r partials and, when f_post is NULL, the
+ * recomputed C(f_t)) lives in a fixed array of LBSEP_FIXED_SCRATCH_BYTES
+ * inside the library, one per GPU, set up on the first call on that GPU and
+ * held until the process ends. Allocates nothing, and calls no allocating
+ * routine.
+ *   Sizes: needs 864 ny + 8 ceil(nx ny / 256) bytes plus a few KB, and
+ *   144 nx ny bytes more when f_post is NULL (at most about 57,000 nodes);
+ *   LBSEP_ESIZE when that exceeds LBSEP_FIXED_SCRATCH_BYTES (nothing is
+ *   enqueued then).
+ *   Sharing: every call on one GPU uses that GPU's one array, and each call
+ *   overwrites everything of it that the call reads. Calls that overlap in
+ *   time on one GPU (several streams, several host threads) race on it and
+ *   must be serialised by the caller; stream-ordered calls on one stream are
+ *   safe. Other arguments, errors and aliasing rules as lbsep_adjoint_step.
+ * Enqueues only. */
+int lbsep_adjoint_step_noalloc(lbsep_channel* ch, const double* f_t, const double* f_post, const double* lam_next,
+                               double* lam_out, double* dparams);
 
 /* Seed of J = CL (Eq. (CL)) at the pre-collision state f_T: lam_out = dCL/df_T
  * (nonzero on the column of the smallest C_l only, R16) and dparams[1] +=

@@ -31,6 +31,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 #include <string>
 
 #include "lbsep.h"
@@ -782,14 +783,16 @@ struct AdjLayout {
   int nblocks;
 };
 
-AdjLayout adj_layout(const lbsep_params* p) {
+// with_post: room for the recomputed post-collision state C(f_t) (a caller
+// workspace always has it; the fixed scratch only when the call needs it)
+AdjLayout adj_layout(const lbsep_params* p, bool with_post = true) {
   AdjLayout L{};
   auto up = [](size_t v) { return (v + 255) / 256 * 256; };
   const long long n = (long long)p->nx * p->ny;
   L.nblocks = (int)((n + kAT - 1) / kAT);
   size_t off = 0;
   L.fpost = off;
-  off += up(18ull * n * sizeof(double));
+  if (with_post) off += up(18ull * n * sizeof(double));
   L.lamP = off;
   off += up(2ull * 2 * 3 * 9 * p->ny * sizeof(double));
   L.part_ends = off;
@@ -802,13 +805,11 @@ AdjLayout adj_layout(const lbsep_params* p) {
   return L;
 }
 
-int make_adj(const lbsep_channel* ch, void* ws, size_t bytes, AdjParams& ap, AdjLayout& L, hipStream_t& st) {
+// The channel's parameters and stream as the adjoint kernels take them.
+int adj_params(const lbsep_channel* ch, AdjParams& ap, hipStream_t& st, lbsep_params* pp = nullptr) {
   ChannelView v;
   if (!channel_view(ch, &v)) return set_error(LBSEP_EINVAL, "channel is NULL");
-  L = adj_layout(&v.p);
-  if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255u))
-    return set_error(LBSEP_EINVAL, "adjoint workspace must be a non-NULL 256-byte aligned device pointer");
-  if (bytes < L.total) return set_error(LBSEP_ESIZE, "adjoint workspace too small");
+  if (pp) *pp = v.p;
   ap.rc = v.rc;
   ap.nx = v.p.nx;
   ap.ny = v.p.ny;
@@ -825,6 +826,78 @@ int make_adj(const lbsep_channel* ch, void* ws, size_t bytes, AdjParams& ap, Adj
   ap.cl_in = v.p.cl_in;
   ap.inv_cl_in = 1.0 / v.p.cl_in;
   st = v.stream;
+  return LBSEP_OK;
+}
+
+int make_adj(const lbsep_channel* ch, void* ws, size_t bytes, AdjParams& ap, AdjLayout& L, hipStream_t& st) {
+  lbsep_params p;
+  if (int e = adj_params(ch, ap, st, &p)) return e;
+  L = adj_layout(&p);
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255u))
+    return set_error(LBSEP_EINVAL, "adjoint workspace must be a non-NULL 256-byte aligned device pointer");
+  if (bytes < L.total) return set_error(LBSEP_ESIZE, "adjoint workspace too small");
+  return LBSEP_OK;
+}
+
+// One reverse step (lbsep_adjoint_step) with its scratch at ws laid out by L.
+int enqueue_adjoint_step(const AdjParams& ap, const AdjLayout& L, hipStream_t st, char* ws, const double* f_t,
+                         const double* f_post, const double* lam_next, double* lam_out, double* dparams) {
+  if (!f_t || !lam_next || !lam_out || !dparams) return set_error(LBSEP_EINVAL, "NULL buffer");
+  if (lam_out == lam_next || lam_out == f_t || (f_post && lam_out == f_post))
+    return set_error(LBSEP_EINVAL, "lam_out must not alias the inputs");
+  const double* fpost = f_post;
+  double* lamP = reinterpret_cast<double*>(ws + L.lamP);
+  double* pe = reinterpret_cast<double*>(ws + L.part_ends);
+  double* pr = reinterpret_cast<double*>(ws + L.part_r);
+  if (!fpost) {  // recompute C(f_t) into the scratch
+    double* own = reinterpret_cast<double*>(ws + L.fpost);
+    hipLaunchKernelGGL(k_adj_post, dim3(L.nblocks), dim3(kAT), 0, st, ap, f_t, own);
+    fpost = own;
+  }
+  const bool ends = !(ap.flags & LBSEP_PERIODIC_X);
+  if (ends) hipLaunchKernelGGL(k_adj_ends, dim3(4), dim3(kAT), 0, st, ap, fpost, lam_next, lamP, pe);
+  hipLaunchKernelGGL(k_adj_main, dim3(L.nblocks), dim3(kAT), 0, st, ap, f_t, fpost, lam_next, lamP, lam_out, pr);
+  hipLaunchKernelGGL(k_adj_params, dim3(1), dim3(kAT), 0, st, ends ? pe : nullptr, pr, L.nblocks, nullptr, 0,
+                     dparams);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_error(LBSEP_EDEVICE, (std::string("adjoint step launch: ") + hipGetErrorString(e)).c_str());
+  return LBSEP_OK;
+}
+
+// ---- fixed scratch of the allocation-free reverse step ------------------------
+// One copy of this array per GPU, loaded with the code object and held until
+// the process ends. Host code never passes the array's name to a kernel (on
+// the host it is only a stand-in for the symbol): the device address comes
+// from hipGetSymbolAddress, once per device, with that device current.
+__device__ __align__(256) unsigned char scratch[LBSEP_FIXED_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices];
+
+// Device address of `scratch` on the device of stream st.
+int fixed_scratch(hipStream_t st, char** out) {
+  hipDevice_t dev = -1;
+  // the null stream belongs to the current device
+  hipError_t e = st ? hipStreamGetDevice(st, &dev) : hipGetDevice(&dev);
+  if (e != hipSuccess)
+    return set_error(LBSEP_EDEVICE, (std::string("device of the channel's stream: ") + hipGetErrorString(e)).c_str());
+  if (dev < 0 || dev >= kMaxDevices) return set_error(LBSEP_EINVAL, "device index beyond the fixed scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    int prev = -1;
+    e = hipGetDevice(&prev);
+    if (e == hipSuccess && prev != dev) e = hipSetDevice(dev);
+    void* p = nullptr;
+    if (e == hipSuccess) e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    const hipError_t e2 = (prev >= 0 && prev != dev) ? hipSetDevice(prev) : hipSuccess;
+    if (e != hipSuccess || !p)
+      return set_error(LBSEP_EDEVICE, (std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e)).c_str());
+    if (e2 != hipSuccess)
+      return set_error(LBSEP_EDEVICE, (std::string("hipSetDevice: ") + hipGetErrorString(e2)).c_str());
+    g_scratch_ptr[dev] = static_cast<char*>(p);
+  }
+  *out = g_scratch_ptr[dev];
   return LBSEP_OK;
 }
 
@@ -852,25 +925,26 @@ int lbsep_adjoint_step(lbsep_channel* ch, const double* f_t, const double* f_pos
   AdjLayout L;
   hipStream_t st;
   if (int e = make_adj(ch, adj_ws, adj_ws_bytes, ap, L, st)) return e;
-  if (!f_t || !lam_next || !lam_out || !dparams) return set_error(LBSEP_EINVAL, "NULL buffer");
-  if (lam_out == lam_next || lam_out == f_t || (f_post && lam_out == f_post))
-    return set_error(LBSEP_EINVAL, "lam_out must not alias the inputs");
-  char* ws = static_cast<char*>(adj_ws);
-  const double* fpost = f_post;
-  double* lamP = reinterpret_cast<double*>(ws + L.lamP);
-  double* pe = reinterpret_cast<double*>(ws + L.part_ends);
-  double* pr = reinterpret_cast<double*>(ws + L.part_r);
-  if (!fpost) {  // recompute C(f_t) into the workspace
-    double* own = reinterpret_cast<double*>(ws + L.fpost);
-    hipLaunchKernelGGL(k_adj_post, dim3(L.nblocks), dim3(kAT), 0, st, ap, f_t, own);
-    fpost = own;
-  }
-  const bool ends = !(ap.flags & LBSEP_PERIODIC_X);
-  if (ends) hipLaunchKernelGGL(k_adj_ends, dim3(4), dim3(kAT), 0, st, ap, fpost, lam_next, lamP, pe);
-  hipLaunchKernelGGL(k_adj_main, dim3(L.nblocks), dim3(kAT), 0, st, ap, f_t, fpost, lam_next, lamP, lam_out, pr);
-  hipLaunchKernelGGL(k_adj_params, dim3(1), dim3(kAT), 0, st, ends ? pe : nullptr, pr, L.nblocks, nullptr, 0,
-                     dparams);
-  return hip_ok("adjoint step launch");
+  return enqueue_adjoint_step(ap, L, st, static_cast<char*>(adj_ws), f_t, f_post, lam_next, lam_out, dparams);
+}
+
+int lbsep_adjoint_step_noalloc(lbsep_channel* ch, const double* f_t, const double* f_post, const double* lam_next,
+                               double* lam_out, double* dparams) {
+  AdjParams ap;
+  hipStream_t st;
+  lbsep_params p;
+  if (int e = adj_params(ch, ap, st, &p)) return e;
+  const AdjLayout L = adj_layout(&p, f_post == nullptr);
+  if (L.total > (size_t)LBSEP_FIXED_SCRATCH_BYTES)
+    return set_error(LBSEP_ESIZE, ("lbsep_adjoint_step_noalloc: this channel needs " + std::to_string(L.total) +
+                                   " bytes of scratch, the fixed scratch holds " +
+                                   std::to_string((size_t)LBSEP_FIXED_SCRATCH_BYTES) +
+                                   (f_post ? "" : " (passing f_post needs less)") +
+                                   "; use lbsep_adjoint_step with a workspace")
+                                      .c_str());
+  char* ws = nullptr;
+  if (int e = fixed_scratch(st, &ws)) return e;
+  return enqueue_adjoint_step(ap, L, st, ws, f_t, f_post, lam_next, lam_out, dparams);
 }
 
 int lbsep_adjoint_seed_cl(lbsep_channel* ch, const double* f_T, double* lam_out, double* dparams, void* adj_ws,

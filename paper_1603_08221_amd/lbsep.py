@@ -87,6 +87,7 @@ def load():
         "lbsep_adjoint_workspace_bytes": (c_size_t, [P]),
         "lbsep_adjoint_step": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                        c_size_t]),
+        "lbsep_adjoint_step_noalloc": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
         "lbsep_adjoint_seed_cl": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t]),
         "lbsep_adjoint_initial": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_size_t]),
     }
