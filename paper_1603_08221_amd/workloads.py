@@ -81,6 +81,53 @@ def batch_instances(n: int = 64, seed: int = 160308221):
     return out
 
 
+# Table 1 (Sec. 2): the cases of the parametric study, He-Ar and Ne-Ar, on a
+# 20 x 700 lattice. Cases 2 and 7 list Kn_out in {0.3, 0.5, 1, 3, 5} and theta
+# in {2, 3, 4, 5}; Sec. 4.1 sweeps theta at Kn_out = 0.3 and Sec. 4.2 sweeps
+# Kn_out at theta = 2, so those two lines expand to 4 + 5 - 1 runs. Cases 1, 3,
+# 6 and 8 are listed at theta = 4.0 but run at theta = 2.0 in the text of
+# Sec. 4.3; both are included (reading R28).
+TABLE1 = [
+    # (case, pair, C_in, C_out, Kn_out values, theta values)
+    (1, "He-Ar", 0.3, 0.3, (0.3,), (4.0,)),
+    (2, "He-Ar", 0.5, 0.5, (0.3, 0.5, 1.0, 3.0, 5.0), (2.0, 3.0, 4.0, 5.0)),
+    (3, "He-Ar", 0.7, 0.7, (0.3,), (4.0,)),
+    (4, "He-Ar", 0.7, 0.3, (0.3, 1.0), (2.0,)),
+    (5, "He-Ar", 0.3, 0.7, (0.3, 1.0), (2.0,)),
+    (6, "Ne-Ar", 0.3, 0.3, (0.3,), (4.0,)),
+    (7, "Ne-Ar", 0.5, 0.5, (0.3, 0.5, 1.0, 3.0, 5.0), (2.0, 3.0, 4.0, 5.0)),
+    (8, "Ne-Ar", 0.7, 0.7, (0.3,), (4.0,)),
+    (9, "Ne-Ar", 0.7, 0.3, (0.3, 1.0), (2.0,)),
+    (10, "Ne-Ar", 0.3, 0.7, (0.3, 1.0), (2.0,)),
+]
+PAIRS = {"He-Ar": HE_AR, "Ne-Ar": NE_AR}
+
+
+def table1_instances(ny: int = 20, nx: int = 700):
+    """The runs of Table 1 on an ny x nx lattice (the paper's is 20 x 700):
+    the theta sweep at Kn_out = 0.3 and the Kn_out sweep at theta = 2 of
+    cases 2 and 7, cases 1, 3, 6, 8 at the listed theta = 4 and at theta = 2,
+    and the unequal-end cases 4, 5, 9, 10 at each listed Kn_out. Names are
+    "c<case>_th<theta>_kn<Kn_out>"."""
+    out = []
+    seen = set()
+    for case, pair, cin, cout, kns, thetas in TABLE1:
+        runs = []
+        if len(kns) > 1 and len(thetas) > 1:
+            runs += [(0.3, th) for th in thetas] + [(kn, 2.0) for kn in kns]
+        elif len(thetas) == 1 and thetas[0] != 2.0:
+            runs += [(kns[0], thetas[0]), (kns[0], 2.0)]
+        else:
+            runs += [(kn, thetas[0]) for kn in kns]
+        for kn, th in runs:
+            name = f"c{case}_th{th:g}_kn{kn:g}"
+            if name in seen:
+                continue
+            seen.add(name)
+            out.append(Workload(name, nx, ny, *PAIRS[pair], cin, cout, th, kn, 0, "f64"))
+    return out
+
+
 def random_state(ny: int, nx: int, seed: int, scale=(1.0, 8.0), spread: float = 0.2,
                  uniform: bool = False) -> np.ndarray:
     """A seeded positive population field (2, 9, ny, nx) in float64: species
