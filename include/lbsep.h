@@ -108,16 +108,17 @@ typedef struct lbsep_params {
                         differ in the last bits. A channel in a batch that fills the GPU can be
                         faster with 2 or 4 (fewer row-tile partial sums). */
   int32_t fused_steps; /* time levels per sweep launch: 0 = chosen by the library (currently 1),
-                        1, or 2 (needs ny <= 64 and an inlet, an outlet and walls: no periodic
-                        flag; else LBSEP_EINVAL). With 2, a launch advances two levels, keeping
-                        the first in LDS (about half the HBM traffic per level); the states are
-                        bitwise those of single-level launches (FP64, FP32), CL and the column
-                        sums agree to rounding. A third state buffer is allocated; readouts right
-                        after a two-level launch recompute the level before (one launch). Such a
-                        channel cannot join a batch. Measured per level on 64-row channels:
-                        faster in FP32 at every length (64x1280 5.3 vs 7.4 us, 64x81920 120 vs
-                        150 us); in FP64 only on short ones (64x1280 11.6 vs 13.6 us; from
-                        2560 columns on slower, 64x20480 137 vs 89 us). */
+                        1, or 2 (needs ny <= 128 for LBSEP_F32 and LBSEP_F16, ny <= 64 for
+                        LBSEP_F64, and an inlet, an outlet and walls: no periodic flag; else
+                        LBSEP_EINVAL). With 2, a launch advances two levels, keeping the first
+                        in LDS (about half the HBM traffic per level); the states are bitwise
+                        those of single-level launches, CL and the column sums agree to
+                        rounding. A third state buffer is allocated; readouts right after a
+                        two-level launch recompute the level before (one launch). Such a
+                        channel joins only a batch whose members all use 2. Measured per level
+                        on 64-row channels: faster in FP32 at every length (64x1280 5.3 vs
+                        7.4 us, 64x81920 120 vs 150 us); in FP64 only on short ones (64x1280
+                        11.6 vs 13.6 us; from 2560 columns on slower, 64x20480 137 vs 89 us). */
 } lbsep_params;
 
 typedef struct lbsep_channel lbsep_channel;
@@ -244,11 +245,13 @@ const char* lbsep_last_error(void);
  * stepping it alone. The member channels stay usable through the channel API
  * (read_cl, read_moments, get_state ...) between batch steps; stepping or
  * resetting a member on its own invalidates the batch (its next step fails
- * with LBSEP_EINVAL). Members must outlive the batch. */
+ * with LBSEP_EINVAL). Members must outlive the batch. The members share one
+ * fused_steps value: with 2, each launch advances every member by two levels
+ * (an odd remainder by one), as stepping each alone would. */
 typedef struct lbsep_batch lbsep_batch;
 
 /* Device workspace bytes for a batch of the n channels chans[0..n-1] (one
- * dtype, one stream, no channel twice); 0 on invalid input. */
+ * dtype, one stream, one fused_steps, no channel twice); 0 on invalid input. */
 size_t lbsep_batch_workspace_bytes(lbsep_channel* const* chans, int32_t n);
 
 /* Build the batch's instance table in dev_ws (caller-owned, 256-byte aligned,

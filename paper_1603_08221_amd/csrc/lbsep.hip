@@ -1166,19 +1166,27 @@ __device__ __forceinline__ void kappa_from_sums(const KParams& kp, int e, double
 
 // kappa of end e from the values v[it] = rho of the pulled populations of the
 // two inner layers, it = 4 row + 2 species + layer, in LDS, summed in the
-// order of the single-level end blocks: thread L < 256 adds item L, then
-// kappa_from_sums. Every thread of the block must call it (barriers).
+// order of the single-level end blocks: thread L < 256 adds item L and then,
+// for more than 64 rows, item L + 256 (the single-level end blocks of rows
+// 0-63 and 64-127 both hold that pair in thread L), then kappa_from_sums.
+// Every thread of the block must call it (barriers).
 template <class MD>
 __device__ __forceinline__ void kappa_from_values(const KParams& kp, int e, const double* v, double (*red)[kTY][kTX],
                                                   double kap[2], double km1[2]) {
   double sums[2] = {0.0, 0.0};
   const int it = threadIdx.x;
-  if (it < 4 * kp.ny) {
-    const int ss = (it >> 1) & 1, ll = it & 1;
-    if (ss)
-      sums[1] += ll ? -v[it] : 2.0 * v[it];
-    else
-      sums[0] += ll ? -v[it] : 2.0 * v[it];
+  if (it < kThreads) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int item = it + k * kThreads;
+      if (item < 4 * kp.ny) {
+        const int ss = (item >> 1) & 1, ll = item & 1;
+        if (ss)
+          sums[1] += ll ? -v[item] : 2.0 * v[item];
+        else
+          sums[0] += ll ? -v[item] : 2.0 * v[item];
+      }
+    }
   }
   kappa_from_sums<MD>(kp, e, red, sums, kap, km1);
 }
@@ -1218,14 +1226,17 @@ __device__ __forceinline__ double wave_column_sum(const double (*red)[kW2][kTX],
   return v;
 }
 
-// The end strip of a channel of at most 64 rows in LDS: column c (0 = the end
-// column, counted inwards), row j, direction i.
-constexpr int kStripRows = 64;
+// The end strip of a two-level launch in LDS: column c (0 = the end column,
+// counted inwards), row j, direction i; at most 128 rows in the deviation
+// modes (one node per thread of the 512-thread block), 64 in FP64 (a lane
+// pair per node, and twice the bytes per population).
+template <class MD>
+constexpr int kStripRowsOf = MD::kDev ? 128 : 64;
 
 // Pulled populations of node (c, j) of end e's strip from its post-collision
 // pairs Q (storage type): gather_pair with the strip as the source.
 template <class MD>
-__device__ __forceinline__ void strip_gather(const KParams& kp, const typename MD::Pt (*Q)[kStripRows][9], int e,
+__device__ __forceinline__ void strip_gather(const KParams& kp, const typename MD::Pt (*Q)[kStripRowsOf<MD>][9], int e,
                                              int c, int j, long long t, typename MD::Ct fa[9], typename MD::Ct fb[9]) {
   using C = typename MD::Ct;
   const bool bot = j == 0, top = j == kp.ny - 1;
@@ -1251,74 +1262,73 @@ __device__ __forceinline__ void strip_gather(const KParams& kp, const typename M
   }
 }
 
-// end_rebuild of both species of the end node in row j from the inner layers'
-// pulled populations P[layer][j][i][species] in LDS.
-template <class MD>
-__device__ __forceinline__ void strip_rebuild(const KParams& kp, int e, int col, int j,
-                                              const typename MD::Ct (*P)[kStripRows][9][2], const double kap[2],
-                                              const double km1[2], typename MD::Ct fa[9], typename MD::Ct fb[9]) {
-  using C = typename MD::Ct;
-  C g1[9], g2[9];
-#pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    g1[i] = P[0][j][i][0];
-    g2[i] = P[1][j][i][0];
-  }
-  end_rebuild<MD>(kp, e, 0, col, kap[0], km1[0], g1, g2, fa);
-#pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    g1[i] = P[0][j][i][1];
-    g2[i] = P[1][j][i][1];
-  }
-  end_rebuild<MD>(kp, e, 1, col, kap[1], km1[1], g1, g2, fb);
-}
-
 // Columns of each end a two-level launch gives to its end block: the end
 // column and the next two (counted inwards). The tiles own the columns
 // between, so that no tile touches an end column or needs kappa.
 constexpr int kEndCols = 3;
 
-// Per-node sums of an end block, by level, column, quantity (n_a, n_b,
-// rho_a u_ax, rho_b u_bx) and row; kept in LDS until the block reduces them.
-typedef double EndSums[2][kEndCols][4][kStripRows];
+// Per-node sums of one level of an end block, by column, quantity (n_a, n_b,
+// rho_a u_ax, rho_b u_bx) and row, in LDS while the block reduces them.
+template <class MD>
+using EndSums = double[kEndCols][4][kStripRowsOf<MD>];
 
-// End block of a two-level launch on a channel of at most 64 rows, one lane
-// per node: task (c, j) = (thread % 4, thread / 4); the four outermost columns
-// of the first level stay in LDS. Phase 1 pulls every node once: the two inner
-// layers' values give kappa (kappa_from_values) and the end column's rebuild;
-// the four columns collide into LDS in the storage type (nlev = 1: columns 0
-// to 2 are stored to dst instead). Phase 2 pulls columns 0 to 2 from LDS,
-// takes the second kappa the same way, rebuilds the end column and collides
-// and stores the three columns. sums1 / sums2: the node's sums per level.
+// A thread's own sums of the nodes it computed, per level: column c, row j,
+// the quantities q (all four, or with a lane pair per node q = s and 2 + s).
+struct EndNodeSums {
+  double v[2][4];
+  int c[2], j[2], s[2];  // s = -1: all four quantities
+  bool on[2];
+};
+
+// End block of a two-level launch, one lane per node: task (c, j) = (thread
+// % 4, thread / 4), so a quad holds the four outermost columns of row j; the
+// first level of those columns stays in LDS. Phase 1 pulls every node once:
+// the two inner layers' values give kappa (kappa_from_values) and, moved to
+// the end column's lane within the quad, its rebuild; the four columns
+// collide into LDS in the storage type (nlev = 1: columns 0 to 2 are stored to
+// dst instead). Phase 2 pulls columns 0 to 2 from LDS, takes the second kappa
+// the same way, rebuilds the end column and collides and stores the three
+// columns. ns: the node's sums per level.
 template <class MD, bool NT>
 __device__ __forceinline__ void end_block2_node(const KParams& kp, const typename MD::St* __restrict__ src,
                                                 typename MD::St* __restrict__ dst, int e, int nlev, long long t1,
-                                                typename MD::Pt (*Q)[kStripRows][9],
-                                                typename MD::Ct (*P)[kStripRows][9][2], double* Kv,
-                                                double (*redk)[kTY][kTX], EndSums& V) {
+                                                typename MD::Pt (*Q)[kStripRowsOf<MD>][9], double* Kv,
+                                                double (*redk)[kTY][kTX], EndNodeSums& ns) {
   using C = typename MD::Ct;
   const int sgn = e ? -1 : 1, col = e ? kp.nx - 1 : 0;
   const int c = threadIdx.x & 3, j = threadIdx.x >> 2;
-  const bool act = j < kp.ny;
+  const bool act = j < kp.ny;  // uniform over a quad
   const int x = col + sgn * c;
   double kap[2], km1[2];
   double sums1[4] = {0.0, 0.0, 0.0, 0.0}, sums2[4] = {0.0, 0.0, 0.0, 0.0};
+  // the end column's rebuild from the first and second inner layers' pulled
+  // populations, lanes c = 1 and 2 of the same quad (exact moves)
+  auto rebuild = [&](C fa[9], C fb[9]) {
+    C g1[9], g2[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      g1[i] = lane_xor(fa[i], 1);
+      g2[i] = lane_xor(fa[i], 2);
+    }
+    if (c == 0) end_rebuild<MD>(kp, e, 0, col, kap[0], km1[0], g1, g2, fa);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      g1[i] = lane_xor(fb[i], 1);
+      g2[i] = lane_xor(fb[i], 2);
+    }
+    if (c == 0) end_rebuild<MD>(kp, e, 1, col, kap[1], km1[1], g1, g2, fb);
+  };
   // ---- first level
   C fa[9], fb[9];
   if (act) gather_pair<MD, true>(kp, src, x, j, t1, fa, fb);
   if (act && (c == 1 || c == 2)) {
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      P[c - 1][j][i][0] = fa[i];
-      P[c - 1][j][i][1] = fb[i];
-    }
     Kv[4 * j + (c - 1)] = double(sum9(fa));
     Kv[4 * j + 2 + (c - 1)] = double(sum9(fb));
   }
   __syncthreads();
   kappa_from_values<MD>(kp, e, Kv, redk, kap, km1);
   if (act) {
-    if (c == 0) strip_rebuild<MD>(kp, e, col, j, P, kap, km1, fa, fb);
+    rebuild(fa, fb);
     const NodeState<C> st = node_moments<MD, false>(kp, x, j, fa, fb, nullptr, nullptr, nullptr, sums1);
     node_collide_only<MD>(kp, x, j, t1, fa, fb, st);
     if (nlev == 2) {
@@ -1335,15 +1345,10 @@ __device__ __forceinline__ void end_block2_node(const KParams& kp, const typenam
   }
   if (nlev == 2) {
     __syncthreads();
-    // ---- second level: columns 0 to 2
+    // ---- second level: columns 0 to 2 (lanes c = 3 idle)
     if (act && c < kEndCols) {
       strip_gather<MD>(kp, Q, e, c, j, t1 + 1, fa, fb);
       if (c > 0) {
-#pragma unroll
-        for (int i = 0; i < 9; ++i) {
-          P[c - 1][j][i][0] = fa[i];
-          P[c - 1][j][i][1] = fb[i];
-        }
         Kv[4 * j + (c - 1)] = double(sum9(fa));
         Kv[4 * j + 2 + (c - 1)] = double(sum9(fb));
       }
@@ -1351,19 +1356,24 @@ __device__ __forceinline__ void end_block2_node(const KParams& kp, const typenam
     __syncthreads();
     kappa_from_values<MD>(kp, e, Kv, redk, kap, km1);
     if (act && c < kEndCols) {
-      if (c == 0) strip_rebuild<MD>(kp, e, col, j, P, kap, km1, fa, fb);
+      rebuild(fa, fb);
       const NodeState<C> st = node_moments<MD, false>(kp, x, j, fa, fb, nullptr, nullptr, nullptr, sums2);
       node_collide_only<MD>(kp, x, j, t1 + 1, fa, fb, st);
       node_store<MD, NT>(kp, x, j, fa, fb, dst);
     }
   }
-  // kappa_from_values ends with a barrier: V (in the reduction scratch) is free
-  if (act && c < kEndCols)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      V[0][c][q][j] = sums1[q];
-      V[1][c][q][j] = sums2[q];
-    }
+  for (int q = 0; q < 4; ++q) {
+    ns.v[0][q] = sums1[q];
+    ns.v[1][q] = sums2[q];
+  }
+#pragma unroll
+  for (int l = 0; l < 2; ++l) {
+    ns.c[l] = c;
+    ns.j[l] = j;
+    ns.s[l] = -1;
+    ns.on[l] = act && c < kEndCols && l < nlev;
+  }
 }
 
 // end_rebuild of species s (a runtime value) at the end column from the inner
@@ -1371,7 +1381,7 @@ __device__ __forceinline__ void end_block2_node(const KParams& kp, const typenam
 // species keeps the parameter indexes constant.
 template <class MD>
 __device__ __forceinline__ void strip_rebuild1(const KParams& kp, int e, int col, int j, int s,
-                                               const typename MD::Ct (*P)[kStripRows][9][2], const double kap[2],
+                                               const typename MD::Ct (*P)[kStripRowsOf<MD>][9][2], const double kap[2],
                                                const double km1[2], typename MD::Ct f[9]) {
   using C = typename MD::Ct;
   C g1[9], g2[9];
@@ -1394,9 +1404,9 @@ __device__ __forceinline__ void strip_rebuild1(const KParams& kp, int e, int col
 template <class MD, bool NT>
 __device__ __forceinline__ void end_block2_pair(const KParams& kp, const typename MD::St* __restrict__ src,
                                                 typename MD::St* __restrict__ dst, int e, int nlev, long long t1,
-                                                typename MD::Pt (*Q)[kStripRows][9],
-                                                typename MD::Ct (*P)[kStripRows][9][2], double* Kv,
-                                                double (*redk)[kTY][kTX], EndSums& V) {
+                                                typename MD::Pt (*Q)[kStripRowsOf<MD>][9],
+                                                typename MD::Ct (*P)[kStripRowsOf<MD>][9][2], double* Kv,
+                                                double (*redk)[kTY][kTX], EndNodeSums& ns) {
   using C = typename MD::Ct;
   using S = typename MD::St;
   const int sgn = e ? -1 : 1, col = e ? kp.nx - 1 : 0;
@@ -1454,15 +1464,17 @@ __device__ __forceinline__ void end_block2_pair(const KParams& kp, const typenam
                                              sums2);
     }
   }
-  // kappa_from_values ends with a barrier: V (in the reduction scratch) is free
-  if (act && c < kEndCols) {
-    V[0][c][s][j] = sums1[0];
-    V[0][c][2 + s][j] = sums1[1];
-  }
-  if (nlev == 2 && act2) {
-    V[1][c2][s][j2] = sums2[0];
-    V[1][c2][2 + s][j2] = sums2[1];
-  }
+  ns.v[0][s] = sums1[0];
+  ns.v[0][2 + s] = sums1[1];
+  ns.v[1][s] = sums2[0];
+  ns.v[1][2 + s] = sums2[1];
+  ns.c[0] = c;
+  ns.j[0] = j;
+  ns.c[1] = c2;
+  ns.j[1] = j2;
+  ns.s[0] = ns.s[1] = s;
+  ns.on[0] = act && c < kEndCols;
+  ns.on[1] = nlev == 2 && act2;
 }
 
 // Lane pairs in the two-level end blocks: in FP64 the wall functions dominate a
@@ -1472,21 +1484,23 @@ __device__ __forceinline__ void end_block2_pair(const KParams& kp, const typenam
 template <class MD>
 constexpr bool kPairEnd = !MD::kDev;
 
-// Inlet (e = 0) or outlet (e = 1) block of k_sweep2 (a channel of at most 64
-// rows): columns 0 to 2 from the end at every level the launch computes, then
-// their sums over the rows: the end column's to the end sums (end block 0 of
-// the level's slot, zeros to the rest), the other two columns' to row tile 0
-// of the partials (zeros to the other row tiles). The zeros go out first (no
-// reduction of this launch reads these levels' slots); each sum is a fixed
-// two-stage order (eight rows per thread, then the eight partial sums).
+// Inlet (e = 0) or outlet (e = 1) block of k_sweep2 (a channel of at most
+// 128 rows, 64 in FP64): columns 0 to 2 from the end at every level the
+// launch computes, then their sums over the rows, level by level: the end
+// column's to the end sums (end block 0 of the level's slot, zeros to the
+// rest), the other two columns' to row tile 0 of the partials (zeros to the
+// other row tiles). The zeros go out first (no reduction of this launch reads
+// these levels' slots); each sum is a fixed two-stage order (an eighth of the
+// strip's rows per thread, then the eight partial sums).
 template <class MD, bool NT>
 __device__ __forceinline__ void end_block2(const KParams& kp, const KBufs& kb, const Lv2& lv,
                                            const typename MD::St* __restrict__ src, typename MD::St* __restrict__ dst,
                                            int e, double (*red)[kW2][kTX], double (*redk)[kTY][kTX],
-                                           typename MD::Pt (*Q)[kStripRows][9], typename MD::Ct (*P)[kStripRows][9][2],
-                                           double* Kv) {
+                                           typename MD::Pt (*Q)[kStripRowsOf<MD>][9],
+                                           typename MD::Ct (*P)[kStripRowsOf<MD>][9][2], double* Kv) {
   if (lv.nlev == 0) return;  // a reductions-only launch
-  static_assert(sizeof(EndSums) <= sizeof(double) * 4 * kW2 * kTX, "the end sums fit the reduction scratch");
+  constexpr int kRows = kStripRowsOf<MD>;
+  static_assert(sizeof(EndSums<MD>) <= sizeof(double) * 4 * kW2 * kTX, "one level's end sums fit the reduction scratch");
   const int sgn = e ? -1 : 1, col = e ? kp.nx - 1 : 0;
   const int t = threadIdx.x;
   if (lv.reduce) {
@@ -1503,37 +1517,50 @@ __device__ __forceinline__ void end_block2(const KParams& kp, const KBufs& kb, c
       }
     }
   }
-  EndSums& V = *reinterpret_cast<EndSums*>(&red[0][0][0]);
-  if (kPairEnd<MD>)
-    end_block2_pair<MD, NT>(kp, src, dst, e, lv.nlev, lv.t1, Q, P, Kv, redk, V);
+  EndNodeSums ns;
+  if constexpr (kPairEnd<MD>)
+    end_block2_pair<MD, NT>(kp, src, dst, e, lv.nlev, lv.t1, Q, P, Kv, redk, ns);
   else
-    end_block2_node<MD, NT>(kp, src, dst, e, lv.nlev, lv.t1, Q, P, Kv, redk, V);
+    end_block2_node<MD, NT>(kp, src, dst, e, lv.nlev, lv.t1, Q, Kv, redk, ns);
   if (!lv.reduce) return;  // uniform over the block
-  __syncthreads();
-  // sum k = (level, column, quantity): thread 8 k + g adds rows 8 g .. 8 g + 7
-  // into Kv (free once kappa is taken), then thread k adds the eight
-  const int nsum = lv.nlev * kEndCols * 4;
-  static_assert(2 * kEndCols * 4 * 8 <= 4 * kStripRows, "the partial sums fit Kv");
-  if (t < 8 * nsum) {
-    const int k = t >> 3, g = t & 7;
-    const double* v = V[k / (kEndCols * 4)][(k / 4) % kEndCols][k % 4];
-    double a = 0.0;
+  // per level: the nodes' sums into LDS by (column, quantity, row), then sum
+  // k = (column, quantity): thread 8 k + g adds rows g R .. g R + R - 1
+  // (R = kRows / 8) into Kv (free once kappa is taken), then thread k adds
+  // the eight
+  EndSums<MD>& V = *reinterpret_cast<EndSums<MD>*>(&red[0][0][0]);
+  constexpr int kGroup = kRows / 8;
+  constexpr int nsum = kEndCols * 4;
+  static_assert(8 * nsum <= 4 * kRows, "the partial sums fit Kv");
 #pragma unroll
-    for (int r = 0; r < 8; ++r)
-      if (8 * g + r < kp.ny) a += v[8 * g + r];
-    Kv[t] = a;
-  }
-  __syncthreads();
-  if (t < nsum) {
-    double a = 0.0;
+  for (int lev = 0; lev < 2; ++lev) {
+    if (lev >= lv.nlev) break;  // uniform over the block
+    __syncthreads();  // red and Kv are free (the last kappa, or the previous level's sums, are read)
+    if (ns.on[lev])
 #pragma unroll
-    for (int g = 0; g < 8; ++g) a += Kv[8 * t + g];
-    const int lev = t / (kEndCols * 4), c = (t / 4) % kEndCols, q = t % 4;
-    const long long level = lv.t1 + lev;
-    if (c == 0)
-      kb.endsum[(((level & 3) * 2 + e) * kMaxEnd) * 4 + q] = a;
-    else
-      kb.partials[(level & 3) * lv.part_stride + (long long)q * lv.nrt * kp.pitch + col + sgn * c] = a;
+      for (int q = 0; q < 4; ++q)
+        if (ns.s[lev] < 0 || q == ns.s[lev] || q == 2 + ns.s[lev]) V[ns.c[lev]][q][ns.j[lev]] = ns.v[lev][q];
+    __syncthreads();
+    if (t < 8 * nsum) {
+      const int k = t >> 3, g = t & 7;
+      const double* v = V[k / 4][k % 4];
+      double a = 0.0;
+#pragma unroll
+      for (int r = 0; r < kGroup; ++r)
+        if (kGroup * g + r < kp.ny) a += v[kGroup * g + r];
+      Kv[t] = a;
+    }
+    __syncthreads();
+    if (t < nsum) {
+      double a = 0.0;
+#pragma unroll
+      for (int g = 0; g < 8; ++g) a += Kv[8 * t + g];
+      const int c = t / 4, q = t % 4;
+      const long long level = lv.t1 + lev;
+      if (c == 0)
+        kb.endsum[(((level & 3) * 2 + e) * kMaxEnd) * 4 + q] = a;
+      else
+        kb.partials[(level & 3) * lv.part_stride + (long long)q * lv.nrt * kp.pitch + col + sgn * c] = a;
+    }
   }
 }
 
@@ -1620,19 +1647,16 @@ __device__ __forceinline__ void tile2(const KParams& kp, const KBufs& kb, const 
   }
 }
 
+// Block b of a two-level launch of one channel (lead blocks, then tiles),
+// with the kernel's LDS.
 template <class MD, bool NT>
-__global__ __launch_bounds__(kT2) void k_sweep2(const KParams* __restrict__ kpp, const KBufs* __restrict__ kbp, Lv2 lv,
-                                                const typename MD::St* __restrict__ src,
-                                                typename MD::St* __restrict__ dst) {
-  const KParams& kp = *kpp;
-  const KBufs& kb = *kbp;
-  __shared__ typename MD::Pt lds[kW2][9][kTX];
-  __shared__ double red[4][kW2][kTX];
-  __shared__ typename MD::Ct pulled[2][kStripRows][9][2];
-  __shared__ double kv[4 * kStripRows];
-  static_assert(4 * kStripRows * 9 <= kW2 * 9 * kTX, "the end strip fits the tile's LDS");
+__device__ __forceinline__ void sweep2_block(const KParams& kp, const KBufs& kb, const Lv2& lv,
+                                             const typename MD::St* __restrict__ src,
+                                             typename MD::St* __restrict__ dst, int b,
+                                             typename MD::Pt (*lds)[9][kTX], double (*red)[kW2][kTX],
+                                             typename MD::Ct (*pulled)[kStripRowsOf<MD>][9][2], double* kv) {
+  constexpr int kRows = kStripRowsOf<MD>;
   double (*redk)[kTY][kTX] = reinterpret_cast<double (*)[kTY][kTX]>(&red[0][0][0]);
-  const int b = blockIdx.x;
   if (b < lv.lead) {
     // the inlet block is block 0 (XCD 0, with the first column strips), the
     // outlet block block 7 (XCD 7, with the last ones); the other lead blocks
@@ -1640,7 +1664,7 @@ __global__ __launch_bounds__(kT2) void k_sweep2(const KParams* __restrict__ kpp,
     if (b == 0 || b == 7) {
       if (!(kp.flags & LBSEP_PERIODIC_X))
         end_block2<MD, NT>(kp, kb, lv, src, dst, b == 7, red, redk,
-                           reinterpret_cast<typename MD::Pt (*)[kStripRows][9]>(&lds[0][0][0]), pulled, kv);
+                           reinterpret_cast<typename MD::Pt (*)[kRows][9]>(&lds[0][0][0]), pulled, kv);
       return;
     }
     const int r = b < 7 ? b - 1 : b - 2;
@@ -1663,6 +1687,83 @@ __global__ __launch_bounds__(kT2) void k_sweep2(const KParams* __restrict__ kpp,
     return;
   }
   tile2<MD, NT>(kp, kb, lv, src, dst, b, lds, red);
+}
+
+// The LDS of a two-level launch: the tile's first level (or an end block's
+// strip), the reduction scratch, the lane-pair end blocks' inner layers and
+// the kappa values.
+#define LBSEP_SWEEP2_LDS                                                                               \
+  constexpr int kRows = kStripRowsOf<MD>;                                                              \
+  __shared__ typename MD::Pt lds[kW2][9][kTX];                                                         \
+  __shared__ double red[4][kW2][kTX];                                                                  \
+  __shared__ typename MD::Ct pulled[kPairEnd<MD> ? 2 : 1][kPairEnd<MD> ? kRows : 1][9][2];             \
+  __shared__ double kv[4 * kRows];                                                                     \
+  static_assert(4 * kRows * 9 <= kW2 * 9 * kTX, "the end strip fits the tile's LDS");                 \
+  auto* pulled_rows = reinterpret_cast<typename MD::Ct (*)[kRows][9][2]>(&pulled[0][0][0][0]);
+
+template <class MD, bool NT>
+__global__ __launch_bounds__(kT2) void k_sweep2(const KParams* __restrict__ kpp, const KBufs* __restrict__ kbp, Lv2 lv,
+                                                const typename MD::St* __restrict__ src,
+                                                typename MD::St* __restrict__ dst) {
+  LBSEP_SWEEP2_LDS
+  sweep2_block<MD, NT>(*kpp, *kbp, lv, src, dst, (int)blockIdx.x, lds, red, pulled_rows, kv);
+}
+
+// A batch of two-level channels swept by one launch per one or two levels:
+// entry i holds channel i's constants (its workspace copies), state buffers
+// and tiling; its blocks are [first_block, first_block + lead + 8 chunk).
+struct Batch2Entry {
+  const KParams* kp;
+  const KBufs* kb;
+  void* f[2];         // the channel's two state buffers
+  long long t0;       // channel level at the batch's creation (no reduction pending then)
+  int cur0;           // buffer holding the post-collision state at creation
+  int first_block;
+  Lv2 lv;             // tiling; the levels are set per launch
+};
+
+// The batch's progress on the device, advanced after each launch
+// (k_batch2_advance), so that a captured step loop replays.
+struct Batch2Levels {
+  long long done;      // levels advanced since creation
+  long long launches;  // launches since creation
+  int prev_n;          // levels of the previous launch (0: none)
+  int prev2_n;         // levels of the launch before it
+};
+
+// One launch of nlev levels for every member: levels t0 + done + 1 ..; the
+// previous launch's levels are strip-reduced and the one's before reduced to
+// records (the order of lbsep_step's two-level launches).
+template <class MD, bool NT>
+__global__ __launch_bounds__(kT2) void k_sweep2_batch(const Batch2Entry* __restrict__ tab,
+                                                      const int* __restrict__ blk_inst,
+                                                      const Batch2Levels* __restrict__ bl, int nlev) {
+  LBSEP_SWEEP2_LDS
+  using S = typename MD::St;
+  const Batch2Entry& e = tab[blk_inst[blockIdx.x]];
+  const long long base = e.t0 + bl->done;  // the members' current level
+  const int pn = bl->prev_n, pn2 = bl->prev2_n;
+  Lv2 lv = e.lv;
+  lv.t1 = base + 1;
+  lv.nlev = nlev;
+  lv.reduce = 1;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    lv.strip[k] = k < pn ? base - pn + 1 + k : -1;
+    lv.glob[k] = k < pn2 ? base - pn - pn2 + 1 + k : -1;
+  }
+  const int c = (e.cur0 + (int)(bl->launches & 1)) & 1;
+  sweep2_block<MD, NT>(*e.kp, *e.kb, lv, static_cast<const S*>(e.f[c]), static_cast<S*>(e.f[c ^ 1]),
+                       (int)blockIdx.x - e.first_block, lds, red, pulled_rows, kv);
+}
+
+__global__ void k_batch2_advance(Batch2Levels* bl, int nlev) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    bl->done += nlev;
+    bl->launches += 1;
+    bl->prev2_n = bl->prev_n;
+    bl->prev_n = nlev;
+  }
 }
 
 __global__ __launch_bounds__(kThreads) void k_finalize(KParams kp, KBufs kb, long long t, long long t_first,
@@ -1846,8 +1947,9 @@ bool validate(const lbsep_params* p, std::string& why) {
     return why = "tile_rows must be 0, 1, 2 or 4", false;
   if (p->fused_steps < 0 || p->fused_steps > 2) return why = "fused_steps must be 0, 1 or 2", false;
   if (p->fused_steps == 2 && (px || py)) return why = "fused_steps = 2 needs an inlet, an outlet and walls", false;
-  if (p->fused_steps == 2 && p->ny > kStripRows)
-    return why = "fused_steps = 2 needs ny <= " + std::to_string(kStripRows), false;
+  if (p->fused_steps == 2 && p->ny > (p->dtype == LBSEP_F64 ? kStripRowsOf<ModeF64> : kStripRowsOf<ModeF32>))
+    return why = std::string("fused_steps = 2 needs ny <= ") +
+                 (p->dtype == LBSEP_F64 ? "64 in FP64" : "128 with deviation storage"), false;
   return true;
 }
 
@@ -2532,6 +2634,9 @@ struct lbsep_batch {
   long long* counter = nullptr;  // device: batch steps taken
   BatchEntry* tab = nullptr;     // device
   int* blk_inst = nullptr;       // device: block -> entry
+  bool two = false;              // members advance two levels per launch (k_sweep2_batch)
+  Batch2Entry* tab2 = nullptr;   // device (two-level members)
+  Batch2Levels* lev2 = nullptr;  // device: progress of the two-level launches
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int64_t graph_steps = 0;
@@ -2542,19 +2647,23 @@ namespace {
 struct BatchLayout {
   size_t counter, tab, blk, total;
   int blocks;
+  bool two;
 };
 
 int batch_layout(lbsep_channel* const* chans, int n, BatchLayout& B) {
   if (!chans || n < 1) return fail(LBSEP_EINVAL, "need at least one channel");
   B.blocks = 0;
+  B.two = chans[0] && chans[0]->L.two;
   for (int i = 0; i < n; ++i) {
     if (!chans[i]) return fail(LBSEP_EINVAL, "channel " + std::to_string(i) + " is NULL");
     for (int k = 0; k < i; ++k)
       if (chans[k] == chans[i]) return fail(LBSEP_EINVAL, "a channel appears twice in the batch");
     if (chans[i]->p.dtype != chans[0]->p.dtype) return fail(LBSEP_EINVAL, "all channels of a batch share one dtype");
     if (chans[i]->stream != chans[0]->stream) return fail(LBSEP_EINVAL, "all channels of a batch share one stream");
-    if (chans[i]->L.two) return fail(LBSEP_EINVAL, "batch members step one level per launch (fused_steps != 2)");
-    const long long nb = (long long)chans[i]->L.lead + 8LL * chans[i]->L.chunk;
+    if (chans[i]->L.two != B.two)
+      return fail(LBSEP_EINVAL, "batch members all advance one level per launch or all two (fused_steps)");
+    const long long nb = B.two ? (long long)chans[i]->L.lead2 + 8LL * chans[i]->L.chunk2
+                               : (long long)chans[i]->L.lead + 8LL * chans[i]->L.chunk;
     if (B.blocks + nb > (1LL << 30)) return fail(LBSEP_EINVAL, "batch grid too large");
     B.blocks += (int)nb;
   }
@@ -2562,7 +2671,7 @@ int batch_layout(lbsep_channel* const* chans, int n, BatchLayout& B) {
   B.counter = off;
   off += 256;
   B.tab = off;
-  off += align_up((size_t)n * sizeof(BatchEntry), 256);
+  off += align_up((size_t)n * std::max(sizeof(BatchEntry), sizeof(Batch2Entry)) + sizeof(Batch2Levels), 256);
   B.blk = off;
   off += align_up((size_t)B.blocks * sizeof(int), 256);
   B.total = off;
@@ -2579,8 +2688,39 @@ void launch_batch(lbsep_batch* b, int k_local) {
                        b->blk_inst, b->counter, k_local);
 }
 
+template <class MD>
+void launch_batch2(lbsep_batch* b, int nlev) {
+  hipLaunchKernelGGL((k_sweep2_batch<MD, true>), dim3(b->total_blocks), dim3(kT2), 0, b->stream, b->tab2,
+                     b->blk_inst, b->lev2, nlev);
+  hipLaunchKernelGGL(k_batch2_advance, dim3(1), dim3(64), 0, b->stream, b->lev2, nlev);
+}
+
+// n levels of a two-level batch: launches of two levels, the last of one if
+// n is odd; the device record of the progress follows each launch.
+void enqueue_batch2_levels(lbsep_batch* b, int64_t n) {
+  for (int64_t left = n; left > 0;) {
+    const int nlev = left >= 2 ? 2 : 1;
+    switch (b->dtype) {
+      case LBSEP_F64:
+        launch_batch2<ModeF64>(b, nlev);
+        break;
+      case LBSEP_F32:
+        launch_batch2<ModeF32>(b, nlev);
+        break;
+      default:
+        launch_batch2<ModeF16>(b, nlev);
+        break;
+    }
+    left -= nlev;
+  }
+}
+
 // n sweeps (k_local = 0 .. n-1 from the current counter), then counter += n.
 void enqueue_batch_steps(lbsep_batch* b, int64_t n) {
+  if (b->two) {
+    enqueue_batch2_levels(b, n);
+    return;
+  }
   for (int64_t k = 0; k < n; ++k) {
     switch (b->dtype) {
       case LBSEP_F64:
@@ -2648,11 +2788,42 @@ int lbsep_batch_create(lbsep_channel* const* chans, int32_t n, void* dev_ws, siz
   b->tab = reinterpret_cast<BatchEntry*>(ws + B.tab);
   b->blk_inst = reinterpret_cast<int*>(ws + B.blk);
   b->total_blocks = B.blocks;
+  b->two = B.two;
+  if (B.two) {
+    b->tab2 = reinterpret_cast<Batch2Entry*>(ws + B.tab);
+    b->lev2 = reinterpret_cast<Batch2Levels*>(ws + B.tab + (size_t)n * sizeof(Batch2Entry));
+    // the two-level pipeline starts with nothing pending: every member's
+    // records are completed first (enqueued before the table copy)
+    for (int i = 0; i < n; ++i)
+      if (int e = finalize(chans[i])) {
+        delete b;
+        return e;
+      }
+  }
   std::vector<BatchEntry> host(n);
+  std::vector<Batch2Entry> host2(B.two ? n : 0);
   std::vector<int> blk(B.blocks);
   size_t node_state = 0;
   int first = 0;
-  for (int i = 0; i < n; ++i) {
+  for (int i = 0; i < n && B.two; ++i) {
+    lbsep_channel* c = chans[i];
+    Batch2Entry& e = host2[i];
+    std::memset(&e, 0, sizeof(e));
+    e.kp = reinterpret_cast<const KParams*>(c->ws + c->L.consts);
+    e.kb = reinterpret_cast<const KBufs*>(c->ws + c->L.consts + align_up(sizeof(KParams), 256));
+    e.f[0] = c->f[0];
+    e.f[1] = c->f[1];
+    e.t0 = c->t;
+    e.cur0 = c->cur;
+    e.first_block = first;
+    e.lv = sweep2_args(c, c->t + 1, 2, 1);  // tiling; the levels are set per launch
+    const int nb = c->L.lead2 + 8 * c->L.chunk2;
+    for (int k = 0; k < nb; ++k) blk[first + k] = i;
+    first += nb;
+    b->ch.push_back(c);
+    b->gen_expect.push_back(c->gen);
+  }
+  for (int i = 0; i < n && !B.two; ++i) {
     lbsep_channel* c = chans[i];
     BatchEntry& e = host[i];
     std::memset(&e, 0, sizeof(e));
@@ -2677,7 +2848,13 @@ int lbsep_batch_create(lbsep_channel* const* chans, int32_t n, void* dev_ws, siz
   b->nt = node_state > (128ull << 20);
   const long long zero = 0;
   int rc = check_hip(hipMemcpyAsync(b->counter, &zero, sizeof(zero), hipMemcpyHostToDevice, b->stream), "batch copy");
-  if (!rc)
+  static const Batch2Levels start{0, 0, 0, 0};
+  if (!rc && B.two)
+    rc = check_hip(hipMemcpyAsync(b->tab2, host2.data(), n * sizeof(Batch2Entry), hipMemcpyHostToDevice, b->stream),
+                   "batch copy");
+  if (!rc && B.two)
+    rc = check_hip(hipMemcpyAsync(b->lev2, &start, sizeof(start), hipMemcpyHostToDevice, b->stream), "batch copy");
+  if (!rc && !B.two)
     rc = check_hip(hipMemcpyAsync(b->tab, host.data(), n * sizeof(BatchEntry), hipMemcpyHostToDevice, b->stream),
                    "batch copy");
   if (!rc)
@@ -2703,19 +2880,41 @@ int lbsep_batch_step(lbsep_batch* b, int64_t nsteps) {
     if (b->ch[i]->gen != b->gen_expect[i])
       return fail(LBSEP_EINVAL, "channel " + std::to_string(i) + " was stepped or reset outside its batch");
   int64_t left = nsteps;
+  std::vector<int64_t> runs;  // level counts of the graph replays and the eager rest, in order
   while (b->exec && left >= b->graph_steps) {
     if (int e = check_hip(hipGraphLaunch(b->exec, b->stream), "batch graph launch")) return e;
     left -= b->graph_steps;
+    runs.push_back(b->graph_steps);
   }
-  if (left > 0) enqueue_batch_steps(b, left);
+  if (left > 0) {
+    enqueue_batch_steps(b, left);
+    runs.push_back(left);
+  }
   for (size_t i = 0; i < b->ch.size(); ++i) {
     lbsep_channel* c = b->ch[i];
-    c->t += nsteps;
-    c->cur = (c->cur + (int)(nsteps & 1)) & 1;
-    if (nsteps > 0) {
-      c->prev_pre = false;
-      c->prev_buf = 1 - c->cur;
-      c->finalized = false;
+    if (b->two) {
+      // the host side of each two-level launch, as in lbsep_step
+      for (int64_t run : runs)
+        for (int64_t n = run; n > 0;) {
+          const int nlev = n >= 2 ? 2 : 1;
+          c->pipe2 = true;
+          c->glob_next = c->strip_next;
+          c->strip_next = c->t + 1;
+          c->prev_buf = nlev == 2 ? -1 : c->cur;
+          c->cur = 1 - c->cur;
+          c->prev_pre = false;
+          c->t += nlev;
+          c->finalized = false;
+          n -= nlev;
+        }
+    } else {
+      c->t += nsteps;
+      c->cur = (c->cur + (int)(nsteps & 1)) & 1;
+      if (nsteps > 0) {
+        c->prev_pre = false;
+        c->prev_buf = 1 - c->cur;
+        c->finalized = false;
+      }
     }
     if (nsteps > 0) ++c->gen;
     b->gen_expect[i] = c->gen;

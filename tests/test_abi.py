@@ -52,7 +52,7 @@ def test_workspace_size_is_positive_and_grows_with_the_grid():
     dict(theta=0.0), dict(kn_out=-1.0), dict(dbb_r=2.0), dict(dbb_r=-0.1), dict(accom=0.0),
     dict(accom=1.5), dict(dtype=7), dict(hist_cap=0), dict(flags=lbsep.PERIODIC_Y),
     dict(flags=lbsep.BGK_TEST, tau_bgk=0.5), dict(flags=0x100), dict(tile_mode=3), dict(tile_rows=3), dict(tile_rows=-1), dict(fused_steps=3), dict(fused_steps=2, flags=lbsep.PERIODIC_X),
-    dict(fused_steps=2, flags=lbsep.PERIODIC_Y | lbsep.PERIODIC_X), dict(fused_steps=2, ny=65), dict(ny=2049),
+    dict(fused_steps=2, flags=lbsep.PERIODIC_Y | lbsep.PERIODIC_X), dict(fused_steps=2, ny=65), dict(fused_steps=2, ny=129, dtype=1), dict(ny=2049),
 ])
 def test_invalid_parameters_are_rejected_on_the_host(bad):
     p = _params(**bad)

@@ -197,3 +197,90 @@ def test_autotuner_picks_a_candidate_and_caches_it(tmp_path):
     lbsep.Batch(plain).step(40)
     for a, b in zip(tuned, plain):
         assert torch.equal(a.get_state(), b.get_state())
+
+
+# two levels per launch: members of at most 128 rows (64 in FP64)
+MEMBERS2 = [
+    Workload("d0", 80, 8, *HE_AR, 0.5, 0.5, 2.0, 0.1, 0),
+    Workload("d1", 333, 24, *NE_AR, 0.3, 0.3, 3.0, 0.05, 0),
+    Workload("d2", 150, 13, *HE_AR, 0.7, 0.4, 2.5, 0.5, 0),
+    Workload("d3", 1000, 100, *HE_AR, 0.5, 0.5, 2.0, 0.2, 0),
+    Workload("d4", 640, 64, *NE_AR, 0.6, 0.6, 1.5, 0.03, 0),
+    Workload("d5", 40, 128, *HE_AR, 0.45, 0.45, 1.5, 0.3, 0),
+]
+
+
+def _make2(ws, dtype, fused, stream=None):
+    out = []
+    for w in ws:
+        p = lbsep.make_params(w.nx, w.ny, w.m_a, w.m_b, w.cl_in, w.cl_out, w.theta, w.kn_out, r_of(w),
+                              dtype=dtype, hist_cap=512, fused_steps=fused)
+        out.append(lbsep.Channel(p, device="cuda:0", stream=stream))
+    return out
+
+
+def _same_states(a, b, what):
+    for k, (x, y) in enumerate(zip(a, b)):
+        assert x.t == y.t, what
+        assert torch.equal(_bits(x.get_state()), _bits(y.get_state())), f"{what}: member {k} state"
+        assert torch.equal(_bits(x.get_post_collision()), _bits(y.get_post_collision())), f"{what}: member {k} post"
+        ca, cb = x.read_cl(profile=True), y.read_cl(profile=True)
+        # column sums are grouped per tile, so CL agrees to rounding
+        assert abs(ca["cl"] - cb["cl"]) <= 1e-12 * abs(ca["cl"]) + 1e-14, f"{what}: member {k} CL"
+        np.testing.assert_allclose(cb["profile"], ca["profile"], rtol=1e-13, atol=0, err_msg=what)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16", "f64"])
+def test_two_level_batch_matches_members_stepped_alone(dtype):
+    """A batch of two-level channels (one launch per two levels, the last of
+    one level when the count is odd) against the same channels stepped alone
+    with one level per launch: bitwise equal states, CL to rounding, with
+    readouts and a reset between batch steps refused."""
+    ws = [w for w in MEMBERS2 if dtype != "f64" or w.ny <= 64]
+    stream = torch.cuda.Stream()
+    batched = _make2(ws, dtype, 2, stream=stream)
+    alone = _make2(ws, dtype, 1)
+    b = lbsep.Batch(batched)
+    total = 0
+    for n in (2, 5, 1, 40):
+        b.step(n)
+        total += n
+        for c in alone:
+            c.step(n)
+        torch.cuda.synchronize()
+        _same_states(batched, alone, f"{dtype}, {total} levels")
+    b.capture(10)
+    for n in (10, 20, 13):  # replays, then an odd rest
+        b.step(n)
+        total += n
+        for c in alone:
+            c.step(n)
+        torch.cuda.synchronize()
+        _same_states(batched, alone, f"{dtype}, graph, {total} levels")
+    t0 = total - 20
+    for x, y in zip(batched, alone):
+        ha, hb = x.read_history(t0, 21), y.read_history(t0, 21)
+        np.testing.assert_array_equal(ha[:, 0], hb[:, 0])
+        np.testing.assert_allclose(ha[:, 1:3], hb[:, 1:3], rtol=1e-11, atol=1e-14)
+    batched[0].step(1)
+    with pytest.raises(lbsep.LbsepError, match="outside its batch"):
+        b.step(2)
+
+
+def test_two_level_batch_of_the_sweep_table_matches_the_one_level_batch():
+    """The 64-member parametric table (every member has at most 128 rows) in
+    FP32: two levels per launch against one, bitwise equal states after 60
+    levels (the members that diverge do so identically)."""
+    ws = batch_instances()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    one = _make2(ws, "f32", 1, stream=s1)
+    two = _make2(ws, "f32", 2, stream=s2)
+    b1, b2 = lbsep.Batch(one), lbsep.Batch(two)
+    b2.capture(20)
+    b1.step(60)
+    b2.step(60)
+    torch.cuda.synchronize()
+    for k, (x, y) in enumerate(zip(one, two)):
+        assert torch.equal(_bits(x.get_state()), _bits(y.get_state())), ws[k].name
+        assert _cl_or_error(x) == pytest.approx(_cl_or_error(y), rel=1e-12, abs=1e-14) \
+            if _cl_or_error(x) != "non-finite" else _cl_or_error(y) == "non-finite"

@@ -66,6 +66,36 @@ def test_two_levels_per_launch_match_single_levels(dtype, shape):
     np.testing.assert_allclose(hb[:, 1:3], ha[:, 1:3], rtol=1e-11, atol=1e-14)
 
 
+# channels of 65 to 128 rows: two end blocks per end in single-level launches,
+# one two-level end block of 512 nodes (deviation storage only)
+TALL = [(200, 100), (90, 128), (150, 65), (9, 127)]
+
+
+@pytest.mark.parametrize("shape", TALL, ids=[f"{s[0]}x{s[1]}" for s in TALL])
+@pytest.mark.parametrize("dtype", ["f32", "f16"])
+def test_two_levels_per_launch_on_channels_up_to_128_rows(dtype, shape):
+    w = Workload("fused_tall", shape[0], shape[1], *HE_AR, 0.4, 0.55, 2.5, 0.1, 0)
+    a, b = _pair(w, dtype)
+    _agree(a, b, "initial state", dtype)
+    for n in (2, 3, 36):
+        a.step(n)
+        b.step(n)
+        _agree(a, b, f"t = {a.t}", dtype)
+    t0 = max(1, a.t - 30)
+    ha, hb = a.read_history(t0, a.t - t0 + 1), b.read_history(t0, b.t - t0 + 1)
+    np.testing.assert_allclose(hb[:, 1:3], ha[:, 1:3], rtol=1e-11, atol=1e-14)
+
+
+def test_two_levels_per_launch_limits():
+    """FP64 end blocks hold at most 64 rows, the deviation modes 128."""
+    w = Workload("fused_lim", 90, 65, *HE_AR, 0.4, 0.4, 2.0, 0.1, 0)
+    with pytest.raises(lbsep.LbsepError, match="64 in FP64"):
+        lbsep.Channel(_params(w, 2, "f64"))
+    with pytest.raises(lbsep.LbsepError, match="128"):
+        lbsep.Channel(_params(w.with_(ny=129), 2, "f32"))
+    lbsep.Channel(_params(w.with_(ny=128), 2, "f32")).step(2)
+
+
 VARIANTS = {
     # the wall function off (constant relaxation times from the mean free path)
     "mfp_off": dict(flags=lbsep.MFP_OFF),
@@ -167,7 +197,7 @@ def test_fp64_two_level_path_against_the_oracle():
     assert_cl(ch.read_cl()["cl"], O.diagnostics(f, p).cl, 0.0, 1e-12)
 
 
-def test_two_level_channels_do_not_join_a_batch():
+def test_one_and_two_level_channels_do_not_share_a_batch():
     w = CONFIGS["he_ar_8x80"]
     a = lbsep.Channel(_params(w, 1, "f32"))
     b = lbsep.Channel(_params(w, 2, "f32"))
