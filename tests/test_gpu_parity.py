@@ -112,6 +112,44 @@ def test_full_size_ne_ar_64x1280(dtype, tol, levels):
     assert abs(cl["cl"] - d.cl) <= (CL64 if dtype == "f64" else tol)
 
 
+def _stored_reference(name):
+    import json
+    import os
+    return json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)))
+
+
+@pytest.mark.parametrize("levels", [1, 2])
+@pytest.mark.parametrize("dtype,tol", [("f64", TOL64), ("f32", TOL32)])
+def test_full_size_ne_ar_64x1280_2000_steps_against_stored_oracle(dtype, tol, levels):
+    """The 64 x 1280 channel after 2000 steps against the oracle's own run of
+    the same length (sampled moments, the whole C_l(x) profile, CL, C~_l;
+    tests/golden/ne_ar_64x1280_2000.json, written by the script beside it from
+    oracle/ alone). Species densities and momenta normwise as everywhere."""
+    ref = _stored_reference("ne_ar_64x1280_2000.json")
+    w = CONFIGS["ne_ar_64x1280"]
+    r = r_of(w)
+    assert r == ref["dbb_r"]
+    print(f"[case] {dtype} {w.name} {ref['steps']} steps against the stored oracle, {levels} level(s)", flush=True)
+    ch = channel(w, r, dtype=dtype, fused_steps=levels)
+    ch.step(ref["steps"])
+    mom = ch.read_moments()
+    cl = ch.read_cl(profile=True)
+    rows, cols = ref["rows"], ref["cols"]
+    got = {k: mom[i][np.ix_(rows, cols)] for i, k in enumerate(("rho_a", "rho_b", "u_ax", "u_ay", "u_bx", "u_by"))}
+    exp = {k: np.array(v) for k, v in ref["moments"].items()}
+    errs = []
+    for rho, ux, uy in (("rho_a", "u_ax", "u_ay"), ("rho_b", "u_bx", "u_by")):
+        scale = np.max(np.abs(exp[rho]))
+        errs.append(np.max(np.abs(got[rho] - exp[rho])) / scale)
+        for u in (ux, uy):
+            errs.append(np.max(np.abs(got[rho] * got[u] - exp[rho] * exp[u])) / scale)
+    assert max(errs) <= tol, errs
+    assert np.max(np.abs(cl["profile"] - np.array(ref["cl_profile"]))) <= (1e-13 if dtype == "f64" else tol)
+    assert abs(cl["cl"] - ref["cl"]) <= (CL64 if dtype == "f64" else tol)
+    assert abs(cl["cl_tilde"] - ref["cl_tilde"]) <= (CL64 if dtype == "f64" else tol)
+    print(f"    moments {max(errs):.2e}, CL {abs(cl['cl'] - ref['cl']):.2e}", flush=True)
+
+
 def _oracle_window(w, r, x0, x1, k):
     """Oracle on the columns [x0, x1) of the full channel after k steps, from a
     window wide enough that its artificial edges cannot reach [x0, x1)."""
