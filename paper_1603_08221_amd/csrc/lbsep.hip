@@ -98,7 +98,7 @@ struct KParams {
   int nx, ny, pitch;
   int nxt, nrt, rpt;    // 64-column reduction strips, row tiles, rows per thread
   int ntx;              // 32-column tile strips
-  int tiles, chunk;     // nxt * nrt, ceil(tiles / 8)
+  int tiles;            // ntx * nrt
   int lead;             // lead blocks (multiple of 8) before the first tile
   int nend;             // blocks per inlet/outlet column (64 rows each)
   long long row;        // elements per row of a state buffer: 18 * pitch
@@ -966,13 +966,12 @@ __device__ __forceinline__ void sweep_block(const KParams& kp, const KBufs& kb,
     return;
   }
   // ---- interior tile --------------------------------------------------------------
-  const int xcd = b & 7;
-  const int k = (b - kp.lead) >> 3;
-  const int lin = xcd * kp.chunk + k;
+  // tiles in grid order, without regard to XCDs: the blocks in flight on all
+  // XCDs then read and write one compact stretch of the state (measured on
+  // 512 x 10240 FP32: 5% faster than giving each XCD a contiguous share)
+  const int lin = b - kp.lead;
   if (lin >= kp.tiles) return;
-  // consecutive tiles of an XCD run down a column strip (small channels: the
-  // strip's rows stay together) or along a row band (large channels: an
-  // XCD's concurrent tiles read and write adjacent blocks of a few rows)
+  // row bands (one lane per node) or column strips (lane pairs)
   int bx, by;
   if (kp.flags & kRowMajorTiles) {
     by = lin / kp.ntx;
@@ -1056,9 +1055,11 @@ __global__ __launch_bounds__(kThreads) void k_sweep(KParams kp, KBufs kb, const 
 }
 
 // A batch of channels swept by one launch: entry i holds channel i's constants,
-// reduction buffers and state buffers; its blocks are the contiguous range
-// [first_block, first_block + lead + 8 chunk) of the batch grid (a multiple of
-// 8 blocks each, so the XCD interleave of the tiles is kept).
+// reduction buffers and state buffers. Block k of the batch grid runs block
+// blk_ref[k].y of the launch of channel blk_ref[k].x alone; the grid lists
+// every member's end blocks first, then every member's reduction blocks, then
+// the members' tiles: the end blocks, the longest, start first rather than
+// stretching the end of the launch.
 struct BatchEntry {
   KParams kp;
   KBufs kb;
@@ -1066,7 +1067,6 @@ struct BatchEntry {
   long long t0;        // channel level when the batch's step counter was 0
   long long t_first;   // first level with a history record
   int cur0;            // buffer holding the post-collision state at counter 0
-  int first_block;
   int split;           // tile kind: lane pair per node (1) or one lane per node (0)
   int pad;
 };
@@ -1074,17 +1074,17 @@ struct BatchEntry {
 // Batch step k = *counter + k_local: every channel advances by one level.
 template <class MD, bool NT>
 __global__ __launch_bounds__(kThreads) void k_sweep_batch(const BatchEntry* __restrict__ tab,
-                                                          const int* __restrict__ blk_inst,
+                                                          const int2* __restrict__ blk_ref,
                                                           const long long* __restrict__ counter, int k_local) {
   __shared__ double red[4][kTY][kTX];
   using S = typename MD::St;
-  const int inst = blk_inst[blockIdx.x];
-  const BatchEntry& e = tab[inst];
+  const int2 ref = blk_ref[blockIdx.x];
+  const BatchEntry& e = tab[ref.x];
   const long long k = *counter + k_local;
   const int c = (e.cur0 + (int)(k & 1)) & 1;
   const S* src = static_cast<const S*>(e.f[c]);
   S* dst = static_cast<S*>(e.f[c ^ 1]);
-  const int b = (int)blockIdx.x - e.first_block;
+  const int b = ref.y;
   if (e.split)
     sweep_block<MD, true, false, true, false>(e.kp, e.kb, src, dst, nullptr, nullptr, nullptr, e.t0 + k + 1,
                                               e.t_first, b, red);
@@ -1658,9 +1658,9 @@ __device__ __forceinline__ void sweep2_block(const KParams& kp, const KBufs& kb,
   constexpr int kRows = kStripRowsOf<MD>;
   double (*redk)[kTY][kTX] = reinterpret_cast<double (*)[kTY][kTX]>(&red[0][0][0]);
   if (b < lv.lead) {
-    // the inlet block is block 0 (XCD 0, with the first column strips), the
-    // outlet block block 7 (XCD 7, with the last ones); the other lead blocks
-    // reduce, in order
+    // the inlet block is block 0 (in a launch of this channel alone on XCD 0,
+    // with the first column strips), the outlet block block 7 (XCD 7, with the
+    // last ones); the other lead blocks reduce, in order
     if (b == 0 || b == 7) {
       if (!(kp.flags & LBSEP_PERIODIC_X))
         end_block2<MD, NT>(kp, kb, lv, src, dst, b == 7, red, redk,
@@ -1711,14 +1711,15 @@ __global__ __launch_bounds__(kT2) void k_sweep2(const KParams* __restrict__ kpp,
 
 // A batch of two-level channels swept by one launch per one or two levels:
 // entry i holds channel i's constants (its workspace copies), state buffers
-// and tiling; its blocks are [first_block, first_block + lead + 8 chunk).
+// and tiling. The grid is ordered as the one-level batch's (blk_ref), with
+// each member's tiles starting at a multiple of 8 blocks, so that its blocks
+// keep the XCDs of a launch of that channel alone.
 struct Batch2Entry {
   const KParams* kp;
   const KBufs* kb;
   void* f[2];         // the channel's two state buffers
   long long t0;       // channel level at the batch's creation (no reduction pending then)
   int cur0;           // buffer holding the post-collision state at creation
-  int first_block;
   Lv2 lv;             // tiling; the levels are set per launch
 };
 
@@ -1736,11 +1737,13 @@ struct Batch2Levels {
 // records (the order of lbsep_step's two-level launches).
 template <class MD, bool NT>
 __global__ __launch_bounds__(kT2) void k_sweep2_batch(const Batch2Entry* __restrict__ tab,
-                                                      const int* __restrict__ blk_inst,
+                                                      const int2* __restrict__ blk_ref,
                                                       const Batch2Levels* __restrict__ bl, int nlev) {
   LBSEP_SWEEP2_LDS
   using S = typename MD::St;
-  const Batch2Entry& e = tab[blk_inst[blockIdx.x]];
+  const int2 ref = blk_ref[blockIdx.x];
+  if (ref.y < 0) return;  // filler before a member's tiles (uniform over the block)
+  const Batch2Entry& e = tab[ref.x];
   const long long base = e.t0 + bl->done;  // the members' current level
   const int pn = bl->prev_n, pn2 = bl->prev2_n;
   Lv2 lv = e.lv;
@@ -1754,7 +1757,7 @@ __global__ __launch_bounds__(kT2) void k_sweep2_batch(const Batch2Entry* __restr
   }
   const int c = (e.cur0 + (int)(bl->launches & 1)) & 1;
   sweep2_block<MD, NT>(*e.kp, *e.kb, lv, static_cast<const S*>(e.f[c]), static_cast<S*>(e.f[c ^ 1]),
-                       (int)blockIdx.x - e.first_block, lds, red, pulled_rows, kv);
+                       ref.y, lds, red, pulled_rows, kv);
 }
 
 __global__ void k_batch2_advance(Batch2Levels* bl, int nlev) {
@@ -1908,7 +1911,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 size_t elem_bytes(int dtype) { return dtype == LBSEP_F64 ? 8 : dtype == LBSEP_F32 ? 4 : 2; }
 
 struct Layout {
-  int pitch, nxt, ntx, nrt, rpt, tiles, chunk, lead, nend;
+  int pitch, nxt, ntx, nrt, rpt, tiles, lead, nend;
   bool split;
   bool big;  // a state buffer exceeds half the last-level cache: row-major tiles, non-temporal stores
   bool two;  // two time levels per launch (k_sweep2)
@@ -1991,9 +1994,8 @@ Layout make_layout(const lbsep_params* p) {
   }
   L.nrt = (p->ny + kTY * L.rpt - 1) / (kTY * L.rpt);
   L.tiles = L.ntx * L.nrt;
-  L.chunk = (L.tiles + 7) / 8;
   L.nend = (p->ny + 63) / 64;
-  L.lead = (int)align_up((size_t)(2 * L.nend + L.nxt + 1), 8);
+  L.lead = 2 * L.nend + L.nxt + 1;
   L.state_buf = align_up(18ull * p->ny * L.pitch * L.elem, 256);
   L.big = !L.split && L.state_buf > (128ull << 20);
   // two levels per launch: tiles own 62 columns x 6 rows of the interior
@@ -2072,7 +2074,7 @@ template <class MD, bool PULL, bool EVAL>
 void launch_sweep(lbsep_channel* h, const void* src, void* dst, double* mom, void* fraw, double* ffull,
                   long long t) {
   using S = typename MD::St;
-  const int grid = h->L.lead + 8 * h->L.chunk;
+  const int grid = h->L.lead + h->L.tiles;
   if (h->L.split)
     hipLaunchKernelGGL((k_sweep<MD, PULL, EVAL, true, false>), dim3(grid), dim3(kThreads), 0, h->stream, h->kp,
                        h->kb, static_cast<const S*>(src), static_cast<S*>(dst), mom, static_cast<S*>(fraw), ffull, t,
@@ -2295,7 +2297,6 @@ int lbsep_init(const lbsep_params* p, void* dev_ws, size_t ws_bytes, void* hip_s
   kp.ntx = L.ntx;
   kp.rpt = L.rpt;
   kp.tiles = L.tiles;
-  kp.chunk = L.chunk;
   kp.lead = L.lead;
   kp.nend = L.nend;
   kp.row = 18LL * L.pitch;
@@ -2422,7 +2423,7 @@ int lbsep_step_record(lbsep_channel* h, double* dev_pre, double* dev_post) {
   if (h->L.two) return fail(LBSEP_EINVAL, "lbsep_step_record needs one level per launch (fused_steps 0 or 1)");
   ++h->gen;
   const int nxt_buf = 1 - h->cur;
-  const int grid = h->L.lead + 8 * h->L.chunk;
+  const int grid = h->L.lead + h->L.tiles;
   const double* src = static_cast<const double*>(h->f[h->cur]);
   double* dst = static_cast<double*>(h->f[nxt_buf]);
   // the recording variant: ffull <- pulled populations, fraw <- post-collision
@@ -2633,7 +2634,7 @@ struct lbsep_batch {
   int total_blocks = 0;
   long long* counter = nullptr;  // device: batch steps taken
   BatchEntry* tab = nullptr;     // device
-  int* blk_inst = nullptr;       // device: block -> entry
+  int2* blk_ref = nullptr;       // device: block -> (entry, block of that entry's launch)
   bool two = false;              // members advance two levels per launch (k_sweep2_batch)
   Batch2Entry* tab2 = nullptr;   // device (two-level members)
   Batch2Levels* lev2 = nullptr;  // device: progress of the two-level launches
@@ -2650,6 +2651,46 @@ struct BatchLayout {
   bool two;
 };
 
+// The batch grid (see BatchEntry): every member's end blocks, then every
+// member's reduction blocks, then each member's tiles; with two levels per
+// launch (end blocks 0 and 7 of a member's lead) each member's tiles start at
+// a multiple of 8. Returns the number of blocks; fills refs if not NULL.
+long long batch_grid(lbsep_channel* const* chans, int n, bool two, std::vector<int2>* refs) {
+  long long k = 0;
+  auto put = [&](int i, int b) {
+    if (refs) (*refs)[k] = make_int2(i, b);
+    ++k;
+  };
+  for (int i = 0; i < n; ++i) {
+    const Layout& L = chans[i]->L;
+    if (two) {
+      put(i, 0);
+      put(i, 7);
+    } else {
+      for (int b = 0; b < 2 * L.nend; ++b) put(i, b);
+    }
+  }
+  for (int i = 0; i < n; ++i) {
+    const Layout& L = chans[i]->L;
+    if (two) {
+      for (int b = 1; b < L.lead2; ++b)
+        if (b != 7) put(i, b);
+    } else {
+      for (int b = 2 * L.nend; b < L.lead; ++b) put(i, b);
+    }
+  }
+  for (int i = 0; i < n; ++i) {
+    const Layout& L = chans[i]->L;
+    if (two) {
+      while (k & 7) put(i, -1);  // filler block
+      for (int b = 0; b < 8 * L.chunk2; ++b) put(i, L.lead2 + b);
+    } else {
+      for (int b = 0; b < L.tiles; ++b) put(i, L.lead + b);
+    }
+  }
+  return k;
+}
+
 int batch_layout(lbsep_channel* const* chans, int n, BatchLayout& B) {
   if (!chans || n < 1) return fail(LBSEP_EINVAL, "need at least one channel");
   B.blocks = 0;
@@ -2662,18 +2703,17 @@ int batch_layout(lbsep_channel* const* chans, int n, BatchLayout& B) {
     if (chans[i]->stream != chans[0]->stream) return fail(LBSEP_EINVAL, "all channels of a batch share one stream");
     if (chans[i]->L.two != B.two)
       return fail(LBSEP_EINVAL, "batch members all advance one level per launch or all two (fused_steps)");
-    const long long nb = B.two ? (long long)chans[i]->L.lead2 + 8LL * chans[i]->L.chunk2
-                               : (long long)chans[i]->L.lead + 8LL * chans[i]->L.chunk;
-    if (B.blocks + nb > (1LL << 30)) return fail(LBSEP_EINVAL, "batch grid too large");
-    B.blocks += (int)nb;
   }
+  const long long nb = batch_grid(chans, n, B.two, nullptr);
+  if (nb > (1LL << 30)) return fail(LBSEP_EINVAL, "batch grid too large");
+  B.blocks = (int)nb;
   size_t off = 0;
   B.counter = off;
   off += 256;
   B.tab = off;
   off += align_up((size_t)n * std::max(sizeof(BatchEntry), sizeof(Batch2Entry)) + sizeof(Batch2Levels), 256);
   B.blk = off;
-  off += align_up((size_t)B.blocks * sizeof(int), 256);
+  off += align_up((size_t)B.blocks * sizeof(int2), 256);
   B.total = off;
   return LBSEP_OK;
 }
@@ -2682,16 +2722,16 @@ template <class MD>
 void launch_batch(lbsep_batch* b, int k_local) {
   if (b->nt)
     hipLaunchKernelGGL((k_sweep_batch<MD, true>), dim3(b->total_blocks), dim3(kThreads), 0, b->stream, b->tab,
-                       b->blk_inst, b->counter, k_local);
+                       b->blk_ref, b->counter, k_local);
   else
     hipLaunchKernelGGL((k_sweep_batch<MD, false>), dim3(b->total_blocks), dim3(kThreads), 0, b->stream, b->tab,
-                       b->blk_inst, b->counter, k_local);
+                       b->blk_ref, b->counter, k_local);
 }
 
 template <class MD>
 void launch_batch2(lbsep_batch* b, int nlev) {
   hipLaunchKernelGGL((k_sweep2_batch<MD, true>), dim3(b->total_blocks), dim3(kT2), 0, b->stream, b->tab2,
-                     b->blk_inst, b->lev2, nlev);
+                     b->blk_ref, b->lev2, nlev);
   hipLaunchKernelGGL(k_batch2_advance, dim3(1), dim3(64), 0, b->stream, b->lev2, nlev);
 }
 
@@ -2786,7 +2826,7 @@ int lbsep_batch_create(lbsep_channel* const* chans, int32_t n, void* dev_ws, siz
   b->dtype = chans[0]->p.dtype;
   b->counter = reinterpret_cast<long long*>(ws + B.counter);
   b->tab = reinterpret_cast<BatchEntry*>(ws + B.tab);
-  b->blk_inst = reinterpret_cast<int*>(ws + B.blk);
+  b->blk_ref = reinterpret_cast<int2*>(ws + B.blk);
   b->total_blocks = B.blocks;
   b->two = B.two;
   if (B.two) {
@@ -2802,9 +2842,9 @@ int lbsep_batch_create(lbsep_channel* const* chans, int32_t n, void* dev_ws, siz
   }
   std::vector<BatchEntry> host(n);
   std::vector<Batch2Entry> host2(B.two ? n : 0);
-  std::vector<int> blk(B.blocks);
+  std::vector<int2> blk(B.blocks);
+  batch_grid(chans, n, B.two, &blk);
   size_t node_state = 0;
-  int first = 0;
   for (int i = 0; i < n && B.two; ++i) {
     lbsep_channel* c = chans[i];
     Batch2Entry& e = host2[i];
@@ -2815,11 +2855,7 @@ int lbsep_batch_create(lbsep_channel* const* chans, int32_t n, void* dev_ws, siz
     e.f[1] = c->f[1];
     e.t0 = c->t;
     e.cur0 = c->cur;
-    e.first_block = first;
     e.lv = sweep2_args(c, c->t + 1, 2, 1);  // tiling; the levels are set per launch
-    const int nb = c->L.lead2 + 8 * c->L.chunk2;
-    for (int k = 0; k < nb; ++k) blk[first + k] = i;
-    first += nb;
     b->ch.push_back(c);
     b->gen_expect.push_back(c->gen);
   }
@@ -2834,11 +2870,7 @@ int lbsep_batch_create(lbsep_channel* const* chans, int32_t n, void* dev_ws, siz
     e.t0 = c->t;
     e.t_first = c->t_first;
     e.cur0 = c->cur;
-    e.first_block = first;
     e.split = c->L.split ? 1 : 0;
-    const int nb = c->L.lead + 8 * c->L.chunk;
-    for (int k = 0; k < nb; ++k) blk[first + k] = i;
-    first += nb;
     if (!c->L.split) node_state += c->L.state_buf;
     b->ch.push_back(c);
     b->gen_expect.push_back(c->gen);
@@ -2858,7 +2890,7 @@ int lbsep_batch_create(lbsep_channel* const* chans, int32_t n, void* dev_ws, siz
     rc = check_hip(hipMemcpyAsync(b->tab, host.data(), n * sizeof(BatchEntry), hipMemcpyHostToDevice, b->stream),
                    "batch copy");
   if (!rc)
-    rc = check_hip(hipMemcpyAsync(b->blk_inst, blk.data(), blk.size() * sizeof(int), hipMemcpyHostToDevice,
+    rc = check_hip(hipMemcpyAsync(b->blk_ref, blk.data(), blk.size() * sizeof(int2), hipMemcpyHostToDevice,
                                   b->stream),
                    "batch copy");
   if (!rc) rc = check_hip(hipStreamSynchronize(b->stream), "batch copy");
