@@ -734,82 +734,80 @@ __device__ __forceinline__ void process_pair(const KParams& kp, int x, int j, lo
 // partials (the inlet/outlet columns come from their own blocks), store them,
 // and reduce the strip to (min C_l, its column, sum (C_l - C_in), bad flag).
 // par: the level's slot in the reduction buffers; nrt, stride: row tiles and
-// slot size of the partials. Run by 256 threads (tid = 0..255) with their own
-// red; with valid == false they only meet the barrier.
-__device__ __forceinline__ void strip_reduce(const KParams& kp, const KBufs& kb, int bx, long long step, int par, int nrt,
-                             long long stride, double (*red)[kTY][kTX], int tid, bool valid,
-                             bool store_cols = true) {
-  const int tx = tid & (kTX - 1);
-  const int q = tid / kTX;  // which sum
-  const int x = bx * kTX + tx;
+// slot size of the partials. Run by one wavefront (lane = column), which keeps
+// the four sums of its column: each is added in row-tile order.
+__device__ __forceinline__ void strip_reduce(const KParams& kp, const KBufs& kb, int bx, long long step, int par,
+                                             int nrt, long long stride, bool store_cols = true) {
+  const int lane = threadIdx.x & (kTX - 1);
+  const int x = bx * kTX + lane;
   const bool px = kp.flags & LBSEP_PERIODIC_X;
-  double v = 0.0;
-  if (valid && x < kp.nx) {
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  if (x < kp.nx) {
     if (!px && (x == 0 || x == kp.nx - 1)) {
-      const int e = x == 0 ? 0 : 1;
-      const double* p = kb.endsum + (par * 2 + e) * kMaxEnd * 4 + q;
-      for (int b0 = 0; b0 < kp.nend; b0 += 8) {
-        double w[8];
+      const double* p = kb.endsum + (par * 2 + (x == 0 ? 0 : 1)) * kMaxEnd * 4;
+      for (int b = 0; b < kp.nend; ++b) {
 #pragma unroll
-        for (int k = 0; k < 8; ++k) w[k] = b0 + k < kp.nend ? p[(b0 + k) * 4] : 0.0;
-#pragma unroll
-        for (int k = 0; k < 8; ++k)
-          if (b0 + k < kp.nend) v += w[k];
+        for (int q = 0; q < 4; ++q) v[q] += p[b * 4 + q];
       }
     } else {
-      // loads issued 16 at a time (the partials were just written by other
-      // XCDs, so each one is a trip past this XCD's L2); the additions keep
-      // their sequential order
-      const double* p = kb.partials + par * stride + (long long)q * nrt * kp.pitch + x;
-      for (int b0 = 0; b0 < nrt; b0 += 16) {
-        double w[16];
+      // loads issued 32 at a time (the partials were just written by other
+      // XCDs, so each one is a trip past this XCD's L2)
+      const double* p = kb.partials + par * stride + x;
+      for (int b0 = 0; b0 < nrt; b0 += 8) {
+        double w[4][8];
 #pragma unroll
-        for (int k = 0; k < 16; ++k) w[k] = b0 + k < nrt ? p[(long long)(b0 + k) * kp.pitch] : 0.0;
+        for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int k = 0; k < 16; ++k)
-          if (b0 + k < nrt) v += w[k];
+          for (int k = 0; k < 8; ++k) w[q][k] = b0 + k < nrt ? p[((long long)q * nrt + b0 + k) * kp.pitch] : 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int k = 0; k < 8; ++k)
+            if (b0 + k < nrt) v[q] += w[q][k];
       }
     }
-    if (store_cols) kb.colsum[(long long)q * kp.pitch + x] = v;
+    if (store_cols) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) kb.colsum[(long long)q * kp.pitch + x] = v[q];
+    }
   }
-  red[q][0][tx] = v;
-  __syncthreads();
-  if (valid && q == 0) {
-    double cl = 1e300, dev = 0.0, arg = 1e300;
-    double bad = 0.0;
-    if (x < kp.nx) {
-      const double na = red[0][0][tx], nb = red[1][0][tx];
-      cl = na / (na + nb);
-      dev = cl - kp.cl_in;
-      arg = double(x);
-      const bool ok = (na > 0.0) && (nb > 0.0) && isfinite(na + nb) && isfinite(red[2][0][tx]) &&
-                      isfinite(red[3][0][tx]);
-      bad = ok ? 0.0 : 1.0;
-      if (!ok) cl = -1e300;  // keep a bad column visible in the minimum
-    }
-    // wavefront tree reductions: min (ties -> smaller x), sum, max
+  double cl = 1e300, dev = 0.0, arg = 1e300;
+  double bad = 0.0;
+  if (x < kp.nx) {
+    const double na = v[0], nb = v[1];
+    cl = na / (na + nb);
+    dev = cl - kp.cl_in;
+    arg = double(x);
+    const bool ok = (na > 0.0) && (nb > 0.0) && isfinite(na + nb) && isfinite(v[2]) && isfinite(v[3]);
+    bad = ok ? 0.0 : 1.0;
+    if (!ok) cl = -1e300;  // keep a bad column visible in the minimum
+  }
+  // wavefront tree reductions: min (ties -> smaller x), sum, max
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-      const double ocl = lane_xor(cl, off);
-      const double oarg = lane_xor(arg, off);
-      const double odev = lane_xor(dev, off);
-      const double obad = lane_xor(bad, off);
-      if (ocl < cl || (ocl == cl && oarg < arg)) {
-        cl = ocl;
-        arg = oarg;
-      }
-      dev += odev;
-      bad = fmax(bad, obad);
+  for (int off = 32; off >= 1; off >>= 1) {
+    const double ocl = lane_xor(cl, off);
+    const double oarg = lane_xor(arg, off);
+    const double odev = lane_xor(dev, off);
+    const double obad = lane_xor(bad, off);
+    if (ocl < cl || (ocl == cl && oarg < arg)) {
+      cl = ocl;
+      arg = oarg;
     }
-    if (tx == 0) {
-      double* st = kb.strip + ((long long)par * kp.nxt + bx) * 4;
-      st[0] = cl;
-      st[1] = arg;
-      st[2] = dev;
-      st[3] = bad;
-    }
+    dev += odev;
+    bad = fmax(bad, obad);
+  }
+  if (lane == 0) {
+    double* st = kb.strip + ((long long)par * kp.nxt + bx) * 4;
+    st[0] = cl;
+    st[1] = arg;
+    st[2] = dev;
+    st[3] = bad;
   }
 }
+
+// Strip-reduction blocks of a launch: each wavefront of a block reduces one
+// strip.
+__host__ __device__ constexpr int strip_blocks(int nxt, int waves) { return (nxt + waves - 1) / waves; }
 
 // Record of level `step` from its strip results (slot par): CL (Eq. (CL)),
 // C~_l (Eq. (Clline)) and the column of the smallest C_l. One wavefront.
@@ -885,9 +883,12 @@ __device__ __forceinline__ void sweep_block(const KParams& kp, const KBufs& kb,
       // ---- pipelined reductions of the two previous levels --------------------
       if (EVAL) return;
       const int r = b - 2 * kp.nend;
-      if (r < kp.nxt) {
-        if (t - 1 >= t_first) strip_reduce(kp, kb, r, t - 1, int((t - 1) & 1), kp.nrt, kb.part_stride, red, threadIdx.x, true);
-      } else if (r == kp.nxt) {
+      const int nsb = strip_blocks(kp.nxt, kTY);
+      if (r < nsb) {
+        const int bx = r * kTY + int(threadIdx.x / kTX);
+        if (bx < kp.nxt && t - 1 >= t_first)
+          strip_reduce(kp, kb, bx, t - 1, int((t - 1) & 1), kp.nrt, kb.part_stride);
+      } else if (r == nsb) {
         if (t - 2 >= t_first && threadIdx.x < kTX) global_reduce(kp, kb, t - 2, int((t - 2) & 1));
       }
       return;
@@ -1668,16 +1669,16 @@ __device__ __forceinline__ void sweep2_block(const KParams& kp, const KBufs& kb,
       return;
     }
     const int r = b < 7 ? b - 1 : b - 2;
-    if (r < kp.nxt) {
-      // strip reductions in two 256-thread groups, task = (level, strip)
-      const int g = threadIdx.x / kThreads;
-      const int task = 2 * r + g;
+    constexpr int kWaves = kT2 / kTX;
+    const int nsb = strip_blocks(2 * kp.nxt, kWaves);
+    if (r < nsb) {
+      // strip reductions, one wavefront per task = (level, strip)
+      const int task = r * kWaves + int(threadIdx.x / kTX);
       const int li = task / kp.nxt, bx = task - li * kp.nxt;
       const long long level = li < 2 ? lv.strip[li] : -1;
       const bool last = li == 1 || lv.strip[1] < 0;  // the latest level keeps the column sums
-      strip_reduce(kp, kb, bx, level, int(level & 3), lv.nrt, lv.part_stride, redk + 4 * g,
-                   threadIdx.x & (kThreads - 1), level >= 0, last);
-    } else if (r == kp.nxt) {
+      if (level >= 0) strip_reduce(kp, kb, bx, level, int(level & 3), lv.nrt, lv.part_stride, last);
+    } else if (r == nsb) {
       // the records of up to two levels by one wavefront, in level order: a
       // history ring of one slot keeps the later one
       if (threadIdx.x < kTX)
@@ -1771,12 +1772,12 @@ __global__ void k_batch2_advance(Batch2Levels* bl, int nlev) {
 
 __global__ __launch_bounds__(kThreads) void k_finalize(KParams kp, KBufs kb, long long t, long long t_first,
                                                        int phase) {
-  __shared__ double red[4][kTY][kTX];
   const int b = blockIdx.x;
   if (phase == 0) {
-    if (b < kp.nxt)
-      strip_reduce(kp, kb, b, t, int(t & 1), kp.nrt, kb.part_stride, red, threadIdx.x, true);
-    else if (t - 1 >= t_first && threadIdx.x < kTX)
+    if (b < strip_blocks(kp.nxt, kTY)) {
+      const int bx = b * kTY + int(threadIdx.x / kTX);
+      if (bx < kp.nxt) strip_reduce(kp, kb, bx, t, int(t & 1), kp.nrt, kb.part_stride);
+    } else if (t - 1 >= t_first && threadIdx.x < kTX)
       global_reduce(kp, kb, t - 1, int((t - 1) & 1));
   } else if (threadIdx.x < kTX) {
     global_reduce(kp, kb, t, int(t & 1));
@@ -1995,7 +1996,7 @@ Layout make_layout(const lbsep_params* p) {
   L.nrt = (p->ny + kTY * L.rpt - 1) / (kTY * L.rpt);
   L.tiles = L.ntx * L.nrt;
   L.nend = (p->ny + 63) / 64;
-  L.lead = 2 * L.nend + L.nxt + 1;
+  L.lead = 2 * L.nend + strip_blocks(L.nxt, kTY) + 1;
   L.state_buf = align_up(18ull * p->ny * L.pitch * L.elem, 256);
   L.big = !L.split && L.state_buf > (128ull << 20);
   // two levels per launch: tiles own 62 columns x 6 rows of the interior
@@ -2005,7 +2006,7 @@ Layout make_layout(const lbsep_params* p) {
   L.nrt2 = (p->ny + kR2 - 1) / kR2;
   L.tiles2 = L.ntx2 * L.nrt2;
   L.chunk2 = (L.tiles2 + 7) / 8;
-  L.lead2 = (int)align_up((size_t)(2 + L.nxt + 1), 8);
+  L.lead2 = (int)align_up((size_t)(2 + strip_blocks(2 * L.nxt, kT2 / kTX) + 1), 8);
   size_t off = 0;
   L.f0 = off;
   off += L.state_buf;
@@ -2195,7 +2196,7 @@ int finalize(lbsep_channel* h) {
     launch_sweep2(h, lv, nullptr, nullptr);
     h->glob_next = h->strip_next;
   } else {
-    hipLaunchKernelGGL(k_finalize, dim3(h->L.nxt + 1), dim3(kThreads), 0, h->stream, h->kp, h->kb,
+    hipLaunchKernelGGL(k_finalize, dim3(strip_blocks(h->L.nxt, kTY) + 1), dim3(kThreads), 0, h->stream, h->kp, h->kb,
                        (long long)h->t, (long long)h->t_first, 0);
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, h->stream, h->kp, h->kb, (long long)h->t,
                        (long long)h->t_first, 1);
