@@ -172,6 +172,9 @@ int lbsep_read_cl(lbsep_channel* ch, double* cl, double* cl_tilde, int32_t* x_mi
 
 /* Column sums of the current state, host [4][nx]: sum_j n_a, sum_j n_b,
  * sum_j rho_a u_ax, sum_j rho_b u_bx (species velocity of Eq. (rhou)).
+ * The density sums are those behind the CL record; one-level steps carry no
+ * momentum sums, so for a channel last advanced by one-level launches these
+ * come from an extra evaluation sweep of the current state (no store).
  * Synchronises. */
 int lbsep_read_column_sums(lbsep_channel* ch, double* host);
 

@@ -558,6 +558,8 @@ __device__ __forceinline__ NodeState<typename MD::Ct> node_moments(const KParams
         ffull[(9 + i) * n + o] = double(fb[i]) + (MD::kDev ? kp.wa[1][i] * r0b : 0.0);
       }
     }
+    acc[2] += double(pxa);  // the momentum sums, as a step adds them
+    acc[3] += double(pxb);
     return st;
   }
   acc[0] += ra_d * kp.rc.inv_m[0];
@@ -705,6 +707,7 @@ __device__ __forceinline__ void process_pair(const KParams& kp, int x, int j, lo
 #pragma unroll
       for (int i = 0; i < 9; ++i) ffull[(9 * s + i) * n + o] = double(f[i]) + (MD::kDev ? kp.wa[s][i] * r0 : 0.0);
     }
+    acc[1] += double(px);  // the momentum sum, as a step adds it
     return;
   }
   C we, weps;
@@ -734,10 +737,11 @@ __device__ __forceinline__ void process_pair(const KParams& kp, int x, int j, lo
 // partials (the inlet/outlet columns come from their own blocks), store them,
 // and reduce the strip to (min C_l, its column, sum (C_l - C_in), bad flag).
 // par: the level's slot in the reduction buffers; nrt, stride: row tiles and
-// slot size of the partials. Run by one wavefront (lane = column), which keeps
-// the four sums of its column: each is added in row-tile order.
+// slot size of the partials; nq: the sums carried (2: the densities, as
+// one-level launches write; 4: also the momenta). Run by one wavefront (lane =
+// column), which keeps the sums of its column: each is added in row-tile order.
 __device__ __forceinline__ void strip_reduce(const KParams& kp, const KBufs& kb, int bx, long long step, int par,
-                                             int nrt, long long stride, bool store_cols = true) {
+                                             int nrt, long long stride, int nq, bool store_cols = true) {
   const int lane = threadIdx.x & (kTX - 1);
   const int x = bx * kTX + lane;
   const bool px = kp.flags & LBSEP_PERIODIC_X;
@@ -747,28 +751,31 @@ __device__ __forceinline__ void strip_reduce(const KParams& kp, const KBufs& kb,
       const double* p = kb.endsum + (par * 2 + (x == 0 ? 0 : 1)) * kMaxEnd * 4;
       for (int b = 0; b < kp.nend; ++b) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) v[q] += p[b * 4 + q];
+        for (int q = 0; q < 4; ++q)
+          if (q < nq) v[q] += p[b * 4 + q];
       }
     } else {
-      // loads issued 32 at a time (the partials were just written by other
-      // XCDs, so each one is a trip past this XCD's L2)
+      // loads issued up to 32 at a time (the partials were just written by
+      // other XCDs, so each one is a trip past this XCD's L2)
       const double* p = kb.partials + par * stride + x;
       for (int b0 = 0; b0 < nrt; b0 += 8) {
         double w[4][8];
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
-          for (int k = 0; k < 8; ++k) w[q][k] = b0 + k < nrt ? p[((long long)q * nrt + b0 + k) * kp.pitch] : 0.0;
+          for (int k = 0; k < 8; ++k)
+            w[q][k] = q < nq && b0 + k < nrt ? p[((long long)q * nrt + b0 + k) * kp.pitch] : 0.0;
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
           for (int k = 0; k < 8; ++k)
-            if (b0 + k < nrt) v[q] += w[q][k];
+            if (q < nq && b0 + k < nrt) v[q] += w[q][k];
       }
     }
     if (store_cols) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) kb.colsum[(long long)q * kp.pitch + x] = v[q];
+      for (int q = 0; q < 4; ++q)
+        if (q < nq) kb.colsum[(long long)q * kp.pitch + x] = v[q];
     }
   }
   double cl = 1e300, dev = 0.0, arg = 1e300;
@@ -778,7 +785,7 @@ __device__ __forceinline__ void strip_reduce(const KParams& kp, const KBufs& kb,
     cl = na / (na + nb);
     dev = cl - kp.cl_in;
     arg = double(x);
-    const bool ok = (na > 0.0) && (nb > 0.0) && isfinite(na + nb) && isfinite(v[2]) && isfinite(v[3]);
+    const bool ok = (na > 0.0) && (nb > 0.0) && isfinite(na + nb);
     bad = ok ? 0.0 : 1.0;
     if (!ok) cl = -1e300;  // keep a bad column visible in the minimum
   }
@@ -808,6 +815,30 @@ __device__ __forceinline__ void strip_reduce(const KParams& kp, const KBufs& kb,
 // Strip-reduction blocks of a launch: each wavefront of a block reduces one
 // strip.
 __host__ __device__ constexpr int strip_blocks(int nxt, int waves) { return (nxt + waves - 1) / waves; }
+
+// The momentum column sums (quantities 2, 3) of one strip from the partials
+// of slot par (written by an evaluation sweep), added in row-tile order and
+// stored to colsum. One wavefront (lane = column).
+__device__ __forceinline__ void jsum_reduce(const KParams& kp, const KBufs& kb, int bx, int par) {
+  const int x = bx * kTX + int(threadIdx.x & (kTX - 1));
+  if (x >= kp.nx) return;
+  double v[2] = {0.0, 0.0};
+  if (!(kp.flags & LBSEP_PERIODIC_X) && (x == 0 || x == kp.nx - 1)) {
+    const double* p = kb.endsum + (par * 2 + (x == 0 ? 0 : 1)) * kMaxEnd * 4;
+    for (int b = 0; b < kp.nend; ++b) {
+      v[0] += p[b * 4 + 2];
+      v[1] += p[b * 4 + 3];
+    }
+  } else {
+    const double* p = kb.partials + par * kb.part_stride + x;
+    for (int b = 0; b < kp.nrt; ++b) {
+      v[0] += p[((long long)2 * kp.nrt + b) * kp.pitch];
+      v[1] += p[((long long)3 * kp.nrt + b) * kp.pitch];
+    }
+  }
+  kb.colsum[2LL * kp.pitch + x] = v[0];
+  kb.colsum[3LL * kp.pitch + x] = v[1];
+}
 
 // Record of level `step` from its strip results (slot par): CL (Eq. (CL)),
 // C~_l (Eq. (Clline)) and the column of the smallest C_l. One wavefront.
@@ -869,13 +900,15 @@ __device__ __forceinline__ void block_sum(double (*red)[kTY][kTX], const double*
 }
 
 // One block of the fused sweep of a channel, block index b of the channel's
-// own grid (lead blocks, then XCD-interleaved tiles).
+// own grid (lead blocks, then the tiles). jsums (with EVAL): the momentum
+// column sums of level t, which steps do not carry, go to the partials of the
+// other reduction slot ((t + 1) & 1, free once level t is finalized).
 template <class MD, bool PULL, bool EVAL, bool SPLIT, bool NT, bool REC = false>
 __device__ __forceinline__ void sweep_block(const KParams& kp, const KBufs& kb,
                                             const typename MD::St* __restrict__ src, typename MD::St* __restrict__ dst,
                                             double* __restrict__ mom, typename MD::St* __restrict__ fraw,
                                             double* __restrict__ ffull, long long t, long long t_first, int b,
-                                            double (*red)[kTY][kTX]) {
+                                            double (*red)[kTY][kTX], bool jsums = false) {
   using C = typename MD::Ct;
   const bool px = kp.flags & LBSEP_PERIODIC_X;
   if (b < kp.lead) {
@@ -887,7 +920,7 @@ __device__ __forceinline__ void sweep_block(const KParams& kp, const KBufs& kb,
       if (r < nsb) {
         const int bx = r * kTY + int(threadIdx.x / kTX);
         if (bx < kp.nxt && t - 1 >= t_first)
-          strip_reduce(kp, kb, bx, t - 1, int((t - 1) & 1), kp.nrt, kb.part_stride);
+          strip_reduce(kp, kb, bx, t - 1, int((t - 1) & 1), kp.nrt, kb.part_stride, 2);
       } else if (r == nsb) {
         if (t - 2 >= t_first && threadIdx.x < kTX) global_reduce(kp, kb, t - 2, int((t - 2) & 1));
       }
@@ -960,10 +993,12 @@ __device__ __forceinline__ void sweep_block(const KParams& kp, const KBufs& kb,
     double acc2[2] = {0.0, 0.0};
     process_pair<MD, EVAL, 2, true, false, REC>(kp, col, j, t, s, active && layer == 0, f, dst, mom, fraw, ffull, acc2,
                                                 reinterpret_cast<double*>(fraw));
-    if (EVAL) return;
+    if (EVAL && !jsums) return;
     const double acc[4] = {s ? 0.0 : acc2[0], s ? acc2[0] : 0.0, s ? 0.0 : acc2[1], s ? acc2[1] : 0.0};
     block_sum(red, acc, 4);
-    if (threadIdx.x < 4) kb.endsum[(((t & 1) * 2 + e) * kMaxEnd + blk) * 4 + threadIdx.x] = red[threadIdx.x][0][0];
+    // a step: all four sums of level t; an evaluation sweep: the momenta, to the other slot
+    if (threadIdx.x < 4 && (!EVAL || threadIdx.x >= 2))
+      kb.endsum[((((EVAL ? t + 1 : t) & 1) * 2 + e) * kMaxEnd + blk) * 4 + threadIdx.x] = red[threadIdx.x][0][0];
     return;
   }
   // ---- interior tile --------------------------------------------------------------
@@ -1002,17 +1037,18 @@ __device__ __forceinline__ void sweep_block(const KParams& kp, const KBufs& kb,
                                                      reinterpret_cast<double*>(fraw));
       }
     }
-    if (EVAL) return;
-    // per-column sums of this row tile: quantity q = s (n_s) and 2 + s (rho_s u_sx)
+    if (EVAL && !jsums) return;
+    // per-column sums of this row tile: quantity q = s (n_s) and 2 + s
+    // (rho_s u_sx); the densities in a step, the momenta in an evaluation sweep
     red[s][ty][cx] = acc[0];
     red[2 + s][ty][cx] = acc[1];
     __syncthreads();
-    if (threadIdx.x < 128) {
-      const int q = threadIdx.x >> 5, c = threadIdx.x & 31;
+    if (threadIdx.x < 64) {
+      const int q = (threadIdx.x >> 5) + (EVAL ? 2 : 0), c = threadIdx.x & 31;
       const int xc = bx * 32 + c;
       if (xc < kp.nx) {
         const double v = ((red[q][0][c] + red[q][1][c]) + red[q][2][c]) + red[q][3][c];
-        kb.partials[(t & 1) * kb.part_stride + ((long long)q * kp.nrt + by) * kp.pitch + xc] = v;
+        kb.partials[((EVAL ? t + 1 : t) & 1) * kb.part_stride + ((long long)q * kp.nrt + by) * kp.pitch + xc] = v;
       }
     }
   } else {
@@ -1030,14 +1066,15 @@ __device__ __forceinline__ void sweep_block(const KParams& kp, const KBufs& kb,
                                         reinterpret_cast<double*>(fraw));
       }
     }
-    if (EVAL) return;
-    // per-column sums of this row tile (4 wavefronts -> 1), quantity q = ty
+    if (EVAL && !jsums) return;
+    // per-column sums of this row tile (4 wavefronts -> 1), quantity q = ty:
+    // the densities in a step, the momenta in an evaluation sweep
 #pragma unroll
     for (int q = 0; q < 4; ++q) red[q][ty][lane] = acc[q];
     __syncthreads();
-    if (x < kp.nx) {
+    if (x < kp.nx && (ty >= 2) == EVAL) {
       const double v = ((red[ty][0][lane] + red[ty][1][lane]) + red[ty][2][lane]) + red[ty][3][lane];
-      kb.partials[(t & 1) * kb.part_stride + ((long long)ty * kp.nrt + by) * kp.pitch + x] = v;
+      kb.partials[((EVAL ? t + 1 : t) & 1) * kb.part_stride + ((long long)ty * kp.nrt + by) * kp.pitch + x] = v;
     }
   }
 }
@@ -1050,9 +1087,10 @@ __global__ __launch_bounds__(kThreads) void k_sweep(KParams kp, KBufs kb, const 
                                                     typename MD::St* __restrict__ dst, double* __restrict__ mom,
                                                     typename MD::St* __restrict__ fraw,
                                                     double* __restrict__ ffull, long long t,
-                                                    long long t_first) {
+                                                    long long t_first, int jsums) {
   __shared__ double red[4][kTY][kTX];
-  sweep_block<MD, PULL, EVAL, SPLIT, NT, REC>(kp, kb, src, dst, mom, fraw, ffull, t, t_first, (int)blockIdx.x, red);
+  sweep_block<MD, PULL, EVAL, SPLIT, NT, REC>(kp, kb, src, dst, mom, fraw, ffull, t, t_first, (int)blockIdx.x, red,
+                                              jsums != 0);
 }
 
 // A batch of channels swept by one launch: entry i holds channel i's constants,
@@ -1677,7 +1715,7 @@ __device__ __forceinline__ void sweep2_block(const KParams& kp, const KBufs& kb,
       const int li = task / kp.nxt, bx = task - li * kp.nxt;
       const long long level = li < 2 ? lv.strip[li] : -1;
       const bool last = li == 1 || lv.strip[1] < 0;  // the latest level keeps the column sums
-      if (level >= 0) strip_reduce(kp, kb, bx, level, int(level & 3), lv.nrt, lv.part_stride, last);
+      if (level >= 0) strip_reduce(kp, kb, bx, level, int(level & 3), lv.nrt, lv.part_stride, 4, last);
     } else if (r == nsb) {
       // the records of up to two levels by one wavefront, in level order: a
       // history ring of one slot keeps the later one
@@ -1776,11 +1814,15 @@ __global__ __launch_bounds__(kThreads) void k_finalize(KParams kp, KBufs kb, lon
   if (phase == 0) {
     if (b < strip_blocks(kp.nxt, kTY)) {
       const int bx = b * kTY + int(threadIdx.x / kTX);
-      if (bx < kp.nxt) strip_reduce(kp, kb, bx, t, int(t & 1), kp.nrt, kb.part_stride);
+      if (bx < kp.nxt) strip_reduce(kp, kb, bx, t, int(t & 1), kp.nrt, kb.part_stride, 2);
     } else if (t - 1 >= t_first && threadIdx.x < kTX)
       global_reduce(kp, kb, t - 1, int((t - 1) & 1));
-  } else if (threadIdx.x < kTX) {
-    global_reduce(kp, kb, t, int(t & 1));
+  } else if (phase == 1) {
+    if (threadIdx.x < kTX) global_reduce(kp, kb, t, int(t & 1));
+  } else {
+    // momentum column sums of level t from an evaluation sweep's partials
+    const int bx = b * kTY + int(threadIdx.x / kTX);
+    if (bx < kp.nxt) jsum_reduce(kp, kb, bx, int((t + 1) & 1));
   }
 }
 
@@ -2073,34 +2115,35 @@ int check_hip(hipError_t e, const char* what) {
 
 template <class MD, bool PULL, bool EVAL>
 void launch_sweep(lbsep_channel* h, const void* src, void* dst, double* mom, void* fraw, double* ffull,
-                  long long t) {
+                  long long t, int jsums) {
   using S = typename MD::St;
   const int grid = h->L.lead + h->L.tiles;
   if (h->L.split)
     hipLaunchKernelGGL((k_sweep<MD, PULL, EVAL, true, false>), dim3(grid), dim3(kThreads), 0, h->stream, h->kp,
                        h->kb, static_cast<const S*>(src), static_cast<S*>(dst), mom, static_cast<S*>(fraw), ffull, t,
-                       (long long)h->t_first);
+                       (long long)h->t_first, jsums);
   else if (h->L.big && !EVAL)
     hipLaunchKernelGGL((k_sweep<MD, PULL, EVAL, false, true>), dim3(grid), dim3(kThreads), 0, h->stream, h->kp,
                        h->kb, static_cast<const S*>(src), static_cast<S*>(dst), mom, static_cast<S*>(fraw), ffull, t,
-                       (long long)h->t_first);
+                       (long long)h->t_first, jsums);
   else
     hipLaunchKernelGGL((k_sweep<MD, PULL, EVAL, false, false>), dim3(grid), dim3(kThreads), 0, h->stream, h->kp,
                        h->kb, static_cast<const S*>(src), static_cast<S*>(dst), mom, static_cast<S*>(fraw), ffull, t,
-                       (long long)h->t_first);
+                       (long long)h->t_first, jsums);
 }
 
 template <bool PULL, bool EVAL>
-void sweep_any(lbsep_channel* h, const void* src, void* dst, double* mom, void* fraw, double* ffull, long long t) {
+void sweep_any(lbsep_channel* h, const void* src, void* dst, double* mom, void* fraw, double* ffull, long long t,
+               int jsums = 0) {
   switch (h->p.dtype) {
     case LBSEP_F64:
-      launch_sweep<ModeF64, PULL, EVAL>(h, src, dst, mom, fraw, ffull, t);
+      launch_sweep<ModeF64, PULL, EVAL>(h, src, dst, mom, fraw, ffull, t, jsums);
       break;
     case LBSEP_F32:
-      launch_sweep<ModeF32, PULL, EVAL>(h, src, dst, mom, fraw, ffull, t);
+      launch_sweep<ModeF32, PULL, EVAL>(h, src, dst, mom, fraw, ffull, t, jsums);
       break;
     default:
-      launch_sweep<ModeF16, PULL, EVAL>(h, src, dst, mom, fraw, ffull, t);
+      launch_sweep<ModeF16, PULL, EVAL>(h, src, dst, mom, fraw, ffull, t, jsums);
       break;
   }
 }
@@ -2206,7 +2249,7 @@ int finalize(lbsep_channel* h) {
 }
 
 // EVAL sweep of the current state into mom, fraw and/or ffull.
-int eval_state(lbsep_channel* h, double* mom, void* fraw, double* ffull) {
+int eval_state(lbsep_channel* h, double* mom, void* fraw, double* ffull, int jsums = 0) {
   if (h->prev_buf < 0) {
     // the last launch advanced two levels: recompute f'(t-1) from f'(t-2)
     // (held by the other buffer) into f2, without reductions
@@ -2215,9 +2258,9 @@ int eval_state(lbsep_channel* h, double* mom, void* fraw, double* ffull) {
   }
   const void* prev = h->prev_buf == 2 ? h->f2 : h->f[h->prev_buf];
   if (h->prev_pre)
-    sweep_any<false, true>(h, prev, nullptr, mom, fraw, ffull, h->t);
+    sweep_any<false, true>(h, prev, nullptr, mom, fraw, ffull, h->t, jsums);
   else
-    sweep_any<true, true>(h, prev, nullptr, mom, fraw, ffull, h->t);
+    sweep_any<true, true>(h, prev, nullptr, mom, fraw, ffull, h->t, jsums);
   return check_hip(hipGetLastError(), "eval launch");
 }
 
@@ -2431,11 +2474,11 @@ int lbsep_step_record(lbsep_channel* h, double* dev_pre, double* dev_post) {
   if (h->L.split)
     hipLaunchKernelGGL((k_sweep<ModeF64, true, false, true, false, true>), dim3(grid), dim3(kThreads), 0, h->stream,
                        h->kp, h->kb, src, dst, nullptr, dev_post, dev_pre, (long long)(h->t + 1),
-                       (long long)h->t_first);
+                       (long long)h->t_first, 0);
   else
     hipLaunchKernelGGL((k_sweep<ModeF64, true, false, false, false, true>), dim3(grid), dim3(kThreads), 0,
                        h->stream, h->kp, h->kb, src, dst, nullptr, dev_post, dev_pre, (long long)(h->t + 1),
-                       (long long)h->t_first);
+                       (long long)h->t_first, 0);
   h->prev_buf = h->cur;
   h->cur = nxt_buf;
   h->prev_pre = false;
@@ -2478,6 +2521,14 @@ int lbsep_read_cl(lbsep_channel* h, double* cl, double* cl_tilde, int32_t* x_min
 int lbsep_read_column_sums(lbsep_channel* h, double* host) {
   if (!h || !host) return fail(LBSEP_EINVAL, "NULL argument");
   if (int e = finalize(h)) return e;
+  if (!h->pipe2) {
+    // one-level launches carry only the density sums: the momentum sums of
+    // the current level come from an evaluation sweep and a strip pass
+    if (int e = eval_state(h, nullptr, nullptr, nullptr, 1)) return e;
+    hipLaunchKernelGGL(k_finalize, dim3(strip_blocks(h->L.nxt, kTY)), dim3(kThreads), 0, h->stream, h->kp, h->kb,
+                       (long long)h->t, (long long)h->t_first, 2);
+    if (int e = check_hip(hipGetLastError(), "column sums launch")) return e;
+  }
   int rc = check_hip(hipMemcpy2DAsync(host, h->p.nx * sizeof(double), h->kb.colsum, h->L.pitch * sizeof(double),
                                       h->p.nx * sizeof(double), 4, hipMemcpyDeviceToHost, h->stream),
                      "column sums copy");

@@ -88,6 +88,45 @@ def test_fp64_ragged_and_edge_shapes(nx, ny, pair, cin, cout, theta, kn, steps):
     assert_argmin(cl["x_min"], d.cl_profile)
 
 
+@pytest.mark.parametrize("tile_mode,levels,periodic_x", [
+    (lbsep.TILE_SPLIT, 1, False), (lbsep.TILE_NODE, 1, False), (lbsep.TILE_NODE, 1, True), (0, 2, False)])
+def test_column_sums_against_the_oracle(tile_mode, levels, periodic_x):
+    """lbsep_read_column_sums on a ragged 150 x 13 channel (row tiles of one
+    row per wavefront, a ragged column strip) after 300 steps: the density
+    sums behind the CL record and the momentum sums of Eq. (rhou), which
+    two-level launches carry and one-level launches leave to an evaluation
+    sweep on request, against the oracle's; reading them changes nothing
+    (the next 50 steps' states and records are bitwise those of a channel
+    that was never read)."""
+    w = Workload("sums", 150, 13, *NE_AR, 0.3, 0.7, 3.0, 0.05, 300)
+    r = r_of(w)
+    modes = {"periodic_x": True} if periodic_x else {}
+    print(f"[case] column sums, tiles {tile_mode}, {levels} level(s), periodic_x {periodic_x}", flush=True)
+    a = channel(w, r, tile_mode=tile_mode, tile_rows=1, fused_steps=levels, **modes)
+    b = channel(w, r, tile_mode=tile_mode, tile_rows=1, fused_steps=levels, **modes)
+    a.step(w.steps)
+    b.step(w.steps)
+    sums = a.read_column_sums()
+    p = oracle_params(w, r, **modes)
+    f, _ = O.run(p, w.steps)
+    d = O.diagnostics(f, p)
+    # each sum against its species' column scale: number densities n_s, and
+    # for the momenta (mass fluxes) the mass densities m_s n_s
+    for k, (got, ref, scale) in enumerate(((sums[0], d.n_a, np.max(d.n_a)), (sums[1], d.n_b, np.max(d.n_b)),
+                                           (sums[2], d.j_a, w.m_a * np.max(d.n_a)),
+                                           (sums[3], d.j_b, w.m_b * np.max(d.n_b)))):
+        err = float(np.max(np.abs(got - ref)) / scale)
+        assert err <= TOL64, (k, err)
+    # the density sums are the record's: its profile is n_l / (n_l + n_h) of them
+    prof = a.read_cl(profile=True)["profile"]
+    assert np.array_equal(prof, sums[0] / (sums[0] + sums[1]))
+    a.step(50)
+    b.step(50)
+    assert torch.equal(a.get_state(), b.get_state())
+    assert np.array_equal(a.read_history(w.steps - 10, 61), b.read_history(w.steps - 10, 61))
+    assert np.array_equal(a.read_column_sums(), b.read_column_sums())
+
+
 def test_fp32_he_ar_8x80():
     w = CONFIGS["he_ar_8x80"]
     print("[case] fp32 he_ar_8x80 2000 steps", flush=True)
