@@ -268,7 +268,8 @@ int lbsep_batch_create(lbsep_channel* const* chans, int32_t n, void* dev_ws, siz
 int lbsep_batch_step(lbsep_batch* b, int64_t nsteps);
 
 /* Capture `steps` batch steps (1 .. 100000) into a HIP graph replayed by
- * lbsep_batch_step; 0 drops the graph. Needs a non-default stream. */
+ * lbsep_batch_step; 0 drops the graph. Needs a non-default stream. The
+ * executable graph's upload to the device is enqueued on that stream. */
 int lbsep_batch_capture(lbsep_batch* b, int64_t steps);
 
 /* Number of member channels; -1 for NULL. */

@@ -3027,7 +3027,8 @@ int lbsep_batch_capture(lbsep_batch* b, int64_t steps) {
   b->graph = g;
   b->exec = x;
   b->graph_steps = steps;
-  return LBSEP_OK;
+  // move the executable graph to the device now rather than on its first replay
+  return check_hip(hipGraphUpload(x, b->stream), "graph upload");
 }
 
 int32_t lbsep_batch_size(const lbsep_batch* b) { return b ? (int32_t)b->ch.size() : -1; }
