@@ -78,3 +78,14 @@ def test_source_hash_ignores_comments(tmp_path, monkeypatch):
     assert bench.source_hash() == ha
     b.write_text("int f() {\n  return 2;\n}\n")
     assert bench.source_hash() != ha
+
+
+def test_named_tile_assignment_skips_the_tuner():
+    """--tiles picks one of the tuner's candidates by name (for profiling runs
+    that must see the assignment a traffic record was taken with)."""
+    from paper_1603_08221_amd import lbsep
+
+    t = bench.tune_table(lbsep, bench.parse_args(["--tiles", "node,rows2"]))
+    assert t["name"] == "node,rows2" and set(t["rows"]) == {2} and len(t["modes"]) == 64
+    with pytest.raises(SystemExit):
+        bench.tune_table(lbsep, bench.parse_args(["--tiles", "no-such-assignment"]))
