@@ -10,7 +10,7 @@ from oracle import binary_lbm as O
 from paper_1603_08221_amd import lbsep
 from paper_1603_08221_amd.workloads import HE_AR, NE_AR, Workload, batch_instances
 
-from gpu_helpers import assert_cl, assert_moments, oracle_params, r_of
+from gpu_helpers import assert_argmin, assert_cl, assert_moments, oracle_params, r_of
 
 pytestmark = pytest.mark.gpu
 
@@ -284,3 +284,37 @@ def test_two_level_batch_of_the_sweep_table_matches_the_one_level_batch():
         assert torch.equal(_bits(x.get_state()), _bits(y.get_state())), ws[k].name
         assert _cl_or_error(x) == pytest.approx(_cl_or_error(y), rel=1e-12, abs=1e-14) \
             if _cl_or_error(x) != "non-finite" else _cl_or_error(y) == "non-finite"
+
+
+def test_table1_runs_as_one_batch_match_the_oracle():
+    """Runs of Table 1 (workloads.table1_instances on an 8 x 280 lattice, the
+    paper's L/H = 35) of every kind: the theta and Kn_out sweeps of cases 2
+    (He-Ar) and 7 (Ne-Ar), the mole fractions of cases 1 and 8, the unequal
+    ends of cases 4 and 10. They advance as one FP64 batch through a
+    captured graph for 400 steps, and each is checked against the oracle:
+    moments to 1e-12, CL, C~_l and x_min, and the CL record every 50 steps."""
+    from paper_1603_08221_amd.workloads import table1_instances
+
+    names = ["c2_th4_kn0.3", "c2_th2_kn3", "c7_th3_kn0.3", "c7_th2_kn5", "c1_th2_kn0.3", "c8_th4_kn0.3",
+             "c4_th2_kn1", "c10_th2_kn0.3"]
+    runs = {w.name: w for w in table1_instances(8, 280)}
+    ws = [runs[n] for n in names]
+    stream = torch.cuda.Stream()
+    chans = _make(ws, "f64", stream)
+    b = lbsep.Batch(chans)
+    b.capture(100)
+    print(f"[case] Table 1 runs {names} as one batch, 400 steps", flush=True)
+    b.step(400)
+    for w, c in zip(ws, chans):
+        p = oracle_params(w, r_of(w))
+        f, hist = O.run(p, 400, record_every=50)
+        d = O.diagnostics(f, p)
+        assert_moments(c.read_moments(), O.moment_fields(f, p), 1e-12, w.name)
+        got = c.read_cl(profile=True)
+        assert_cl(got["cl"], d.cl, 0.0, 1e-12)
+        assert_cl(got["cl_tilde"], d.cl_tilde, 0.0, 1e-12)
+        assert_argmin(got["x_min"], d.cl_profile)
+        rec = c.read_history(0, 401)
+        for t, cl, clt in hist:
+            assert abs(rec[t, 1] - cl) <= 1e-12 and abs(rec[t, 2] - clt) <= 1e-12, (w.name, t)
+    b.close()
