@@ -101,12 +101,14 @@ typedef struct lbsep_params {
   int32_t dtype;    /* LBSEP_F64, LBSEP_F32 or LBSEP_F16                                         */
   int32_t hist_cap; /* per-step diagnostic records kept on the device (ring), >= 1               */
   int32_t tile_mode; /* LBSEP_TILE_AUTO / _SPLIT / _NODE: how nodes map to lanes (same results)  */
-  int32_t tile_rows; /* rows each wavefront of a tile walks: 0 = chosen from the size (4 if that
-                        leaves >= 2048 tiles, except for LBSEP_F32; 2 if >= 512; else 1),
-                        else 1, 2 or 4. The states are the same whatever the value; the column
-                        sums behind CL and the profiles are associated per tile, so those may
-                        differ in the last bits. A channel in a batch that fills the GPU can be
-                        faster with 2 or 4 (fewer row-tile partial sums). */
+  int32_t tile_rows; /* rows each wavefront of a tile walks (a tile is 8 wavefronts for
+                        LBSEP_F32, 4 otherwise, each on 64 columns, or 32 with lane pairs):
+                        0 = chosen from the size (4 if that leaves >= 2048 tiles, except for
+                        LBSEP_F32; 2 if >= 512; else 1), else 1, 2 or 4. The states are the
+                        same whatever the value; the column sums behind CL and the profiles are
+                        associated per tile, so those may differ in the last bits. A channel in
+                        a batch that fills the GPU can be faster with 2 or 4 (fewer row-tile
+                        partial sums). */
   int32_t fused_steps; /* time levels per sweep launch: 0 = chosen by the library (currently 1),
                         1, or 2 (needs ny <= 128 for LBSEP_F32 and LBSEP_F16, ny <= 64 for
                         LBSEP_F64, and an inlet, an outlet and walls: no periodic flag; else

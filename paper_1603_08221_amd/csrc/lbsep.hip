@@ -77,8 +77,10 @@ namespace lbsep {
 namespace {
 
 constexpr int kTX = 64;         // columns per block (one wavefront across x)
-constexpr int kTY = 4;          // wavefronts per block
+constexpr int kTY = 4;          // wavefronts of the 256-thread units below
 constexpr int kThreads = kTX * kTY;
+// an inlet/outlet block's items: 4 lanes (species, inner layer) per row, 64 rows
+constexpr int kEndThreads = 256;
 constexpr int kMaxEnd = 32;     // end blocks per inlet/outlet column: ny <= 64 * kMaxEnd
 constexpr unsigned kRowMajorTiles = 1u << 16;  // KParams::flags bit above the ABI flags
 
@@ -92,6 +94,16 @@ struct Mode {
 using ModeF64 = Mode<double, double, false>;
 using ModeF32 = Mode<float, float, true>;
 using ModeF16 = Mode<_Float16, float, true>;
+
+// Wavefronts per block of the one-level sweep. FP32: 8, so that a tile of two
+// rows per wavefront covers 16 rows and its column partial sums are half as
+// many as with 4 (64-member table: 187.3 -> 184.8 us per step; 512 x 10240:
+// 133.5 -> 132.0 us). FP64 and FP16 keep 4: their register counts (167 and 91
+// VGPRs) leave room for 3 and 5 wavefronts per SIMD, which blocks of 8 would
+// cut to 2 and 4 (the table: FP64 462 -> 658 us, FP16 148.8 -> 156.9 us).
+template <class MD>
+constexpr int kWaves = std::is_same<typename MD::St, float>::value ? 8 : 4;
+constexpr int waves_of(int dtype) { return dtype == LBSEP_F32 ? 8 : 4; }
 
 struct KParams {
   RelaxConsts rc;
@@ -877,20 +889,25 @@ __device__ __forceinline__ void global_reduce(const KParams& kp, const KBufs& kb
   }
 }
 
-// Block-wide sum of nv <= 4 doubles per thread of the first kThreads
-// (fixed order); the result for quantity k is left in red[k][0][0]. Every
-// thread of the block (NT threads) reaches every barrier.
-template <int NT = kThreads>
-__device__ __forceinline__ void block_sum(double (*red)[kTY][kTX], const double* v, int nv) {
+// Block-wide sum of nv <= 4 doubles per thread of the first W wavefronts
+// (fixed order: the wavefronts' values in wavefront order, then a lane
+// butterfly); the result for quantity k is left in red[k][0][0]. Every thread
+// of the block (NT threads) reaches every barrier. Wavefronts beyond W only
+// meet the barriers; wavefronts that hold zeros leave the sum's bits as they
+// are (x + 0 = x), so a block of 8 whose last 4 hold nothing sums like one of 4.
+template <int W = kTY, int NT = kTX * W>
+__device__ __forceinline__ void block_sum(double (*red)[W][kTX], const double* v, int nv) {
   const int tx = threadIdx.x & (kTX - 1);
-  const int w = threadIdx.x / kTX;  // in larger blocks, wavefronts beyond the fourth only meet the barriers
-  if (NT <= kThreads || w < kTY)
+  const int w = threadIdx.x / kTX;
+  if (NT <= kTX * W || w < W)
     for (int k = 0; k < nv; ++k) red[k][w][tx] = v[k];
   __syncthreads();
   const int k = w;  // wavefront w sums quantity k = w (wave-uniform)
   double s = 0.0;
   if (k < nv) {
-    s = ((red[k][0][tx] + red[k][1][tx]) + red[k][2][tx]) + red[k][3][tx];
+    s = red[k][0][tx];
+#pragma unroll
+    for (int u = 1; u < W; ++u) s += red[k][u][tx];
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) s += lane_xor(s, off);
   }
@@ -908,17 +925,18 @@ __device__ __forceinline__ void sweep_block(const KParams& kp, const KBufs& kb,
                                             const typename MD::St* __restrict__ src, typename MD::St* __restrict__ dst,
                                             double* __restrict__ mom, typename MD::St* __restrict__ fraw,
                                             double* __restrict__ ffull, long long t, long long t_first, int b,
-                                            double (*red)[kTY][kTX], bool jsums = false) {
+                                            double (*red)[kWaves<MD>][kTX], bool jsums = false) {
   using C = typename MD::Ct;
+  constexpr int W = kWaves<MD>;
   const bool px = kp.flags & LBSEP_PERIODIC_X;
   if (b < kp.lead) {
     if (b >= 2 * kp.nend) {
       // ---- pipelined reductions of the two previous levels --------------------
       if (EVAL) return;
       const int r = b - 2 * kp.nend;
-      const int nsb = strip_blocks(kp.nxt, kTY);
+      const int nsb = strip_blocks(kp.nxt, W);
       if (r < nsb) {
-        const int bx = r * kTY + int(threadIdx.x / kTX);
+        const int bx = r * W + int(threadIdx.x / kTX);
         if (bx < kp.nxt && t - 1 >= t_first)
           strip_reduce(kp, kb, bx, t - 1, int((t - 1) & 1), kp.nrt, kb.part_stride, 2);
       } else if (r == nsb) {
@@ -927,7 +945,8 @@ __device__ __forceinline__ void sweep_block(const KParams& kp, const KBufs& kb,
       return;
     }
     // ---- inlet (e = 0) / outlet (e = 1) column, rows [64 blk, 64 blk + 64) ----
-    // Lane L = 4 j' + 2 s + layer holds, for row j = 64 blk + j' and species s,
+    // Lane L = 4 j' + 2 s + layer (L < 256; in blocks of 8 wavefronts the last
+    // four only meet the barriers) holds, for row j = 64 blk + j' and species s,
     // the pulled populations of the first (layer 0) or second (layer 1) inner
     // layer; layer-0 lanes also pull the boundary node itself. All these loads
     // are in flight together; Eq. (rho2) then needs the whole column's sum of
@@ -944,7 +963,7 @@ __device__ __forceinline__ void sweep_block(const KParams& kp, const KBufs& kb,
     const int layer = L & 1;
     const int s = (L >> 1) & 1;
     const int j = blk * 64 + (L >> 2);
-    const bool active = j < kp.ny;
+    const bool active = L < kEndThreads && j < kp.ny;
     C g[9], f[9];
     double kap = 1.0, km1 = 0.0;
 #pragma unroll
@@ -961,7 +980,7 @@ __device__ __forceinline__ void sweep_block(const KParams& kp, const KBufs& kb,
         const double v = double(sum9(g));
         if (s) sums[1] += layer ? -v : 2.0 * v; else sums[0] += layer ? -v : 2.0 * v;
       }
-      for (int it = L; it < 4 * kp.ny; it += kThreads) {
+      for (int it = L; L < kEndThreads && it < 4 * kp.ny; it += kEndThreads) {
         const int jj = it >> 2;
         if ((jj >> 6) == blk) continue;
         const int ss = (it >> 1) & 1, ll = it & 1;
@@ -970,7 +989,7 @@ __device__ __forceinline__ void sweep_block(const KParams& kp, const KBufs& kb,
         const double v = double(sum9(h));
         if (ss) sums[1] += ll ? -v : 2.0 * v; else sums[0] += ll ? -v : 2.0 * v;
       }
-      block_sum(red, sums, 2);
+      block_sum<W>(red, sums, 2);
       const double n = double(kp.ny), sum = red[s][0][0];
       __syncthreads();  // red is reused by the block sum below
       if (MD::kDev) {
@@ -995,7 +1014,7 @@ __device__ __forceinline__ void sweep_block(const KParams& kp, const KBufs& kb,
                                                 reinterpret_cast<double*>(fraw));
     if (EVAL && !jsums) return;
     const double acc[4] = {s ? 0.0 : acc2[0], s ? acc2[0] : 0.0, s ? 0.0 : acc2[1], s ? acc2[1] : 0.0};
-    block_sum(red, acc, 4);
+    block_sum<W>(red, acc, 4);
     // a step: all four sums of level t; an evaluation sweep: the momenta, to the other slot
     if (threadIdx.x < 4 && (!EVAL || threadIdx.x >= 2))
       kb.endsum[((((EVAL ? t + 1 : t) & 1) * 2 + e) * kMaxEnd + blk) * 4 + threadIdx.x] = red[threadIdx.x][0][0];
@@ -1021,7 +1040,7 @@ __device__ __forceinline__ void sweep_block(const KParams& kp, const KBufs& kb,
   // state buffers then stay in scalar registers
   const int ty = __builtin_amdgcn_readfirstlane(threadIdx.x / kTX);
   if (SPLIT) {
-    // 32 columns x (4 rpt) rows; lanes 0-31 hold species a, 32-63 species b
+    // 32 columns x (W rpt) rows; lanes 0-31 hold species a, 32-63 species b
     const int s = lane >> 5;
     const int cx = lane & 31;
     const int x = bx * 32 + cx;
@@ -1029,7 +1048,7 @@ __device__ __forceinline__ void sweep_block(const KParams& kp, const KBufs& kb,
     double acc[2] = {0.0, 0.0};
 #pragma unroll 1
     for (int r = 0; r < kp.rpt; ++r) {
-      const int j = by * (kTY * kp.rpt) + r * kTY + ty;
+      const int j = by * (W * kp.rpt) + r * W + ty;
       if (j < kp.ny) {  // wave-uniform
         C f[9];
         if (xin) gather1<MD, PULL>(kp, src, s, x, j, t, f);
@@ -1047,18 +1066,20 @@ __device__ __forceinline__ void sweep_block(const KParams& kp, const KBufs& kb,
       const int q = (threadIdx.x >> 5) + (EVAL ? 2 : 0), c = threadIdx.x & 31;
       const int xc = bx * 32 + c;
       if (xc < kp.nx) {
-        const double v = ((red[q][0][c] + red[q][1][c]) + red[q][2][c]) + red[q][3][c];
+        double v = red[q][0][c];
+#pragma unroll
+        for (int u = 1; u < W; ++u) v += red[q][u][c];
         kb.partials[((EVAL ? t + 1 : t) & 1) * kb.part_stride + ((long long)q * kp.nrt + by) * kp.pitch + xc] = v;
       }
     }
   } else {
-    // 64 columns x (4 rpt) rows, one lane per node
+    // 64 columns x (W rpt) rows, one lane per node
     const int x = bx * kTX + lane;
     const bool xin = (x < kp.nx) && (px || (x > 0 && x < kp.nx - 1));
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll 1
     for (int r = 0; r < kp.rpt; ++r) {
-      const int j = by * (kTY * kp.rpt) + r * kTY + ty;
+      const int j = by * (W * kp.rpt) + r * W + ty;
       if (xin && j < kp.ny) {
         C fa[9], fb[9];
         gather_pair<MD, PULL>(kp, src, x, j, t, fa, fb);
@@ -1067,13 +1088,16 @@ __device__ __forceinline__ void sweep_block(const KParams& kp, const KBufs& kb,
       }
     }
     if (EVAL && !jsums) return;
-    // per-column sums of this row tile (4 wavefronts -> 1), quantity q = ty:
-    // the densities in a step, the momenta in an evaluation sweep
+    // per-column sums of this row tile (W wavefronts -> 1), quantity q = ty
+    // (wavefronts 0-3): the densities in a step, the momenta in an evaluation
+    // sweep
 #pragma unroll
     for (int q = 0; q < 4; ++q) red[q][ty][lane] = acc[q];
     __syncthreads();
-    if (x < kp.nx && (ty >= 2) == EVAL) {
-      const double v = ((red[ty][0][lane] + red[ty][1][lane]) + red[ty][2][lane]) + red[ty][3][lane];
+    if (x < kp.nx && ty < 4 && (ty >= 2) == EVAL) {
+      double v = red[ty][0][lane];
+#pragma unroll
+      for (int u = 1; u < W; ++u) v += red[ty][u][lane];
       kb.partials[((EVAL ? t + 1 : t) & 1) * kb.part_stride + ((long long)ty * kp.nrt + by) * kp.pitch + x] = v;
     }
   }
@@ -1083,12 +1107,12 @@ __device__ __forceinline__ void sweep_block(const KParams& kp, const KBufs& kb,
 // the pulled (pre-collision) populations and fraw the post-collision ones,
 // both dense [2][9][ny][nx].
 template <class MD, bool PULL, bool EVAL, bool SPLIT, bool NT, bool REC = false>
-__global__ __launch_bounds__(kThreads) void k_sweep(KParams kp, KBufs kb, const typename MD::St* __restrict__ src,
+__global__ __launch_bounds__(kTX * kWaves<MD>) void k_sweep(KParams kp, KBufs kb, const typename MD::St* __restrict__ src,
                                                     typename MD::St* __restrict__ dst, double* __restrict__ mom,
                                                     typename MD::St* __restrict__ fraw,
                                                     double* __restrict__ ffull, long long t,
                                                     long long t_first, int jsums) {
-  __shared__ double red[4][kTY][kTX];
+  __shared__ double red[4][kWaves<MD>][kTX];
   sweep_block<MD, PULL, EVAL, SPLIT, NT, REC>(kp, kb, src, dst, mom, fraw, ffull, t, t_first, (int)blockIdx.x, red,
                                               jsums != 0);
 }
@@ -1112,10 +1136,10 @@ struct BatchEntry {
 
 // Batch step k = *counter + k_local: every channel advances by one level.
 template <class MD, bool NT>
-__global__ __launch_bounds__(kThreads) void k_sweep_batch(const BatchEntry* __restrict__ tab,
+__global__ __launch_bounds__(kTX * kWaves<MD>) void k_sweep_batch(const BatchEntry* __restrict__ tab,
                                                           const int2* __restrict__ blk_ref,
                                                           const long long* __restrict__ counter, int k_local) {
-  __shared__ double red[4][kTY][kTX];
+  __shared__ double red[4][kWaves<MD>][kTX];
   using S = typename MD::St;
   const int2 ref = blk_ref[blockIdx.x];
   const BatchEntry& e = tab[ref.x];
@@ -1182,7 +1206,7 @@ template <class MD>
 __device__ __forceinline__ void kappa_from_sums(const KParams& kp, int e, double (*red)[kTY][kTX], double sums[2],
                                                 double kap[2], double km1[2]) {
   const int col = e ? kp.nx - 1 : 0;
-  block_sum<kT2>(red, sums, 2);
+  block_sum<kTY, kT2>(red, sums, 2);
   const double n = double(kp.ny);
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
@@ -1214,10 +1238,10 @@ __device__ __forceinline__ void kappa_from_values(const KParams& kp, int e, cons
                                                   double kap[2], double km1[2]) {
   double sums[2] = {0.0, 0.0};
   const int it = threadIdx.x;
-  if (it < kThreads) {
+  if (it < kEndThreads) {
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
-      const int item = it + k * kThreads;
+      const int item = it + k * kEndThreads;
       if (item < 4 * kp.ny) {
         const int ss = (item >> 1) & 1, ll = item & 1;
         if (ss)
@@ -1808,12 +1832,13 @@ __global__ void k_batch2_advance(Batch2Levels* bl, int nlev) {
   }
 }
 
-__global__ __launch_bounds__(kThreads) void k_finalize(KParams kp, KBufs kb, long long t, long long t_first,
+__global__ __launch_bounds__(kTX * 8) void k_finalize(KParams kp, KBufs kb, long long t, long long t_first,
                                                        int phase) {
   const int b = blockIdx.x;
   if (phase == 0) {
-    if (b < strip_blocks(kp.nxt, kTY)) {
-      const int bx = b * kTY + int(threadIdx.x / kTX);
+    const int waves = int(blockDim.x / kTX);  // the channel's sweep block: one strip per wavefront
+    if (b < strip_blocks(kp.nxt, waves)) {
+      const int bx = b * waves + int(threadIdx.x / kTX);
       if (bx < kp.nxt) strip_reduce(kp, kb, bx, t, int(t & 1), kp.nrt, kb.part_stride, 2);
     } else if (t - 1 >= t_first && threadIdx.x < kTX)
       global_reduce(kp, kb, t - 1, int((t - 1) & 1));
@@ -1821,7 +1846,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(KParams kp, KBufs kb, lon
     if (threadIdx.x < kTX) global_reduce(kp, kb, t, int(t & 1));
   } else {
     // momentum column sums of level t from an evaluation sweep's partials
-    const int bx = b * kTY + int(threadIdx.x / kTX);
+    const int bx = b * int(blockDim.x / kTX) + int(threadIdx.x / kTX);
     if (bx < kp.nxt) jsum_reduce(kp, kb, bx, int((t + 1) & 1));
   }
 }
@@ -1954,7 +1979,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 size_t elem_bytes(int dtype) { return dtype == LBSEP_F64 ? 8 : dtype == LBSEP_F32 ? 4 : 2; }
 
 struct Layout {
-  int pitch, nxt, ntx, nrt, rpt, tiles, lead, nend;
+  int pitch, nxt, ntx, nrt, rpt, waves, tiles, lead, nend;
   bool split;
   bool big;  // a state buffer exceeds half the last-level cache: row-major tiles, non-temporal stores
   bool two;  // two time levels per launch (k_sweep2)
@@ -2016,6 +2041,7 @@ Layout make_layout(const lbsep_params* p) {
     L.split = (long long)p->nx * p->ny <= (1LL << 16);
   const int cols = L.split ? 32 : 64;
   L.ntx = (p->nx + cols - 1) / cols;
+  L.waves = waves_of(p->dtype);
   // rows per thread: as asked, else 4 if that still gives >= 2048 tiles, 2 if
   // >= 512, else 1 (a channel alone needs the parallelism; in a batch that
   // fills the GPU, more rows cut the row-tile partial sums). FP32 stops at 2:
@@ -2028,17 +2054,17 @@ Layout make_layout(const lbsep_params* p) {
   } else {
     for (int r : {4, 2}) {
       if (r == 4 && p->dtype == LBSEP_F32) continue;
-      const int nrt = (p->ny + kTY * r - 1) / (kTY * r);
+      const int nrt = (p->ny + L.waves * r - 1) / (L.waves * r);
       if ((long long)L.ntx * nrt >= (r == 4 ? 2048 : 512)) {
         L.rpt = r;
         break;
       }
     }
   }
-  L.nrt = (p->ny + kTY * L.rpt - 1) / (kTY * L.rpt);
+  L.nrt = (p->ny + L.waves * L.rpt - 1) / (L.waves * L.rpt);
   L.tiles = L.ntx * L.nrt;
   L.nend = (p->ny + 63) / 64;
-  L.lead = 2 * L.nend + strip_blocks(L.nxt, kTY) + 1;
+  L.lead = 2 * L.nend + strip_blocks(L.nxt, L.waves) + 1;
   L.state_buf = align_up(18ull * p->ny * L.pitch * L.elem, 256);
   L.big = !L.split && L.state_buf > (128ull << 20);
   // two levels per launch: tiles own 62 columns x 6 rows of the interior
@@ -2119,15 +2145,15 @@ void launch_sweep(lbsep_channel* h, const void* src, void* dst, double* mom, voi
   using S = typename MD::St;
   const int grid = h->L.lead + h->L.tiles;
   if (h->L.split)
-    hipLaunchKernelGGL((k_sweep<MD, PULL, EVAL, true, false>), dim3(grid), dim3(kThreads), 0, h->stream, h->kp,
+    hipLaunchKernelGGL((k_sweep<MD, PULL, EVAL, true, false>), dim3(grid), dim3(kTX * kWaves<MD>), 0, h->stream, h->kp,
                        h->kb, static_cast<const S*>(src), static_cast<S*>(dst), mom, static_cast<S*>(fraw), ffull, t,
                        (long long)h->t_first, jsums);
   else if (h->L.big && !EVAL)
-    hipLaunchKernelGGL((k_sweep<MD, PULL, EVAL, false, true>), dim3(grid), dim3(kThreads), 0, h->stream, h->kp,
+    hipLaunchKernelGGL((k_sweep<MD, PULL, EVAL, false, true>), dim3(grid), dim3(kTX * kWaves<MD>), 0, h->stream, h->kp,
                        h->kb, static_cast<const S*>(src), static_cast<S*>(dst), mom, static_cast<S*>(fraw), ffull, t,
                        (long long)h->t_first, jsums);
   else
-    hipLaunchKernelGGL((k_sweep<MD, PULL, EVAL, false, false>), dim3(grid), dim3(kThreads), 0, h->stream, h->kp,
+    hipLaunchKernelGGL((k_sweep<MD, PULL, EVAL, false, false>), dim3(grid), dim3(kTX * kWaves<MD>), 0, h->stream, h->kp,
                        h->kb, static_cast<const S*>(src), static_cast<S*>(dst), mom, static_cast<S*>(fraw), ffull, t,
                        (long long)h->t_first, jsums);
 }
@@ -2239,9 +2265,10 @@ int finalize(lbsep_channel* h) {
     launch_sweep2(h, lv, nullptr, nullptr);
     h->glob_next = h->strip_next;
   } else {
-    hipLaunchKernelGGL(k_finalize, dim3(strip_blocks(h->L.nxt, kTY) + 1), dim3(kThreads), 0, h->stream, h->kp, h->kb,
+    hipLaunchKernelGGL(k_finalize, dim3(strip_blocks(h->L.nxt, h->L.waves) + 1), dim3(kTX * h->L.waves), 0, h->stream,
+                       h->kp, h->kb,
                        (long long)h->t, (long long)h->t_first, 0);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, h->stream, h->kp, h->kb, (long long)h->t,
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kTX * h->L.waves), 0, h->stream, h->kp, h->kb, (long long)h->t,
                        (long long)h->t_first, 1);
   }
   h->finalized = true;
@@ -2472,11 +2499,11 @@ int lbsep_step_record(lbsep_channel* h, double* dev_pre, double* dev_post) {
   double* dst = static_cast<double*>(h->f[nxt_buf]);
   // the recording variant: ffull <- pulled populations, fraw <- post-collision
   if (h->L.split)
-    hipLaunchKernelGGL((k_sweep<ModeF64, true, false, true, false, true>), dim3(grid), dim3(kThreads), 0, h->stream,
+    hipLaunchKernelGGL((k_sweep<ModeF64, true, false, true, false, true>), dim3(grid), dim3(kTX * kWaves<ModeF64>), 0, h->stream,
                        h->kp, h->kb, src, dst, nullptr, dev_post, dev_pre, (long long)(h->t + 1),
                        (long long)h->t_first, 0);
   else
-    hipLaunchKernelGGL((k_sweep<ModeF64, true, false, false, false, true>), dim3(grid), dim3(kThreads), 0,
+    hipLaunchKernelGGL((k_sweep<ModeF64, true, false, false, false, true>), dim3(grid), dim3(kTX * kWaves<ModeF64>), 0,
                        h->stream, h->kp, h->kb, src, dst, nullptr, dev_post, dev_pre, (long long)(h->t + 1),
                        (long long)h->t_first, 0);
   h->prev_buf = h->cur;
@@ -2525,7 +2552,7 @@ int lbsep_read_column_sums(lbsep_channel* h, double* host) {
     // one-level launches carry only the density sums: the momentum sums of
     // the current level come from an evaluation sweep and a strip pass
     if (int e = eval_state(h, nullptr, nullptr, nullptr, 1)) return e;
-    hipLaunchKernelGGL(k_finalize, dim3(strip_blocks(h->L.nxt, kTY)), dim3(kThreads), 0, h->stream, h->kp, h->kb,
+    hipLaunchKernelGGL(k_finalize, dim3(strip_blocks(h->L.nxt, h->L.waves)), dim3(kTX * h->L.waves), 0, h->stream, h->kp, h->kb,
                        (long long)h->t, (long long)h->t_first, 2);
     if (int e = check_hip(hipGetLastError(), "column sums launch")) return e;
   }
@@ -2773,10 +2800,10 @@ int batch_layout(lbsep_channel* const* chans, int n, BatchLayout& B) {
 template <class MD>
 void launch_batch(lbsep_batch* b, int k_local) {
   if (b->nt)
-    hipLaunchKernelGGL((k_sweep_batch<MD, true>), dim3(b->total_blocks), dim3(kThreads), 0, b->stream, b->tab,
+    hipLaunchKernelGGL((k_sweep_batch<MD, true>), dim3(b->total_blocks), dim3(kTX * kWaves<MD>), 0, b->stream, b->tab,
                        b->blk_ref, b->counter, k_local);
   else
-    hipLaunchKernelGGL((k_sweep_batch<MD, false>), dim3(b->total_blocks), dim3(kThreads), 0, b->stream, b->tab,
+    hipLaunchKernelGGL((k_sweep_batch<MD, false>), dim3(b->total_blocks), dim3(kTX * kWaves<MD>), 0, b->stream, b->tab,
                        b->blk_ref, b->counter, k_local);
 }
 
