@@ -973,21 +973,22 @@ __device__ __forceinline__ void sweep_block(const KParams& kp, const KBufs& kb,
         gather1<MD, true>(kp, src, s, layer ? l2 : l1, j, t, g);
         if (layer == 0) gather1<MD, true>(kp, src, s, col, j, t, f);
       }
-      // kappa needs sum_j rho'(col, j) over the whole column: own rows from the
-      // registers, the other end blocks' rows pulled again (sum only)
+      // kappa needs sum_j rho'(col, j) over the whole column: thread L adds
+      // items L, L + 256, L + 512, ... (item 4 j + 2 s + layer) in that order,
+      // its own from the registers and the other end blocks' pulled again (sum
+      // only), so that every end block of the column forms the same sums
       double sums[2] = {0.0, 0.0};
-      if (active) {
-        const double v = double(sum9(g));
-        if (s) sums[1] += layer ? -v : 2.0 * v; else sums[0] += layer ? -v : 2.0 * v;
-      }
       for (int it = L; L < kEndThreads && it < 4 * kp.ny; it += kEndThreads) {
         const int jj = it >> 2;
-        if ((jj >> 6) == blk) continue;
-        const int ss = (it >> 1) & 1, ll = it & 1;
-        C h[9];
-        gather1<MD, true>(kp, src, ss, ll ? l2 : l1, jj, t, h);
-        const double v = double(sum9(h));
-        if (ss) sums[1] += ll ? -v : 2.0 * v; else sums[0] += ll ? -v : 2.0 * v;
+        double v;
+        if ((jj >> 6) == blk) {
+          v = double(sum9(g));  // it == 256 blk + L: this thread's own item
+        } else {
+          C h[9];
+          gather1<MD, true>(kp, src, s, layer ? l2 : l1, jj, t, h);
+          v = double(sum9(h));
+        }
+        if (s) sums[1] += layer ? -v : 2.0 * v; else sums[0] += layer ? -v : 2.0 * v;
       }
       block_sum<W>(red, sums, 2);
       const double n = double(kp.ny), sum = red[s][0][0];
