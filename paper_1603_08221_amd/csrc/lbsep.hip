@@ -112,7 +112,8 @@ struct KParams {
   int ntx;              // 32-column tile strips
   int tiles;            // ntx * nrt
   int lead;             // lead blocks (multiple of 8) before the first tile
-  int nend;             // blocks per inlet/outlet column (64 rows each)
+  int nend;             // 64-row units per inlet/outlet column
+  int nendb;            // inlet/outlet blocks of a launch (one or two units each)
   long long row;        // elements per row of a state buffer: 18 * pitch
   unsigned flags;
   double r;             // DBB coefficient
@@ -930,10 +931,10 @@ __device__ __forceinline__ void sweep_block(const KParams& kp, const KBufs& kb,
   constexpr int W = kWaves<MD>;
   const bool px = kp.flags & LBSEP_PERIODIC_X;
   if (b < kp.lead) {
-    if (b >= 2 * kp.nend) {
+    if (b >= kp.nendb) {
       // ---- pipelined reductions of the two previous levels --------------------
       if (EVAL) return;
-      const int r = b - 2 * kp.nend;
+      const int r = b - kp.nendb;
       const int nsb = strip_blocks(kp.nxt, W);
       if (r < nsb) {
         const int bx = r * W + int(threadIdx.x / kTX);
@@ -944,26 +945,44 @@ __device__ __forceinline__ void sweep_block(const KParams& kp, const KBufs& kb,
       }
       return;
     }
-    // ---- inlet (e = 0) / outlet (e = 1) column, rows [64 blk, 64 blk + 64) ----
-    // Lane L = 4 j' + 2 s + layer (L < 256; in blocks of 8 wavefronts the last
-    // four only meet the barriers) holds, for row j = 64 blk + j' and species s,
-    // the pulled populations of the first (layer 0) or second (layer 1) inner
+    // ---- inlet (e = 0) / outlet (e = 1) columns ------------------------------------
+    // An end unit is 64 rows of one end column, held by 256 threads: lane
+    // L = 4 j' + 2 s + layer holds, for row j = 64 u + j' and species s, the
+    // pulled populations of the first (layer 0) or second (layer 1) inner
     // layer; layer-0 lanes also pull the boundary node itself. All these loads
     // are in flight together; Eq. (rho2) then needs the whole column's sum of
     // rho' (Eq. (rho1)) for kappa, after which the layer-0 lanes rebuild the
     // node from their own and their layer-1 neighbour's values and collide it
-    // in species pairs (lanes L and L ^ 2).
+    // in species pairs (lanes L and L ^ 2). A block of 4 wavefronts holds one
+    // unit; a block of 8 holds two: the two ends of a channel of at most 64
+    // rows, else two consecutive units of one end.
     if (px) return;
-    const int e = b / kp.nend;
-    const int blk = b - e * kp.nend;
+    const int L = threadIdx.x & (kEndThreads - 1);
+    const int h = W == 8 ? int(threadIdx.x / kEndThreads) : 0;  // half of a block of 8
+    const bool both = W == 8 && kp.ny <= 64;                     // the halves are the two ends
+    const bool pair_units = W == 8 && !both;                     // the halves are units u, u + 1
+    auto unit_of = [&](int hh, int& ee, int& uu) {
+      if (W != 8) {
+        ee = b / kp.nend;
+        uu = b - ee * kp.nend;
+      } else if (both) {
+        ee = hh;
+        uu = 0;
+      } else {
+        const int per = kp.nendb / 2;
+        ee = b / per;
+        uu = 2 * (b - ee * per) + hh;
+      }
+    };
+    int e, u;
+    unit_of(h, e, u);
     const int col = e ? kp.nx - 1 : 0;
     const int l1 = e ? kp.nx - 2 : 1;
     const int l2 = e ? kp.nx - 3 : 2;  // first and second inner layers
-    const int L = threadIdx.x;
     const int layer = L & 1;
     const int s = (L >> 1) & 1;
-    const int j = blk * 64 + (L >> 2);
-    const bool active = L < kEndThreads && j < kp.ny;
+    const int j = u * 64 + (L >> 2);
+    const bool active = j < kp.ny;
     C g[9], f[9];
     double kap = 1.0, km1 = 0.0;
 #pragma unroll
@@ -973,25 +992,40 @@ __device__ __forceinline__ void sweep_block(const KParams& kp, const KBufs& kb,
         gather1<MD, true>(kp, src, s, layer ? l2 : l1, j, t, g);
         if (layer == 0) gather1<MD, true>(kp, src, s, col, j, t, f);
       }
-      // kappa needs sum_j rho'(col, j) over the whole column: thread L adds
-      // items L, L + 256, L + 512, ... (item 4 j + 2 s + layer) in that order,
-      // its own from the registers and the other end blocks' pulled again (sum
-      // only), so that every end block of the column forms the same sums
-      double sums[2] = {0.0, 0.0};
-      for (int it = L; L < kEndThreads && it < 4 * kp.ny; it += kEndThreads) {
-        const int jj = it >> 2;
-        double v;
-        if ((jj >> 6) == blk) {
-          v = double(sum9(g));  // it == 256 blk + L: this thread's own item
-        } else {
-          C h[9];
-          gather1<MD, true>(kp, src, s, layer ? l2 : l1, jj, t, h);
-          v = double(sum9(h));
-        }
-        if (s) sums[1] += layer ? -v : 2.0 * v; else sums[0] += layer ? -v : 2.0 * v;
+      // kappa needs sum_j rho'(col, j) over the whole column: thread slot L
+      // adds items L, L + 256, L + 512, ... (item 4 j + 2 s + layer, 256 per
+      // unit) in that order: its own unit's from the registers, the other
+      // half's (units u, u + 1 of one end) through LDS, other blocks' pulled
+      // again (sum only); so every block of the column forms the same sums.
+      double* xch = &red[W - 1][0][0];  // 256 doubles of scratch, untouched by the block sums below
+      if (pair_units) {
+        if (h == 1 && active) xch[L] = double(sum9(g));
+        __syncthreads();
       }
-      block_sum<W>(red, sums, 2);
-      const double n = double(kp.ny), sum = red[s][0][0];
+      double sums[2] = {0.0, 0.0};
+      if (h == 0 || both) {
+        for (int it = L; it < 4 * kp.ny; it += kEndThreads) {
+          const int uk = it >> 8;  // unit of item it
+          double v;
+          if (uk == u) {
+            v = double(sum9(g));
+          } else if (pair_units && uk == u + 1) {
+            v = xch[L];
+          } else {
+            C hv[9];
+            gather1<MD, true>(kp, src, s, layer ? l2 : l1, it >> 2, t, hv);
+            v = double(sum9(hv));
+          }
+          if (s) sums[1] += layer ? -v : 2.0 * v; else sums[0] += layer ? -v : 2.0 * v;
+        }
+      }
+      // the two ends of a block of 8 sum apart (quantities 2 e + s); a zero
+      // added to a sum leaves its bits, so each end's sums are those of a
+      // block of 4 that holds the unit alone
+      const double q4[4] = {both && h ? 0.0 : sums[0], both && h ? 0.0 : sums[1], both && h ? sums[0] : 0.0,
+                            both && h ? sums[1] : 0.0};
+      block_sum<W>(red, q4, both ? 4 : 2);
+      const double n = double(kp.ny), sum = red[(both ? 2 * h : 0) + s][0][0];
       __syncthreads();  // red is reused by the block sum below
       if (MD::kDev) {
         // sum_j rho' = n rho0(col) + sum (deviation sums)
@@ -1014,11 +1048,24 @@ __device__ __forceinline__ void sweep_block(const KParams& kp, const KBufs& kb,
     process_pair<MD, EVAL, 2, true, false, REC>(kp, col, j, t, s, active && layer == 0, f, dst, mom, fraw, ffull, acc2,
                                                 reinterpret_cast<double*>(fraw));
     if (EVAL && !jsums) return;
+    // the unit sums: quantity 4 h + q of half h (q: n_a, n_b, rho_a u_ax, rho_b u_bx)
+    double a8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     const double acc[4] = {s ? 0.0 : acc2[0], s ? acc2[0] : 0.0, s ? 0.0 : acc2[1], s ? acc2[1] : 0.0};
-    block_sum<W>(red, acc, 4);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (h == 0) a8[q] = acc[q];
+      else a8[4 + q] = acc[q];
+    }
+    constexpr int kUnitSums = W == 8 ? 8 : 4;
+    block_sum<W>(red, a8, kUnitSums);
     // a step: all four sums of level t; an evaluation sweep: the momenta, to the other slot
-    if (threadIdx.x < 4 && (!EVAL || threadIdx.x >= 2))
-      kb.endsum[((((EVAL ? t + 1 : t) & 1) * 2 + e) * kMaxEnd + blk) * 4 + threadIdx.x] = red[threadIdx.x][0][0];
+    const int tq = threadIdx.x;
+    if (tq < kUnitSums && (!EVAL || (tq & 3) >= 2)) {
+      int ee, uu;
+      unit_of(tq >> 2, ee, uu);
+      if (uu * 64 < kp.ny)
+        kb.endsum[((((EVAL ? t + 1 : t) & 1) * 2 + ee) * kMaxEnd + uu) * 4 + (tq & 3)] = red[tq][0][0];
+    }
     return;
   }
   // ---- interior tile --------------------------------------------------------------
@@ -1113,7 +1160,7 @@ __global__ __launch_bounds__(kTX * kWaves<MD>) void k_sweep(KParams kp, KBufs kb
                                                     typename MD::St* __restrict__ fraw,
                                                     double* __restrict__ ffull, long long t,
                                                     long long t_first, int jsums) {
-  __shared__ double red[4][kWaves<MD>][kTX];
+  __shared__ double red[kWaves<MD>][kWaves<MD>][kTX];  // up to W quantities (inlet/outlet unit sums)
   sweep_block<MD, PULL, EVAL, SPLIT, NT, REC>(kp, kb, src, dst, mom, fraw, ffull, t, t_first, (int)blockIdx.x, red,
                                               jsums != 0);
 }
@@ -1140,7 +1187,7 @@ template <class MD, bool NT>
 __global__ __launch_bounds__(kTX * kWaves<MD>) void k_sweep_batch(const BatchEntry* __restrict__ tab,
                                                           const int2* __restrict__ blk_ref,
                                                           const long long* __restrict__ counter, int k_local) {
-  __shared__ double red[4][kWaves<MD>][kTX];
+  __shared__ double red[kWaves<MD>][kWaves<MD>][kTX];  // up to W quantities (inlet/outlet unit sums)
   using S = typename MD::St;
   const int2 ref = blk_ref[blockIdx.x];
   const BatchEntry& e = tab[ref.x];
@@ -1980,7 +2027,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 size_t elem_bytes(int dtype) { return dtype == LBSEP_F64 ? 8 : dtype == LBSEP_F32 ? 4 : 2; }
 
 struct Layout {
-  int pitch, nxt, ntx, nrt, rpt, waves, tiles, lead, nend;
+  int pitch, nxt, ntx, nrt, rpt, waves, tiles, lead, nend, nendb;
   bool split;
   bool big;  // a state buffer exceeds half the last-level cache: row-major tiles, non-temporal stores
   bool two;  // two time levels per launch (k_sweep2)
@@ -2065,7 +2112,10 @@ Layout make_layout(const lbsep_params* p) {
   L.nrt = (p->ny + L.waves * L.rpt - 1) / (L.waves * L.rpt);
   L.tiles = L.ntx * L.nrt;
   L.nend = (p->ny + 63) / 64;
-  L.lead = 2 * L.nend + strip_blocks(L.nxt, L.waves) + 1;
+  // blocks of 8 wavefronts hold two 64-row units: both ends of a channel of
+  // at most 64 rows, else two units of one end
+  L.nendb = L.waves == 8 ? (p->ny <= 64 ? 1 : 2 * ((p->ny + 127) / 128)) : 2 * L.nend;
+  L.lead = L.nendb + strip_blocks(L.nxt, L.waves) + 1;
   L.state_buf = align_up(18ull * p->ny * L.pitch * L.elem, 256);
   L.big = !L.split && L.state_buf > (128ull << 20);
   // two levels per launch: tiles own 62 columns x 6 rows of the interior
@@ -2371,6 +2421,7 @@ int lbsep_init(const lbsep_params* p, void* dev_ws, size_t ws_bytes, void* hip_s
   kp.tiles = L.tiles;
   kp.lead = L.lead;
   kp.nend = L.nend;
+  kp.nendb = L.nendb;
   kp.row = 18LL * L.pitch;
   kp.flags = p->flags | (h->L.split ? 0u : kRowMajorTiles);
   kp.r = p->dbb_r;
@@ -2747,7 +2798,7 @@ long long batch_grid(lbsep_channel* const* chans, int n, bool two, std::vector<i
       put(i, 0);
       put(i, 7);
     } else {
-      for (int b = 0; b < 2 * L.nend; ++b) put(i, b);
+      for (int b = 0; b < L.nendb; ++b) put(i, b);
     }
   }
   for (int i = 0; i < n; ++i) {
@@ -2756,7 +2807,7 @@ long long batch_grid(lbsep_channel* const* chans, int n, bool two, std::vector<i
       for (int b = 1; b < L.lead2; ++b)
         if (b != 7) put(i, b);
     } else {
-      for (int b = 2 * L.nend; b < L.lead; ++b) put(i, b);
+      for (int b = L.nendb; b < L.lead; ++b) put(i, b);
     }
   }
   for (int i = 0; i < n; ++i) {
