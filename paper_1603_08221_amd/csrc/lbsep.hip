@@ -1340,9 +1340,18 @@ __device__ __forceinline__ double wave_column_sum(const double (*red)[kW2][kTX],
 // The end strip of a two-level launch in LDS: column c (0 = the end column,
 // counted inwards), row j, direction i; at most 128 rows in the deviation
 // modes (one node per thread of the 512-thread block), 64 in FP64 (a lane
-// pair per node, and twice the bytes per population).
+// pair per node, and twice the bytes per population). The two-level kernels
+// are instantiated per strip size: MD there is StripMode<mode, R>, R = 64 for
+// channels of at most 64 rows (the smaller LDS strips and end-column sums
+// keep those channels as fast as before the 128-row strips: 64x1280 FP32
+// 6.25 -> 5.86 us per level) and 128 above.
+template <class MD, int R>
+struct StripMode : MD {
+  static constexpr int kStripRows = R;
+};
 template <class MD>
-constexpr int kStripRowsOf = MD::kDev ? 128 : 64;
+constexpr int kStripRowsOf = MD::kStripRows;
+constexpr int strip_max_rows(int dtype) { return dtype == LBSEP_F64 ? 64 : 128; }
 
 // Pulled populations of node (c, j) of end e's strip from its post-collision
 // pairs Q (storage type): gather_pair with the strip as the source.
@@ -1635,13 +1644,14 @@ __device__ __forceinline__ void end_block2(const KParams& kp, const KBufs& kb, c
     end_block2_node<MD, NT>(kp, src, dst, e, lv.nlev, lv.t1, Q, Kv, redk, ns);
   if (!lv.reduce) return;  // uniform over the block
   // per level: the nodes' sums into LDS by (column, quantity, row), then sum
-  // k = (column, quantity): thread 8 k + g adds rows g R .. g R + R - 1
-  // (R = kRows / 8) into Kv (free once kappa is taken), then thread k adds
-  // the eight
+  // k = (column, quantity): thread G k + g adds rows 8 g .. 8 g + 7 (G =
+  // kRows / 8 groups) into Kv (free once kappa is taken), then thread k adds
+  // the G group sums in order (groups beyond the channel's rows hold zeros,
+  // so both strip sizes give a channel of at most 64 rows the same sums)
   EndSums<MD>& V = *reinterpret_cast<EndSums<MD>*>(&red[0][0][0]);
-  constexpr int kGroup = kRows / 8;
+  constexpr int kGroups = kRows / 8;
   constexpr int nsum = kEndCols * 4;
-  static_assert(8 * nsum <= 4 * kRows, "the partial sums fit Kv");
+  static_assert(kGroups * nsum <= 4 * kRows, "the partial sums fit Kv");
 #pragma unroll
   for (int lev = 0; lev < 2; ++lev) {
     if (lev >= lv.nlev) break;  // uniform over the block
@@ -1651,20 +1661,20 @@ __device__ __forceinline__ void end_block2(const KParams& kp, const KBufs& kb, c
       for (int q = 0; q < 4; ++q)
         if (ns.s[lev] < 0 || q == ns.s[lev] || q == 2 + ns.s[lev]) V[ns.c[lev]][q][ns.j[lev]] = ns.v[lev][q];
     __syncthreads();
-    if (t < 8 * nsum) {
-      const int k = t >> 3, g = t & 7;
+    if (t < kGroups * nsum) {
+      const int k = t / kGroups, g = t - k * kGroups;
       const double* v = V[k / 4][k % 4];
       double a = 0.0;
 #pragma unroll
-      for (int r = 0; r < kGroup; ++r)
-        if (kGroup * g + r < kp.ny) a += v[kGroup * g + r];
+      for (int r = 0; r < 8; ++r)
+        if (8 * g + r < kp.ny) a += v[8 * g + r];
       Kv[t] = a;
     }
     __syncthreads();
     if (t < nsum) {
       double a = 0.0;
 #pragma unroll
-      for (int g = 0; g < 8; ++g) a += Kv[8 * t + g];
+      for (int g = 0; g < kGroups; ++g) a += Kv[kGroups * t + g];
       const int c = t / 4, q = t % 4;
       const long long level = lv.t1 + lev;
       if (c == 0)
@@ -1785,7 +1795,9 @@ __device__ __forceinline__ void sweep2_block(const KParams& kp, const KBufs& kb,
       // strip reductions, one wavefront per task = (level, strip)
       const int task = r * kWaves + int(threadIdx.x / kTX);
       const int li = task / kp.nxt, bx = task - li * kp.nxt;
-      const long long level = li < 2 ? lv.strip[li] : -1;
+      // selects, not an index by li: in the batch kernel lv is a local copy,
+      // which a dynamic index would move to scratch memory
+      const long long level = li == 0 ? lv.strip[0] : (li == 1 ? lv.strip[1] : -1);
       const bool last = li == 1 || lv.strip[1] < 0;  // the latest level keeps the column sums
       if (level >= 0) strip_reduce(kp, kb, bx, level, int(level & 3), lv.nrt, lv.part_stride, 4, last);
     } else if (r == nsb) {
@@ -2066,7 +2078,7 @@ bool validate(const lbsep_params* p, std::string& why) {
     return why = "tile_rows must be 0, 1, 2 or 4", false;
   if (p->fused_steps < 0 || p->fused_steps > 2) return why = "fused_steps must be 0, 1 or 2", false;
   if (p->fused_steps == 2 && (px || py)) return why = "fused_steps = 2 needs an inlet, an outlet and walls", false;
-  if (p->fused_steps == 2 && p->ny > (p->dtype == LBSEP_F64 ? kStripRowsOf<ModeF64> : kStripRowsOf<ModeF32>))
+  if (p->fused_steps == 2 && p->ny > strip_max_rows(p->dtype))
     return why = std::string("fused_steps = 2 needs ny <= ") +
                  (p->dtype == LBSEP_F64 ? "64 in FP64" : "128 with deviation storage"), false;
   return true;
@@ -2239,15 +2251,22 @@ void launch_sweep2_md(lbsep_channel* h, const Lv2& lv, int grid, const void* src
 // k_sweep2 over the whole grid, or (nlev == 0) its lead blocks only.
 void launch_sweep2(lbsep_channel* h, const Lv2& lv, const void* src, void* dst) {
   const int grid = lv.nlev == 0 ? lv.lead : lv.lead + 8 * lv.chunk;
+  const bool tall = h->p.ny > 64;
   switch (h->p.dtype) {
     case LBSEP_F64:
-      launch_sweep2_md<ModeF64>(h, lv, grid, src, dst);
+      launch_sweep2_md<StripMode<ModeF64, 64>>(h, lv, grid, src, dst);
       break;
     case LBSEP_F32:
-      launch_sweep2_md<ModeF32>(h, lv, grid, src, dst);
+      if (tall)
+        launch_sweep2_md<StripMode<ModeF32, 128>>(h, lv, grid, src, dst);
+      else
+        launch_sweep2_md<StripMode<ModeF32, 64>>(h, lv, grid, src, dst);
       break;
     default:
-      launch_sweep2_md<ModeF16>(h, lv, grid, src, dst);
+      if (tall)
+        launch_sweep2_md<StripMode<ModeF16, 128>>(h, lv, grid, src, dst);
+      else
+        launch_sweep2_md<StripMode<ModeF16, 64>>(h, lv, grid, src, dst);
       break;
   }
 }
@@ -2767,6 +2786,7 @@ struct lbsep_batch {
   BatchEntry* tab = nullptr;     // device
   int2* blk_ref = nullptr;       // device: block -> (entry, block of that entry's launch)
   bool two = false;              // members advance two levels per launch (k_sweep2_batch)
+  bool tall2 = false;            // a two-level member has more than 64 rows (128-row end strips)
   Batch2Entry* tab2 = nullptr;   // device (two-level members)
   Batch2Levels* lev2 = nullptr;  // device: progress of the two-level launches
   hipGraph_t graph = nullptr;
@@ -2873,13 +2893,19 @@ void enqueue_batch2_levels(lbsep_batch* b, int64_t n) {
     const int nlev = left >= 2 ? 2 : 1;
     switch (b->dtype) {
       case LBSEP_F64:
-        launch_batch2<ModeF64>(b, nlev);
+        launch_batch2<StripMode<ModeF64, 64>>(b, nlev);
         break;
       case LBSEP_F32:
-        launch_batch2<ModeF32>(b, nlev);
+        if (b->tall2)
+          launch_batch2<StripMode<ModeF32, 128>>(b, nlev);
+        else
+          launch_batch2<StripMode<ModeF32, 64>>(b, nlev);
         break;
       default:
-        launch_batch2<ModeF16>(b, nlev);
+        if (b->tall2)
+          launch_batch2<StripMode<ModeF16, 128>>(b, nlev);
+        else
+          launch_batch2<StripMode<ModeF16, 64>>(b, nlev);
         break;
     }
     left -= nlev;
@@ -2960,6 +2986,8 @@ int lbsep_batch_create(lbsep_channel* const* chans, int32_t n, void* dev_ws, siz
   b->blk_ref = reinterpret_cast<int2*>(ws + B.blk);
   b->total_blocks = B.blocks;
   b->two = B.two;
+  for (int i = 0; i < n; ++i)
+    if (chans[i]->p.ny > 64) b->tall2 = true;
   if (B.two) {
     b->tab2 = reinterpret_cast<Batch2Entry*>(ws + B.tab);
     b->lev2 = reinterpret_cast<Batch2Levels*>(ws + B.tab + (size_t)n * sizeof(Batch2Entry));
