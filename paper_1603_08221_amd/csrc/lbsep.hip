@@ -42,23 +42,22 @@
 // after init / set_state, the pre-collision state f(t)).
 //
 // Work decomposition, two tile shapes with the same arithmetic per node
-// (chosen per channel, bitwise equal results):
-//   lane pair per node (SPLIT): a tile block is 4 wavefronts = 32 columns x
-//     (4 * rpt) rows; lanes 0-31 hold species a and lanes 32-63 species b of
-//     the same 32 columns; the relaxation-time work is split over the pair.
-//     Shortest chain per lane: for channels that leave the GPU mostly idle.
-//   one lane per node: 64 columns x (4 * rpt) rows, both species in one lane;
+// (chosen per channel, bitwise equal results); a block is W wavefronts (8 in
+// FP32, 4 in FP64 and FP16):
+//   lane pair per node (SPLIT): 32 columns x (W * rpt) rows; lanes 0-31 hold
+//     species a and lanes 32-63 species b of the same 32 columns; the
+//     relaxation-time work is split over the pair. Shortest chain per lane:
+//     for channels that leave the GPU mostly idle.
+//   one lane per node: 64 columns x (W * rpt) rows, both species in one lane;
 //     fewest instructions per node: for channels that fill the GPU.
-// Lead blocks come first: 2 nend blocks own the inlet and outlet columns,
-// 64 rows each (they need whole-column sums of the inner layers before they
-// can rebuild the boundary nodes, so each end block sums the full column);
-// then nxt blocks reduce one column strip each of the previous step and one
-// block finishes the step before that; the lead count is rounded up to a
-// multiple of 8. Tiles follow, numbered so that each XCD (block id mod 8) takes
-// a contiguous run of tiles: down a column strip for lane-pair tiles, along a
-// row band for one-lane-per-node tiles (on large channels consecutive tiles
-// then touch adjacent blocks of the same few rows; their stores are also
-// non-temporal).
+// Lead blocks come first: nendb blocks own the inlet and outlet columns in
+// 64-row units (one unit per block of 4 wavefronts, two per block of 8; each
+// unit needs the whole column's sum of the inner layers before it can rebuild
+// its boundary nodes), then blocks that reduce one column strip per wavefront
+// of the previous step, then one block that finishes the step before that.
+// Tiles follow in plain row-major grid order (the hardware deals consecutive
+// blocks to the 8 XCDs in turn, so the blocks in flight stay in one compact
+// stretch of the state); on large channels their stores are non-temporal.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
