@@ -31,7 +31,7 @@ SPLIT, NODE = lbsep.TILE_SPLIT, lbsep.TILE_NODE
 
 def _key(params_list, device) -> str:
     h = hashlib.sha256()
-    h.update(b"tile modes and rows: by size, 2, 4")
+    h.update(b"tile modes and rows: by size, 2, 4 (not 4 in FP32)")
     h.update(torch.cuda.get_device_name(device).encode())
     for p in params_list:
         h.update(f"{p.nx},{p.ny},{p.dtype},{p.flags}".encode())
@@ -45,18 +45,25 @@ def candidates(params_list):
     """Assignments to try, {name: {"modes": [...], "rows": [...]}} per member:
     tile modes all lane pairs, all one-lane-per-node, and size thresholds in
     between (lane pairs for members up to T nodes), each with the rows chosen
-    by size (0) and with two and four rows per wavefront."""
+    by size (0) and with two and four rows per wavefront. FP32 sweeps take no
+    four-row candidates: their blocks of 8 wavefronts already cover 16 rows
+    with two, and four made every block longer in every case measured (the
+    64-member table: 203 against 185 us per step), as the library's own
+    default assumes; short trial timings, under a profiler in particular, can
+    still rank them first."""
     sizes = [p.nx * p.ny for p in params_list]
     modes = {"split": [SPLIT] * len(sizes), "node": [NODE] * len(sizes)}
     for t in (1 << 14, 1 << 16, 1 << 18):
         a = [SPLIT if n <= t else NODE for n in sizes]
         if a not in modes.values():
             modes[f"split<={t}"] = a
+    four = not all(p.dtype == lbsep.F32 for p in params_list)
     out = {}
     for name, m in modes.items():
         out[name] = {"modes": m, "rows": [0] * len(sizes)}
         out[name + ",rows2"] = {"modes": m, "rows": [2] * len(sizes)}
-        out[name + ",rows4"] = {"modes": m, "rows": [4] * len(sizes)}
+        if four:
+            out[name + ",rows4"] = {"modes": m, "rows": [4] * len(sizes)}
     return out
 
 

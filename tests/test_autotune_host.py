@@ -3,10 +3,10 @@ choice among timed candidates, with the GPU timing replaced by fixed numbers."""
 from paper_1603_08221_amd import autotune, lbsep
 
 
-def _params():
+def _params(dtype="f64"):
     # one member below 2^14 nodes and one above, so the size thresholds differ
-    return [lbsep.make_params(80, 16, 4, 40, 0.3, 0.3, 3.0, 0.05, 0.87, dtype="f32"),
-            lbsep.make_params(640, 32, 4, 40, 0.3, 0.3, 3.0, 0.05, 0.87, dtype="f32")]
+    return [lbsep.make_params(80, 16, 4, 40, 0.3, 0.3, 3.0, 0.05, 0.87, dtype=dtype),
+            lbsep.make_params(640, 32, 4, 40, 0.3, 0.3, 3.0, 0.05, 0.87, dtype=dtype)]
 
 
 def test_candidates_cover_modes_and_rows():
@@ -18,10 +18,20 @@ def test_candidates_cover_modes_and_rows():
     assert len(c) % 3 == 0 and all(n + ",rows2" in c and n + ",rows4" in c for n in c if "rows" not in n)
 
 
-def _tune(monkeypatch, ms):
+def test_fp32_candidates_have_no_four_row_tiles():
+    c = autotune.candidates(_params("f32"))
+    assert c["node,rows2"] == {"modes": [autotune.NODE] * 2, "rows": [2, 2]}
+    assert not any(n.endswith(",rows4") for n in c)
+    assert len(c) % 2 == 0 and all(n + ",rows2" in c for n in c if "rows" not in n)
+    # a batch with any member in another dtype keeps them
+    mixed = _params("f32")[:1] + _params("f16")[1:]
+    assert "node,rows4" in autotune.candidates(mixed)
+
+
+def _tune(monkeypatch, ms, dtype="f64"):
     monkeypatch.setattr(autotune, "_key", lambda ps, dev: "k")
     monkeypatch.setattr(autotune, "_time_batch", lambda ps, modes, rows, *a: ms(modes, rows))
-    return autotune.tune(_params())
+    return autotune.tune(_params(dtype))
 
 
 def test_clear_winner_is_chosen(monkeypatch):
