@@ -127,6 +127,20 @@ def test_column_sums_against_the_oracle(tile_mode, levels, periodic_x):
     assert np.array_equal(a.read_column_sums(), b.read_column_sums())
 
 
+@pytest.mark.parametrize("nx,ny,steps", [(48, 200, 200), (40, 129, 200), (40, 257, 120)])
+def test_fp32_tall_channels_against_the_oracle(nx, ny, steps):
+    """FP32 channels taller than 128 rows (and one row over 128): their
+    inlet/outlet columns span several 8-wavefront blocks of two 64-row units,
+    which hand kappa items to each other through LDS and pull the other
+    blocks' rows; moments, CL and the profile against the oracle to 1e-5."""
+    w = Workload("tall", nx, ny, *HE_AR, 0.5, 0.5, 2.0, 0.2, steps)
+    print(f"[case] fp32 tall {nx}x{ny} {steps} steps", flush=True)
+    ch, mom, cl, ref, d = _run_both(w, steps, dtype="f32")
+    assert_moments(mom, ref, TOL32, f"{nx}x{ny}")
+    assert abs(cl["cl"] - d.cl) <= TOL32
+    assert np.max(np.abs(cl["profile"] - d.cl_profile)) <= TOL32
+
+
 def test_fp32_he_ar_8x80():
     w = CONFIGS["he_ar_8x80"]
     print("[case] fp32 he_ar_8x80 2000 steps", flush=True)
