@@ -159,6 +159,71 @@ def check_rational(p, q, tol):
     return worst
 
 
+def psi_exact(a):
+    return 1 + (a - 1) * mp.exp(-a) - a * a * mp.e1(a)
+
+
+def h_exact(a):
+    return mp.exp(-a) - a * mp.e1(a)
+
+
+def pw_interval(q, lo_oct, per_oct):
+    """[lo, hi) of interval q of the piecewise table: octave 2^e, e = lo_oct + q // per_oct,
+    split into per_oct equal parts."""
+    e, m = lo_oct + q // per_oct, q % per_oct
+    base = mp.mpf(2) ** e
+    return base * (1 + mp.mpf(m) / per_oct), base * (1 + mp.mpf(m + 1) / per_oct)
+
+
+def cheb_to_monomial(c):
+    """Monomial coefficients (ascending) of sum_k c_k T_k(s)."""
+    n = len(c)
+    out = [mp.mpf(0)] * n
+    tkm1, tk = [mp.mpf(1)], [mp.mpf(0), mp.mpf(1)]
+    for k, ck in enumerate(c):
+        t = tkm1 if k == 0 else tk
+        if k >= 2:
+            nxt = [mp.mpf(0)] + [2 * v for v in tk]
+            for i, v in enumerate(tkm1):
+                nxt[i] -= v
+            tkm1, tk = tk, nxt
+            t = tk
+        for i, v in enumerate(t):
+            out[i] += ck * v
+    return out
+
+
+def pw_poly(f, lo, hi, deg, nodes=32):
+    """Monomial coefficients in s = (2a - lo - hi) / (hi - lo) of the degree-deg
+    truncation of f's Chebyshev interpolant on [lo, hi] (nodes points)."""
+    mid, half = (lo + hi) / 2, (hi - lo) / 2
+    th = [mp.pi * (j + mp.mpf(1) / 2) / nodes for j in range(nodes)]
+    vals = [f(mid + half * mp.cos(t)) for t in th]
+    c = [2 * mp.fsum(v * mp.cos(k * t) for v, t in zip(vals, th)) / nodes for k in range(deg + 1)]
+    c[0] /= 2
+    return cheb_to_monomial(c)
+
+
+def build_pw(lo_oct, hi_oct, per_oct, deg):
+    """psi and h on [2^lo_oct, 2^hi_oct): per interval the two monomial
+    coefficient lists, and the worst errors of the double-rounded coefficients
+    evaluated exactly (psi relative to psi, h absolute) on 33 points per interval."""
+    rows, wpsi, wh = [], mp.mpf(0), mp.mpf(0)
+    for q in range((hi_oct - lo_oct) * per_oct):
+        lo, hi = pw_interval(q, lo_oct, per_oct)
+        cp = [mp.mpf(float(v)) for v in pw_poly(psi_exact, lo, hi, deg)]
+        ch = [mp.mpf(float(v)) for v in pw_poly(h_exact, lo, hi, deg)]
+        rows.append((cp, ch))
+        for k in range(33):
+            s = -1 + mp.mpf(2 * k) / 32
+            a = (lo + hi) / 2 + (hi - lo) / 2 * s
+            P = mp.fsum(v * s ** i for i, v in enumerate(cp))
+            H = mp.fsum(v * s ** i for i, v in enumerate(ch))
+            wpsi = max(wpsi, abs(P / psi_exact(a) - 1))
+            wh = max(wh, abs(H - h_exact(a)))
+    return rows, wpsi, wh
+
+
 def fmt(x, single):
     if single:
         return mp.nstr(x, 12, min_fixed=-1, max_fixed=-1) + "f"
@@ -215,6 +280,26 @@ def main():
                 lines.append("    {" + ", ".join(fmt(c, single) for c in seg) + "},")
             lines.append("};")
         print(name, "deg", deg, "worst", mp.nstr(worst, 3), "small-argument series", mp.nstr(small, 3))
+    # FP64 piecewise polynomials of psi and h on [2^-20, 64)
+    lo_oct, hi_oct, per_oct, deg = -20, 6, 8, 10
+    rows, wpsi, wh = build_pw(lo_oct, hi_oct, per_oct, deg)
+    assert wpsi < mp.mpf(2) ** -53 and wh < mp.mpf(2) ** -54, (wpsi, wh)
+    lines.append("")
+    lines.append(f"// double, 2^{lo_oct} <= a < 2^{hi_oct}: each octave [2^e, 2^(e+1)) in {per_oct} equal parts;")
+    lines.append(f"// on part q = (e - ({lo_oct})) * {per_oct} + m the coefficients c_0..c_{deg} of psi and of h in")
+    lines.append(f"// s = 2^(4-e) a - (17 + 2m) in [-1, 1) (monomials, ascending). Max relative psi error")
+    lines.append(f"// {mp.nstr(wpsi, 3)}, max absolute h error {mp.nstr(wh, 3)} (coefficients as rounded, exact sums).")
+    lines.append(f"#define LBSEP_PW_F64_LO_OCT ({lo_oct})")
+    lines.append(f"#define LBSEP_PW_F64_HI_OCT {hi_oct}")
+    lines.append(f"#define LBSEP_PW_F64_PER_OCT {per_oct}")
+    lines.append(f"#define LBSEP_PW_F64_DEG {deg}")
+    lines.append(f"#define LBSEP_PW_F64_N {len(rows)}")
+    lines.append(f"__constant__ double LBSEP_TBL(lbsep_wall_pw_f64)[{len(rows)}][2][{deg + 1}] = {{")
+    for cp, ch in rows:
+        lines.append("    {{" + ", ".join(fmt(c, False) for c in cp) + "},")
+        lines.append("     {" + ", ".join(fmt(c, False) for c in ch) + "}},")
+    lines.append("};")
+    print("double piecewise: psi rel", mp.nstr(wpsi, 3), "h abs", mp.nstr(wh, 3))
     p, q = rational_fit()
     worst = check_rational(p, q, mp.mpf("2e-8"))
     lines.append("")

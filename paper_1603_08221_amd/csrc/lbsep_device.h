@@ -20,13 +20,9 @@ namespace lbsep {
 template <typename T> struct E1Traits;
 
 template <> struct E1Traits<double> {
-  static constexpr bool kRational = false;  // octave Chebyshev interpolants for a > 1
-  static constexpr int kSeg = LBSEP_E1_F64_NSEG;
-  static constexpr int kDeg = LBSEP_E1_F64_DEG;
   static constexpr int kSer = LBSEP_E1_F64_NSER;
   __device__ static double pa(int k) { return LBSEP_TBL(lbsep_psi_a_f64)[k]; }
   __device__ static double pb(int k) { return LBSEP_TBL(lbsep_psi_b_f64)[k]; }
-  __device__ static double cheb(int s, int k) { return LBSEP_TBL(lbsep_e1_cheb_f64)[s][k]; }
   __device__ static double ex(double a) { return exp(a); }
   __device__ static double ln(double a) { return log(a); }
   __device__ static double rsq(double a) { return 1.0 / sqrt(a); }
@@ -34,29 +30,89 @@ template <> struct E1Traits<double> {
 };
 
 template <> struct E1Traits<float> {
-  static constexpr bool kRational = true;  // one rational in 1/a for a > 1
-  static constexpr int kSeg = 0;
-  static constexpr int kDeg = 0;
   static constexpr int kSer = LBSEP_E1_F32_NSER;
   __device__ static float pa(int k) { return LBSEP_TBL(lbsep_psi_a_f32)[k]; }
   __device__ static float pb(int k) { return LBSEP_TBL(lbsep_psi_b_f32)[k]; }
-  __device__ static float cheb(int, int) { return 0.0f; }
   __device__ static float ex(float a) { return __builtin_amdgcn_exp2f(a * 1.4426950408889634f); }
   __device__ static float ln(float a) { return __builtin_amdgcn_logf(a) * 0.6931471805599453f; }
   __device__ static float rsq(float a) { return __builtin_amdgcn_rsqf(a); }
   __device__ static float rcp(float a) { return __builtin_amdgcn_rcpf(a); }
 };
 
+// FP64 psi and h on 2^-20 <= a < 64 from the piecewise table: each octave in
+// eight parts, a degree-10 polynomial per part in the local variable s (exact).
+// The part index is usually the same on every lane of a wavefront (its lanes
+// are neighbouring columns of one row), so the lanes are served one distinct
+// index at a time (the first remaining lane's), with the coefficients as
+// scalar loads shared by the wavefront.
+// c_0 + c_1 s + ... + c_10 s^10 by Horner's rule with fused multiply-adds, the
+// coefficients wavefront-uniform values in scalar registers used in place (the
+// compiler's own choice, the accumulating multiply-add, would first copy each
+// one into vector registers: two moves per multiply-add).
+__device__ __forceinline__ double horner10_uniform(double s, const double* c) {
+  static_assert(LBSEP_PW_F64_DEG == 10, "one multiply-add per coefficient below");
+  double p;
+  asm("v_mov_b64 %0, %2\n\t"
+      "v_fma_f64 %0, %0, %1, %3\n\t"
+      "v_fma_f64 %0, %0, %1, %4\n\t"
+      "v_fma_f64 %0, %0, %1, %5\n\t"
+      "v_fma_f64 %0, %0, %1, %6\n\t"
+      "v_fma_f64 %0, %0, %1, %7\n\t"
+      "v_fma_f64 %0, %0, %1, %8\n\t"
+      "v_fma_f64 %0, %0, %1, %9\n\t"
+      "v_fma_f64 %0, %0, %1, %10\n\t"
+      "v_fma_f64 %0, %0, %1, %11\n\t"
+      "v_fma_f64 %0, %0, %1, %12"
+      : "=&v"(p)
+      : "v"(s), "s"(c[10]), "s"(c[9]), "s"(c[8]), "s"(c[7]), "s"(c[6]), "s"(c[5]), "s"(c[4]), "s"(c[3]),
+        "s"(c[2]), "s"(c[1]), "s"(c[0]));
+  return p;
+}
+
+template <bool WANT_H>
+__device__ __forceinline__ void wall_psi_pw(double a, double& psi, double& h) {
+  constexpr int kPer = LBSEP_PW_F64_PER_OCT, kDeg = LBSEP_PW_F64_DEG;
+  static_assert(kPer == 8, "the part index takes the top three mantissa bits");
+  const int hi = __double2hiint(a);
+  const int e = ((hi >> 20) & 0x7ff) - 1023;
+  const int m = (hi >> 17) & 7;
+  const int q = min(max((e - LBSEP_PW_F64_LO_OCT) * kPer + m, 0), LBSEP_PW_F64_N - 1);
+  const double s = ldexp(a, 4 - e) - double(17 + 2 * m);
+  double pv = 0.0, hv = 0.0;
+#pragma unroll 1
+  for (;;) {
+    const int u = __builtin_amdgcn_readfirstlane(q);
+    const double* cp = LBSEP_TBL(lbsep_wall_pw_f64)[u][0];
+    double p = horner10_uniform(s, cp);
+    // keeps the evaluation in the loop on part u's coefficients (otherwise the
+    // compiler substitutes q for u under the test below and loads per lane)
+    asm volatile("" : "+v"(p));
+    double r = 0.0;
+    if (WANT_H) {
+      const double* ch = LBSEP_TBL(lbsep_wall_pw_f64)[u][1];
+      r = horner10_uniform(s, ch);
+      asm volatile("" : "+v"(r));
+    }
+    if (u == q) {
+      pv = p;
+      hv = r;
+      break;
+    }
+  }
+  psi = pv;
+  if (WANT_H) h = hv;
+}
+
 // psi(a) = 1 + (a - 1) e^-a - a^2 E1(a) (wall function of Sec. 3.1) and, when
 // WANT_H, h(a) = e^-a - a E1(a) = psi'(a) / 2.
-//   a <= 1      : psi = A(a) + a^2 ln a, h = B(a) + a ln a, with A and B entire
-//                 power series (Horner); one logarithm, no exponential.
-//   1 < a       : E1 = e^-a G(a) / a with G(a) = a e^a E1(a), so
-//                 psi = 1 + e^-a (a - 1 - a G) and h = e^-a (1 - G).
-//                 FP64: G from the octave's Chebyshev interpolant (Clenshaw) for
-//                 a < 2^n, beyond that psi = 1 and h = 0 to FP64 precision.
-//                 FP32: G = P(1/a) / Q(1/a), one (5, 5) rational on all of
-//                 (1, inf); e^-a underflows where psi rounds to 1.
+//   FP64, 2^-20 <= a < 64: the piecewise polynomials above; a >= 64: psi = 1
+//                 and h = 0 to FP64 precision.
+//   a <= 1 (FP64: a < 2^-20): psi = A(a) + a^2 ln a, h = B(a) + a ln a, with A
+//                 and B entire power series (Horner); one logarithm.
+//   FP32, 1 < a : E1 = e^-a G(a) / a with G(a) = a e^a E1(a) = P(1/a) / Q(1/a),
+//                 one (5, 5) rational on all of (1, inf), so
+//                 psi = 1 + e^-a (a - 1 - a G) and h = e^-a (1 - G); e^-a
+//                 underflows where psi rounds to 1.
 template <typename T, bool WANT_H>
 __device__ __forceinline__ void wall_psi(T a, T& psi, T& h) {
   using E = E1Traits<T>;
@@ -64,6 +120,17 @@ __device__ __forceinline__ void wall_psi(T a, T& psi, T& h) {
     psi = T(0);
     h = T(1);
     return;
+  }
+  if constexpr (std::is_same<T, double>::value) {
+    if (a >= 0x1p-20) {
+      if (a < 64.0) {
+        wall_psi_pw<WANT_H>(a, psi, h);
+      } else {
+        psi = 1.0;
+        h = 0.0;
+      }
+      return;
+    }
   }
   if (a <= T(1)) {
     const T la = E::ln(a);
@@ -79,7 +146,7 @@ __device__ __forceinline__ void wall_psi(T a, T& psi, T& h) {
     }
     return;
   }
-  if constexpr (E::kRational) {
+  if constexpr (!std::is_same<T, double>::value) {
     const T u = E::rcp(a);
     T P = T(lbsep_e1_rat_p_f32[LBSEP_E1_F32_RAT_DEG]);
     T Q = T(lbsep_e1_rat_q_f32[LBSEP_E1_F32_RAT_DEG]);
@@ -92,37 +159,7 @@ __device__ __forceinline__ void wall_psi(T a, T& psi, T& h) {
     const T ea = E::ex(-a);
     psi = T(1) + ea * (a - T(1) - a * g);
     if (WANT_H) h = ea * (T(1) - g);
-    return;
   }
-  const int seg = ilogb(a);
-  if (seg >= E::kSeg) {
-    psi = T(1);
-    h = T(0);
-    return;
-  }
-  // Clenshaw on the octave's Chebyshev series, one octave at a time over a
-  // wave-uniform loop: the coefficients are then scalar loads shared by the
-  // wave (a wave's arguments usually span one or two octaves).
-  T g = T(0);
-#pragma unroll 1
-  for (int sg = 0; sg < E::kSeg; ++sg) {
-    if (!__any(seg == sg)) continue;
-    // t = (2a - 3 * 2^sg) / 2^sg, exact for the lanes of this octave
-    const T t = ldexp(a, 1 - sg) - T(3);
-    const T t2 = t + t;
-    T b1 = T(0), b2 = T(0);
-#pragma unroll
-    for (int k = E::kDeg; k >= 1; --k) {
-      const T b0 = E::cheb(sg, k) + t2 * b1 - b2;
-      b2 = b1;
-      b1 = b0;
-    }
-    const T gs = E::cheb(sg, 0) + t * b1 - b2;
-    if (seg == sg) g = gs;
-  }
-  const T ea = E::ex(-a);
-  psi = T(1) + ea * (a - T(1) - a * g);
-  if (WANT_H) h = ea * (T(1) - g);
 }
 
 template <typename T>
