@@ -14,7 +14,8 @@ Prints one JSON line: node-MLUPS of the timed block (one update = one node
 with both species' 9 populations; wall clock between two device
 synchronisations), the roofline of the batch sweep kernel (algorithmic bytes
 per launch over the mean launch interval from HIP events on its stream), the
-CL error of every member against the FP64 batch after 20,000 steps, the CPU
+CL error of every member against the FP64 batch after 20,000 steps, the FP64
+table (the plain solver) timed the same way beside the headline, the CPU
 oracle on the same table over the host cores, and secondary legs (the
 single 64 x 1280 channel, the 512 x 10240 bandwidth probe, the storage-
 precision comparison on 256 x 5120, the adjoint gradient, the FP64 path
@@ -41,6 +42,7 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_1603_08221_amd", "csrc", n)
                   for n in ("lbsep.hip", "lbsep_device.h", "e1_table.h")]
 METRIC = "MLUPS (both species) + achieved HBM GB/s vs FP64 plain, at CL error ≤1e-5"
 TABLE_STEPS = 20000   # steps per member of the parametric sweep (its CL error is taken there)
+FP64_TIMED_STEPS = 200  # timed FP64 table steps after its 20,000 (the plain solver beside the headline)
 CPU_POOL_MAX = 16     # worker processes of the CPU baseline (one GPU's share of the host)
 
 
@@ -254,10 +256,18 @@ def headline(torch, lbsep, args, tuned, setup):
     return rec, ws
 
 
-def accuracy_fp64(torch, lbsep):
-    """The table in FP64 for 20,000 steps: (CL per member or None, seconds)."""
+def accuracy_fp64(torch, lbsep, timed_steps=FP64_TIMED_STEPS):
+    """The table in FP64 (the plain solver; tile assignment autotuned like the
+    headline's, which changes no result bit) for 20,000 steps, then
+    `timed_steps` more graph-replayed steps timed with HIP events on the
+    batch's stream: (CL per member or None after 20,000 steps, seconds of the
+    20,000, timing record)."""
+    from paper_1603_08221_amd import autotune
+
     _, ps64 = table_params(lbsep, "f64")
-    ch64, b64, _ = table_batch(torch, lbsep, ps64)
+    tuned = autotune.tune(ps64)
+    log(f"FP64 tiles: {tuned['name']} ({tuned['ms_per_step'] * 1e3:.1f} us per trial step)")
+    ch64, b64, stream = table_batch(torch, lbsep, ps64, tuned["modes"], tuned["rows"])
     b64.capture(100)
     t0 = time.perf_counter()
     for k in range(TABLE_STEPS // 5000):
@@ -266,10 +276,24 @@ def accuracy_fp64(torch, lbsep):
         log(f"FP64 table at step {ch64[0].t}")
     f64_s = time.perf_counter() - t0
     cl64 = member_cls(lbsep, ch64)
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    b64.step(timed_steps)
+    end.record(stream)
+    torch.cuda.synchronize()
+    per = start.elapsed_time(end) / 1e3 / timed_steps
+    nodes = sum(p.nx * p.ny for p in ps64)
+    gbs = nodes * 36 * BYTES_PER_POP["f64"] / per / 1e9
+    timed = {"workload": "sweep_table_64", "dtype": "f64", "tiles": tuned["name"], "steps": timed_steps,
+             "us_per_step": round(per * 1e6, 2), "mlups": round(nodes / per / 1e6, 1),
+             "gbps_algorithmic": round(gbs, 1), "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+             "traffic": measured_traffic("sweep_table_64", "f64", tiles=tuned["name"])}
+    log(f"FP64 table: {per * 1e6:.1f} us per step, {gbs:.0f} GB/s algorithmic")
     b64.close()
     for c in ch64:
         c.close()
-    return cl64, f64_s
+    return cl64, f64_s, timed
 
 
 def accuracy_run(torch, lbsep, tuned, dtype):
@@ -294,7 +318,7 @@ def accuracy_leg(lbsep, ws, dtype, run, fp64):
     reduced-precision run and in FP64, and the members that go non-finite
     (with the mean free path per lattice spacing, Kn_out H, of each)."""
     chans, b, lo_s = run
-    cl64, f64_s = fp64
+    cl64, f64_s, _ = fp64
     cl_lo = member_cls(lbsep, chans)
     b.close()
     for c in chans:
@@ -621,6 +645,9 @@ def main(argv=None):
     rec, ws = headline(torch, lbsep, args, tuned, setup)
     if acc is not None:
         legs["table_accuracy"] = accuracy_leg(lbsep, ws, args.dtype, *acc)
+        plain = dict(acc[1][2])
+        plain["headline_speedup"] = round(plain["us_per_step"] / (rec["per_launch_s"] * 1e6), 3)
+        legs["fp64_plain"] = plain
     out = {
         "metric": METRIC,
         "value": round(rec["mlups"], 1),

@@ -97,10 +97,14 @@ def _time_batch(params_list, modes, rows, device, trial_steps, warmup):
     return ms
 
 
-def tune(params_list, device="cuda:0", trial_steps=40, warmup=10, cache_file=None):
+def tune(params_list, device="cuda:0", trial_steps=40, warmup=10, cache_file=None, rounds=2):
     """Fastest tile assignment for sweeping `params_list` together (one
     channel: alone). Returns {"name", "modes", "rows", "ms_per_step",
-    "timings"}: set each member's tile_mode and tile_rows from modes and rows."""
+    "timings"}: set each member's tile_mode and tile_rows from modes and rows.
+    Every candidate is timed once per round, round after round, and keeps its
+    best time: the first round runs while the GPU's clocks are still rising
+    (the FP64 table's first candidates came out 5-8% slow in a single round
+    and the choice 4% slower than the best)."""
     params_list = list(params_list)
     key = _key(params_list, device)
     cache = {}
@@ -111,8 +115,10 @@ def tune(params_list, device="cuda:0", trial_steps=40, warmup=10, cache_file=Non
             return cache[key]
     timings = {}
     cands = candidates(params_list)
-    for name, c in cands.items():
-        timings[name] = _time_batch(params_list, c["modes"], c["rows"], device, trial_steps, warmup)
+    for _ in range(rounds):
+        for name, c in cands.items():
+            ms = _time_batch(params_list, c["modes"], c["rows"], device, trial_steps, warmup)
+            timings[name] = min(ms, timings.get(name, ms))
     # candidates within 1% of the fastest are a tie (trial timings move by
     # about that much between runs): the first of them in candidate order wins,
     # so the same shapes get the same assignment from run to run

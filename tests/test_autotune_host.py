@@ -53,3 +53,21 @@ def test_near_tie_goes_to_the_first_candidate(monkeypatch):
     got = _tune(monkeypatch, lambda m, r: 0.200 if (r == [2, 2] and m == [autotune.SPLIT, autotune.NODE])
                 else 0.210 if (r == [2, 2] and m == [autotune.NODE] * 2) else 0.25)
     assert got["name"] == "split<=16384,rows2"
+
+
+def test_each_candidate_keeps_its_best_round(monkeypatch):
+    # the first round runs while the clocks rise: "node" is slow there and the
+    # fastest in the second round, where the others keep their first times
+    calls = []
+
+    def ms(m, r):
+        calls.append((tuple(m), tuple(r)))
+        first = calls.count((tuple(m), tuple(r))) == 1
+        if m == [autotune.NODE] * 2 and r == [0, 0]:
+            return 0.30 if first else 0.10
+        return 0.20 if first else 0.25
+    got = _tune(monkeypatch, ms)
+    n = len(autotune.candidates(_params()))
+    assert len(calls) == 2 * n  # two rounds over every candidate
+    assert got["name"] == "node" and got["ms_per_step"] == 0.10
+    assert all(v == 0.20 for k, v in got["timings"].items() if k != "node")
