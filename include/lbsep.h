@@ -78,6 +78,12 @@ extern "C" {
 #define LBSEP_F64 0 /* populations stored and collided in double                              */
 #define LBSEP_F32 1 /* deviations from the rest equilibrium stored and collided in float     */
 #define LBSEP_F16 2 /* deviations stored as IEEE binary16, collided in float                 */
+/* In FP64 the wall function (Sec. 3.1) is evaluated from piecewise polynomials
+ * on channels of more than 2^17 nodes (fewest operations: the channels that
+ * fill the GPU) and from its series and exponential form on smaller ones
+ * (registers only: their steps are latency-bound when they run alone). The
+ * two agree to about 1e-16; a channel uses one of them in every kernel that
+ * steps it, alone, in a batch or in the adjoint. */
 
 /* ---- tile shape of the sweep (lbsep_params.tile_mode) ----------------- */
 #define LBSEP_TILE_AUTO 0  /* chosen from the channel size                                */
@@ -232,10 +238,15 @@ double lbsep_dbb_r_from_cm(double c_m, double m_a, double m_b, double cl);
  * psi(alpha) = 1 + (alpha - 1) e^-alpha - alpha^2 E1(alpha) and
  * h(alpha) = psi'(alpha) / 2 = e^-alpha - alpha E1(alpha), evaluated exactly as
  * the sweep kernel does in the arithmetic of dtype (double for LBSEP_F64, float
- * otherwise). dev_alpha, dev_psi, dev_h: device arrays of n doubles (dev_h may
- * be NULL). Enqueues on hip_stream (NULL = default stream). */
+ * otherwise). table (0 or 1; LBSEP_F64 only, ignored otherwise): 1 evaluates as
+ * FP64 channels of more than 2^17 nodes do (piecewise polynomials), 0 as
+ * smaller FP64 channels do (power series, exponential and octave Chebyshev
+ * series); the two agree to about 1e-16. dev_alpha, dev_psi, dev_h: device
+ * arrays of n doubles (dev_h may be NULL). Enqueues on hip_stream (NULL =
+ * default stream). LBSEP_EINVAL for n < 0, missing arrays, a bad dtype or
+ * table. */
 int lbsep_wall_function(const double* dev_alpha, double* dev_psi, double* dev_h, int64_t n, int32_t dtype,
-                        void* hip_stream);
+                        int32_t table, void* hip_stream);
 
 /* Release the host handle (the workspace stays the caller's). NULL is a no-op. */
 void lbsep_destroy(lbsep_channel* ch);

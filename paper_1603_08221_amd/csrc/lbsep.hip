@@ -89,10 +89,22 @@ struct Mode {
   using Ct = C;  // arithmetic type
   using Pt = S __attribute__((ext_vector_type(2)));  // the two species of one population
   static constexpr bool kDev = DEV;
+  static constexpr int kPsi = 0;  // FP64 wall function: the channel's choice, read at run time
 };
 using ModeF64 = Mode<double, double, false>;
 using ModeF32 = Mode<float, float, true>;
 using ModeF16 = Mode<_Float16, float, true>;
+
+// Single-channel FP64 sweeps are compiled once per wall-function evaluation
+// (PSI = 1: the series form, 2: the piecewise polynomials) and launched by the
+// channel's choice, so that each holds only its own registers (with both
+// behind a run-time switch the one-level FP64 sweep takes 176 VGPRs and two
+// wavefronts per SIMD, against 126-159 and three). Batches and the two-level
+// kernel read the choice at run time.
+template <class MD, int PSI>
+struct PsiMode : MD {
+  static constexpr int kPsi = PSI;
+};
 
 // Wavefronts per block of the one-level sweep. FP32: 8, so that a tile of two
 // rows per wavefront covers 16 rows and its column partial sums are half as
@@ -123,6 +135,13 @@ struct KParams {
   double wa[2][9];
   double corr[2][9];    // -c_ix wa[s][i] slope[s]: streaming across one column
 };
+
+// Whether a sweep of mode MD on this channel evaluates the FP64 wall function
+// from the piecewise polynomials.
+template <class MD>
+__device__ __forceinline__ bool psi_table(const KParams& kp) {
+  return MD::kPsi == 0 ? kp.rc.psi_table != 0 : MD::kPsi == 2;
+}
 
 // Reduction buffers are double-buffered by the parity of the time level.
 struct KBufs {
@@ -536,7 +555,7 @@ __device__ __forceinline__ NodeState<typename MD::Ct> node_moments(const KParams
   const C ux = (jxa + jxb) * inv_rho;  // mixture velocity, Eq. (rhou)
   const C uy = (jya + jyb) * inv_rho;
   C ts, td, tq;
-  relaxation_times<C>(kp.rc, j, rho_a, rho_b, ts, td, tq);
+  relaxation_times<C>(kp.rc, j, rho_a, rho_b, ts, td, tq, psi_table<MD>(kp));
   // species momentum of Eq. (rhou): rho_s u_s = (1 - 1/(2 tau_d)) j_s + rho_s u / (2 tau_d)
   const C h2 = C(0.5) * E::rcp(td);
   const C g = C(1) - h2;
@@ -696,7 +715,7 @@ __device__ __forceinline__ void process_pair(const KParams& kp, int x, int j, lo
   const C ux = (jxa + jxb) * inv_rho;  // mixture velocity, Eq. (rhou)
   const C uy = (jya + jyb) * inv_rho;
   C ts, td, tq;
-  relaxation_times_pair<C, XOR>(kp.rc, j, s, rho_a, rho_b, ts, td, tq);
+  relaxation_times_pair<C, XOR>(kp.rc, j, s, rho_a, rho_b, ts, td, tq, psi_table<MD>(kp));
   // species momentum of Eq. (rhou): rho_s u_s = (1 - 1/(2 tau_d)) j_s + rho_s u / (2 tau_d)
   const C h2 = C(0.5) * E::rcp(td);
   const C g = C(1) - h2;
@@ -1942,13 +1961,14 @@ __global__ __launch_bounds__(kThreads) void k_init(KParams kp, typename MD::St* 
   }
 }
 
-// psi(alpha) and psi'(alpha)/2 of the device wall function, element-wise.
+// psi(alpha) and psi'(alpha)/2 of the device wall function, element-wise
+// (FP64: from the piecewise polynomials if `table`, else the series form).
 template <typename T>
 __global__ void k_wall_function(const double* __restrict__ a, double* __restrict__ psi, double* __restrict__ h,
-                                long long n) {
+                                long long n, int table) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
     T p, hh;
-    wall_psi<T>(T(a[i]), p, hh);
+    wall_psi<T>(T(a[i]), p, hh, table != 0);
     psi[i] = double(p);
     if (h) h[i] = double(hh);
   }
@@ -2081,6 +2101,13 @@ bool validate(const lbsep_params* p, std::string& why) {
     return why = std::string("fused_steps = 2 needs ny <= ") +
                  (p->dtype == LBSEP_F64 ? "64 in FP64" : "128 with deviation storage"), false;
   return true;
+}
+
+// FP64 channels of more than 2^17 nodes evaluate the wall function from its
+// piecewise polynomials, smaller ones (whose steps are latency-bound when they
+// run alone) from its series form; a channel keeps its choice in every kernel.
+bool wall_psi_table(const lbsep_params* p) {
+  return p->dtype == LBSEP_F64 && (long long)p->nx * p->ny > (1LL << 17);
 }
 
 Layout make_layout(const lbsep_params* p) {
@@ -2225,7 +2252,10 @@ void sweep_any(lbsep_channel* h, const void* src, void* dst, double* mom, void* 
                int jsums = 0) {
   switch (h->p.dtype) {
     case LBSEP_F64:
-      launch_sweep<ModeF64, PULL, EVAL>(h, src, dst, mom, fraw, ffull, t, jsums);
+      if (h->kp.rc.psi_table)
+        launch_sweep<PsiMode<ModeF64, 2>, PULL, EVAL>(h, src, dst, mom, fraw, ffull, t, jsums);
+      else
+        launch_sweep<PsiMode<ModeF64, 1>, PULL, EVAL>(h, src, dst, mom, fraw, ffull, t, jsums);
       break;
     case LBSEP_F32:
       launch_sweep<ModeF32, PULL, EVAL>(h, src, dst, mom, fraw, ffull, t, jsums);
@@ -2373,6 +2403,19 @@ void launch_set_pop(lbsep_channel* h, const double* src) {
                      static_cast<typename MD::St*>(h->f[0]));
 }
 
+// A recording step of an FP64 channel (MD: its wall-function evaluation).
+template <class MD>
+void launch_record(lbsep_channel* h, int grid, const double* src, double* dst, double* dev_pre, double* dev_post) {
+  if (h->L.split)
+    hipLaunchKernelGGL((k_sweep<MD, true, false, true, false, true>), dim3(grid), dim3(kTX * kWaves<MD>), 0, h->stream,
+                       h->kp, h->kb, src, dst, nullptr, dev_post, dev_pre, (long long)(h->t + 1),
+                       (long long)h->t_first, 0);
+  else
+    hipLaunchKernelGGL((k_sweep<MD, true, false, false, false, true>), dim3(grid), dim3(kTX * kWaves<MD>), 0,
+                       h->stream, h->kp, h->kb, src, dst, nullptr, dev_post, dev_pre, (long long)(h->t + 1),
+                       (long long)h->t_first, 0);
+}
+
 }  // namespace
 
 extern "C" {
@@ -2462,6 +2505,7 @@ int lbsep_init(const lbsep_params* p, void* dev_ws, size_t ws_bytes, void* hip_s
   rc.tau_bgk = p->tau_bgk;
   rc.mfp_off = (p->flags & LBSEP_MFP_OFF) ? 1 : 0;
   rc.bgk = (p->flags & LBSEP_BGK_TEST) ? 1 : 0;
+  rc.psi_table = wall_psi_table(p) ? 1 : 0;
   // species densities at the ends: rho_s = x_s P / (s_s c_s^2)
   kp.rho_bc[0][0] = p->cl_in * p_in / (rc.s[0] * cs2);
   kp.rho_bc[0][1] = (1.0 - p->cl_in) * p_in / (rc.s[1] * cs2);
@@ -2568,14 +2612,10 @@ int lbsep_step_record(lbsep_channel* h, double* dev_pre, double* dev_post) {
   const double* src = static_cast<const double*>(h->f[h->cur]);
   double* dst = static_cast<double*>(h->f[nxt_buf]);
   // the recording variant: ffull <- pulled populations, fraw <- post-collision
-  if (h->L.split)
-    hipLaunchKernelGGL((k_sweep<ModeF64, true, false, true, false, true>), dim3(grid), dim3(kTX * kWaves<ModeF64>), 0, h->stream,
-                       h->kp, h->kb, src, dst, nullptr, dev_post, dev_pre, (long long)(h->t + 1),
-                       (long long)h->t_first, 0);
+  if (h->kp.rc.psi_table)
+    launch_record<PsiMode<ModeF64, 2>>(h, grid, src, dst, dev_pre, dev_post);
   else
-    hipLaunchKernelGGL((k_sweep<ModeF64, true, false, false, false, true>), dim3(grid), dim3(kTX * kWaves<ModeF64>), 0,
-                       h->stream, h->kp, h->kb, src, dst, nullptr, dev_post, dev_pre, (long long)(h->t + 1),
-                       (long long)h->t_first, 0);
+    launch_record<PsiMode<ModeF64, 1>>(h, grid, src, dst, dev_pre, dev_post);
   h->prev_buf = h->cur;
   h->cur = nxt_buf;
   h->prev_pre = false;
@@ -2754,16 +2794,19 @@ int lbsep_set_populations(lbsep_channel* h, const double* dev_src, int64_t t) {
 }
 
 int lbsep_wall_function(const double* dev_alpha, double* dev_psi, double* dev_h, int64_t n, int32_t dtype,
-                        void* hip_stream) {
+                        int32_t table, void* hip_stream) {
   if (n < 0 || (n > 0 && (!dev_alpha || !dev_psi))) return fail(LBSEP_EINVAL, "bad argument");
   if (dtype != LBSEP_F64 && dtype != LBSEP_F32 && dtype != LBSEP_F16) return fail(LBSEP_EINVAL, "bad dtype");
+  if (table != 0 && table != 1) return fail(LBSEP_EINVAL, "bad table");
   if (n == 0) return LBSEP_OK;
   const int grid = (int)std::min<int64_t>(1024, (n + 255) / 256);
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   if (dtype == LBSEP_F64)
-    hipLaunchKernelGGL(k_wall_function<double>, dim3(grid), dim3(256), 0, st, dev_alpha, dev_psi, dev_h, (long long)n);
+    hipLaunchKernelGGL(k_wall_function<double>, dim3(grid), dim3(256), 0, st, dev_alpha, dev_psi, dev_h, (long long)n,
+                       (int)table);
   else
-    hipLaunchKernelGGL(k_wall_function<float>, dim3(grid), dim3(256), 0, st, dev_alpha, dev_psi, dev_h, (long long)n);
+    hipLaunchKernelGGL(k_wall_function<float>, dim3(grid), dim3(256), 0, st, dev_alpha, dev_psi, dev_h, (long long)n,
+                       (int)table);
   return check_hip(hipGetLastError(), "wall function launch");
 }
 

@@ -60,9 +60,9 @@ __device__ __forceinline__ long long didx(const AdjParams& ap, int s, int i, int
   return ((long long)(s * 9 + i) * ap.ny + j) * ap.nx + x;
 }
 
-// E1(a) for a > 0 (A&S 5.1.11 below 1; e^-a G(a) / a above, with G the same
-// octave Chebyshev series the wall function uses; 0 beyond the table, where E1
-// is below 1e-29).
+// E1(a) for a > 0 (A&S 5.1.11 below 1; e^-a G(a) / a above, with G the octave
+// Chebyshev series of the wall function's series form; 0 beyond the table,
+// where E1 is below 1e-29).
 __device__ double e1_dev(double a) {
   if (a <= 1.0) {
     double p = 1.0, s = 0.0;
@@ -111,21 +111,22 @@ __device__ TauState taus_fwd(const RelaxConsts& c, int j, double ra, double rb) 
     taus_from_psi<double>(c, g, 1.0, 1.0, 1.0, g.k * g.lam, 0.0, o.ts, o.td, o.tq);
     return o;
   }
+  const bool tb = c.psi_table != 0;
   o.y = double(j) + 0.5;
   o.ay = o.y * g.il;
   o.ab = (c.height - o.y) * g.il;
   double p1, p2;
-  wall_psi<double, true>(o.ay, p1, o.hay);
-  wall_psi<double, true>(o.ab, p2, o.hab);
+  wall_psi<double, true>(o.ay, p1, o.hay, tb);
+  wall_psi<double, true>(o.ab, p2, o.hab, tb);
   o.psi_m = 0.5 * (p1 + p2);
-  wall_psi<double, true>(g.xa * o.ay, p1, o.h1a);
-  wall_psi<double, true>(g.xa * o.ab, p2, o.h2a);
+  wall_psi<double, true>(g.xa * o.ay, p1, o.h1a, tb);
+  wall_psi<double, true>(g.xa * o.ab, p2, o.h2a, tb);
   o.psi_a = 0.5 * (p1 + p2);
-  wall_psi<double, true>(g.xb * o.ay, p1, o.h1b);
-  wall_psi<double, true>(g.xb * o.ab, p2, o.h2b);
+  wall_psi<double, true>(g.xb * o.ay, p1, o.h1b, tb);
+  wall_psi<double, true>(g.xb * o.ab, p2, o.h2b, tb);
   o.psi_b = 0.5 * (p1 + p2);
   o.aw = c.height * g.il;
-  wall_psi<double, true>(o.aw, o.pw, o.hw);
+  wall_psi<double, true>(o.aw, o.pw, o.hw, tb);
   taus_from_psi<double>(c, g, o.psi_m, o.psi_a, o.psi_b, 0.5 * g.k * g.lam * o.pw, g.k * (1.0 - o.hw), o.ts, o.td,
                         o.tq);
   return o;

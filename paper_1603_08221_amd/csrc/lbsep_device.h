@@ -20,9 +20,13 @@ namespace lbsep {
 template <typename T> struct E1Traits;
 
 template <> struct E1Traits<double> {
+  static constexpr bool kRational = false;  // octave Chebyshev interpolants for a > 1
+  static constexpr int kSeg = LBSEP_E1_F64_NSEG;
+  static constexpr int kDeg = LBSEP_E1_F64_DEG;
   static constexpr int kSer = LBSEP_E1_F64_NSER;
   __device__ static double pa(int k) { return LBSEP_TBL(lbsep_psi_a_f64)[k]; }
   __device__ static double pb(int k) { return LBSEP_TBL(lbsep_psi_b_f64)[k]; }
+  __device__ static double cheb(int s, int k) { return LBSEP_TBL(lbsep_e1_cheb_f64)[s][k]; }
   __device__ static double ex(double a) { return exp(a); }
   __device__ static double ln(double a) { return log(a); }
   __device__ static double rsq(double a) { return 1.0 / sqrt(a); }
@@ -30,9 +34,13 @@ template <> struct E1Traits<double> {
 };
 
 template <> struct E1Traits<float> {
+  static constexpr bool kRational = true;  // one rational in 1/a for a > 1
+  static constexpr int kSeg = 0;
+  static constexpr int kDeg = 0;
   static constexpr int kSer = LBSEP_E1_F32_NSER;
   __device__ static float pa(int k) { return LBSEP_TBL(lbsep_psi_a_f32)[k]; }
   __device__ static float pb(int k) { return LBSEP_TBL(lbsep_psi_b_f32)[k]; }
+  __device__ static float cheb(int, int) { return 0.0f; }
   __device__ static float ex(float a) { return __builtin_amdgcn_exp2f(a * 1.4426950408889634f); }
   __device__ static float ln(float a) { return __builtin_amdgcn_logf(a) * 0.6931471805599453f; }
   __device__ static float rsq(float a) { return __builtin_amdgcn_rsqf(a); }
@@ -104,49 +112,68 @@ __device__ __forceinline__ void wall_psi_pw(double a, double& psi, double& h) {
 }
 
 // psi(a) = 1 + (a - 1) e^-a - a^2 E1(a) (wall function of Sec. 3.1) and, when
-// WANT_H, h(a) = e^-a - a E1(a) = psi'(a) / 2.
-//   FP64, 2^-20 <= a < 64: the piecewise polynomials above; a >= 64: psi = 1
-//                 and h = 0 to FP64 precision.
-//   a <= 1 (FP64: a < 2^-20): psi = A(a) + a^2 ln a, h = B(a) + a ln a, with A
-//                 and B entire power series (Horner); one logarithm.
-//   FP32, 1 < a : E1 = e^-a G(a) / a with G(a) = a e^a E1(a) = P(1/a) / Q(1/a),
-//                 one (5, 5) rational on all of (1, inf), so
-//                 psi = 1 + e^-a (a - 1 - a G) and h = e^-a (1 - G); e^-a
-//                 underflows where psi rounds to 1.
+// WANT_H, h(a) = e^-a - a E1(a) = psi'(a) / 2. FP64 has two evaluations,
+// chosen per channel (`table`, the same in every kernel that steps it); they
+// agree to about 1e-16:
+//   table, 2^-20 <= a < 64: the piecewise polynomials above. Few operations,
+//                 but each evaluation waits for its coefficients: the choice
+//                 for channels that fill the GPU.
+//   otherwise (and below 2^-20):
+//   a <= 1      : psi = A(a) + a^2 ln a, h = B(a) + a ln a, with A and B entire
+//                 power series (Horner); one logarithm, no exponential.
+//   1 < a       : E1 = e^-a G(a) / a with G(a) = a e^a E1(a), so
+//                 psi = 1 + e^-a (a - 1 - a G) and h = e^-a (1 - G); G from the
+//                 octave's Chebyshev interpolant (Clenshaw). Registers only:
+//                 the choice for small channels, whose steps are latency-bound.
+//   a >= 64     : psi = 1 and h = 0 to FP64 precision.
+// FP32 (`table` ignored): the series for a <= 1; above, G = P(1/a) / Q(1/a),
+// one (5, 5) rational on all of (1, inf), and e^-a underflows where psi rounds
+// to 1.
+// psi = A(a) + a^2 ln a and h = B(a) + a ln a (the power series for small a).
 template <typename T, bool WANT_H>
-__device__ __forceinline__ void wall_psi(T a, T& psi, T& h) {
+__device__ __forceinline__ void wall_psi_small(T a, T& psi, T& h) {
+  using E = E1Traits<T>;
+  const T la = E::ln(a);
+  T A = E::pa(E::kSer - 1);
+#pragma unroll
+  for (int k = E::kSer - 2; k >= 1; --k) A = A * a + E::pa(k);
+  psi = A * a + a * a * la;  // alpha_0 = 0
+  if (WANT_H) {
+    T B = E::pb(E::kSer - 1);
+#pragma unroll
+    for (int k = E::kSer - 2; k >= 0; --k) B = B * a + E::pb(k);
+    h = B + a * la;
+  }
+}
+
+template <typename T, bool WANT_H>
+__device__ __forceinline__ void wall_psi(T a, T& psi, T& h, bool table) {
   using E = E1Traits<T>;
   if (!(a > T(0))) {
     psi = T(0);
     h = T(1);
     return;
   }
-  if constexpr (std::is_same<T, double>::value) {
-    if (a >= 0x1p-20) {
-      if (a < 64.0) {
+  if constexpr (!E::kRational) {
+    // every argument of the table evaluation returns here (with `table` known
+    // at compile time, the series form below is then not compiled in)
+    if (table) {
+      if (a < T(0x1p-20)) {
+        wall_psi_small<T, WANT_H>(a, psi, h);
+      } else if (a < T(64)) {
         wall_psi_pw<WANT_H>(a, psi, h);
       } else {
-        psi = 1.0;
-        h = 0.0;
+        psi = T(1);
+        h = T(0);
       }
       return;
     }
   }
   if (a <= T(1)) {
-    const T la = E::ln(a);
-    T A = E::pa(E::kSer - 1);
-#pragma unroll
-    for (int k = E::kSer - 2; k >= 1; --k) A = A * a + E::pa(k);
-    psi = A * a + a * a * la;  // alpha_0 = 0
-    if (WANT_H) {
-      T B = E::pb(E::kSer - 1);
-#pragma unroll
-      for (int k = E::kSer - 2; k >= 0; --k) B = B * a + E::pb(k);
-      h = B + a * la;
-    }
+    wall_psi_small<T, WANT_H>(a, psi, h);
     return;
   }
-  if constexpr (!std::is_same<T, double>::value) {
+  if constexpr (E::kRational) {
     const T u = E::rcp(a);
     T P = T(lbsep_e1_rat_p_f32[LBSEP_E1_F32_RAT_DEG]);
     T Q = T(lbsep_e1_rat_q_f32[LBSEP_E1_F32_RAT_DEG]);
@@ -159,18 +186,49 @@ __device__ __forceinline__ void wall_psi(T a, T& psi, T& h) {
     const T ea = E::ex(-a);
     psi = T(1) + ea * (a - T(1) - a * g);
     if (WANT_H) h = ea * (T(1) - g);
+    return;
+  } else {
+    const int seg = ilogb(a);
+    if (seg >= E::kSeg) {
+      psi = T(1);
+      h = T(0);
+      return;
+    }
+    // Clenshaw on the octave's Chebyshev series, one octave at a time over a
+    // wave-uniform loop: the coefficients are then scalar loads shared by the
+    // wave (a wave's arguments usually span one or two octaves).
+    T g = T(0);
+#pragma unroll 1
+    for (int sg = 0; sg < E::kSeg; ++sg) {
+      if (!__any(seg == sg)) continue;
+      // t = (2a - 3 * 2^sg) / 2^sg, exact for the lanes of this octave
+      const T t = ldexp(a, 1 - sg) - T(3);
+      const T t2 = t + t;
+      T b1 = T(0), b2 = T(0);
+#pragma unroll
+      for (int k = E::kDeg; k >= 1; --k) {
+        const T b0 = E::cheb(sg, k) + t2 * b1 - b2;
+        b2 = b1;
+        b1 = b0;
+      }
+      const T gs = E::cheb(sg, 0) + t * b1 - b2;
+      if (seg == sg) g = gs;
+    }
+    const T ea = E::ex(-a);
+    psi = T(1) + ea * (a - T(1) - a * g);
+    if (WANT_H) h = ea * (T(1) - g);
   }
 }
 
 template <typename T>
-__device__ __forceinline__ void wall_psi(T a, T& psi, T& h) {
-  wall_psi<T, true>(a, psi, h);
+__device__ __forceinline__ void wall_psi(T a, T& psi, T& h, bool table) {
+  wall_psi<T, true>(a, psi, h, table);
 }
 
 template <typename T>
-__device__ __forceinline__ T wall_psi_only(T a) {
+__device__ __forceinline__ T wall_psi_only(T a, bool table) {
   T p, h;
-  wall_psi<T, false>(a, p, h);
+  wall_psi<T, false>(a, p, h, table);
   return p;
 }
 
@@ -188,12 +246,15 @@ struct RelaxConsts {
   double tau_bgk;
   int mfp_off;
   int bgk;
+  int psi_table;    // FP64 wall function from the piecewise polynomials (1) or its series/exponential form (0)
 };
 
 // Relaxation times of one node, recomputed every step from its pre-collision
 // state. The common part (mixture quantities and mean free path) and the final
 // formulas are shared; the seven wall-function evaluations are either done by
 // one lane (relaxation_times) or split over a lane pair (relaxation_times_pair).
+// tb: the FP64 wall-function evaluation (the piecewise polynomials or the
+// series form, see wall_psi).
 template <typename T>
 struct NodeGas {
   T xa, xb, mx, il, lam, k;
@@ -234,7 +295,7 @@ __device__ __forceinline__ void taus_from_psi(const RelaxConsts& c, const NodeGa
 // One lane per node: all seven wall-function evaluations here.
 template <typename T>
 __device__ __forceinline__ void relaxation_times(const RelaxConsts& c, int j, T rho_a, T rho_b, T& tau_s,
-                                                 T& tau_d, T& tau_q) {
+                                                 T& tau_d, T& tau_q, bool tb) {
   if (c.bgk) {
     tau_s = tau_d = tau_q = T(c.tau_bgk);
     return;
@@ -246,13 +307,13 @@ __device__ __forceinline__ void relaxation_times(const RelaxConsts& c, int j, T 
   }
   const T y = T(j) + T(0.5);
   const T ay = y * g.il, ab = (T(c.height) - y) * g.il;
-  const T psi_m = T(0.5) * (wall_psi_only(ay) + wall_psi_only(ab));
+  const T psi_m = T(0.5) * (wall_psi_only(ay, tb) + wall_psi_only(ab, tb));
   // lambda_sigma = lambda / x_sigma  ->  y / lambda_sigma = x_sigma y / lambda (R6)
-  const T psi_a = T(0.5) * (wall_psi_only(g.xa * ay) + wall_psi_only(g.xa * ab));
-  const T psi_b = T(0.5) * (wall_psi_only(g.xb * ay) + wall_psi_only(g.xb * ab));
+  const T psi_a = T(0.5) * (wall_psi_only(g.xa * ay, tb) + wall_psi_only(g.xa * ab, tb));
+  const T psi_b = T(0.5) * (wall_psi_only(g.xb * ay, tb) + wall_psi_only(g.xb * ab, tb));
   // wall values (R8): tau~_s(0) = k lam psi(H/lam) / 2, tau~'_s(0) = k (1 - h(H/lam))
   T pw, hw;
-  wall_psi(T(c.height) * g.il, pw, hw);
+  wall_psi(T(c.height) * g.il, pw, hw, tb);
   taus_from_psi<T>(c, g, psi_m, psi_a, psi_b, T(0.5) * g.k * g.lam * pw, g.k * (T(1) - hw), tau_s, tau_d,
                    tau_q);
 }
@@ -282,7 +343,7 @@ __device__ __forceinline__ double lane_xor(double v, int m) {
 // with identical tau values.
 template <typename T, int XOR>
 __device__ __forceinline__ void relaxation_times_pair(const RelaxConsts& c, int j, int s, T rho_a, T rho_b,
-                                                      T& tau_s, T& tau_d, T& tau_q) {
+                                                      T& tau_s, T& tau_d, T& tau_q, bool tb) {
   if (c.bgk) {
     tau_s = tau_d = tau_q = T(c.tau_bgk);
     return;
@@ -296,12 +357,12 @@ __device__ __forceinline__ void relaxation_times_pair(const RelaxConsts& c, int 
   const T ay = y * g.il, ab = (T(c.height) - y) * g.il;
   // lane a: psi(y/l), psi((H-y)/l), psi(x_a y/l), psi(x_a (H-y)/l)
   // lane b: psi(x_b y/l), psi(x_b (H-y)/l), psi and h of H/l
-  const T p0 = wall_psi_only(s ? g.xb * ay : ay);
-  const T p1 = wall_psi_only(s ? g.xb * ab : ab);
+  const T p0 = wall_psi_only(s ? g.xb * ay : ay, tb);
+  const T p1 = wall_psi_only(s ? g.xb * ab : ab, tb);
   T p2, h2;
-  wall_psi<T, true>(s ? T(c.height) * g.il : g.xa * ay, p2, h2);
+  wall_psi<T, true>(s ? T(c.height) * g.il : g.xa * ay, p2, h2, tb);
   T p3 = T(0);
-  if (s == 0) p3 = wall_psi_only(g.xa * ab);
+  if (s == 0) p3 = wall_psi_only(g.xa * ab, tb);
   const T X = T(0.5) * (p0 + p1);           // lane a: Psi(y; l), lane b: Psi(y; l_b)
   const T Y = s ? p2 : T(0.5) * (p2 + p3);  // lane a: Psi(y; l_a), lane b: psi(H/l)
   const T Xo = lane_xor(X, XOR);

@@ -75,7 +75,7 @@ def load():
         "lbsep_step_record": (c_int, [c_void_p, c_void_p, c_void_p]),
         "lbsep_set_populations": (c_int, [c_void_p, c_void_p, c_int64]),
         "lbsep_dbb_r_from_cm": (c_double, [c_double, c_double, c_double, c_double]),
-        "lbsep_wall_function": (c_int, [c_void_p, c_void_p, c_void_p, c_int64, c_int32, c_void_p]),
+        "lbsep_wall_function": (c_int, [c_void_p, c_void_p, c_void_p, c_int64, c_int32, c_int32, c_void_p]),
         "lbsep_destroy": (None, [c_void_p]),
         "lbsep_last_error": (c_char_p, []),
         "lbsep_batch_workspace_bytes": (c_size_t, [POINTER(c_void_p), c_int32]),
@@ -127,8 +127,10 @@ def dbb_r_from_cm(c_m: float, m_a: float, m_b: float, cl: float) -> float:
     return load().lbsep_dbb_r_from_cm(c_m, m_a, m_b, cl)
 
 
-def wall_function(alpha: torch.Tensor, dtype="f64"):
-    """(psi, psi'/2) of the device wall function for a float64 cuda tensor."""
+def wall_function(alpha: torch.Tensor, dtype="f64", table=True):
+    """(psi, psi'/2) of the device wall function for a float64 cuda tensor
+    (FP64: as channels above 2^17 nodes evaluate it if `table`, else as smaller
+    ones do)."""
     if alpha.dtype != torch.float64 or alpha.device.type != "cuda":
         raise ValueError("alpha must be a float64 cuda tensor")
     a = alpha.contiguous()
@@ -136,7 +138,8 @@ def wall_function(alpha: torch.Tensor, dtype="f64"):
     h = torch.empty_like(a)
     code = _DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
     _check(load().lbsep_wall_function(c_void_p(a.data_ptr()), c_void_p(psi.data_ptr()), c_void_p(h.data_ptr()),
-                                      a.numel(), code, c_void_p(torch.cuda.current_stream().cuda_stream)))
+                                      a.numel(), code, 1 if table else 0,
+                                      c_void_p(torch.cuda.current_stream().cuda_stream)))
     return psi, h
 
 

@@ -64,8 +64,9 @@ def test_post_collision_state_is_the_collision_of_the_populations(dtype, tol):
 @pytest.mark.parametrize("shape,tile_mode,modes", [((90, 12), lbsep.TILE_NODE, {}),
                                                    ((90, 12), lbsep.TILE_SPLIT, {}),
                                                    ((70, 130), lbsep.TILE_AUTO, {}),
-                                                   ((48, 10), lbsep.TILE_AUTO, {"periodic_x": True})],
-                         ids=["node", "pair", "three-end-blocks", "periodic-x"])
+                                                   ((48, 10), lbsep.TILE_AUTO, {"periodic_x": True}),
+                                                   ((1100, 120), lbsep.TILE_AUTO, {})],
+                         ids=["node", "pair", "three-end-blocks", "periodic-x", "piecewise-wall-function"])
 def test_recording_step_writes_what_the_readouts_return(shape, tile_mode, modes):
     """A recording step's pre- and post-collision outputs are bitwise the
     readouts after a plain step from the same state, and the two channels

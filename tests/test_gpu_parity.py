@@ -78,6 +78,7 @@ def test_fp64_history_matches_oracle_per_step():
     (333, 24, HE_AR, 0.5, 0.5, 5.0, 0.01, 150),    # tiny mean free path, large tau_q
     (24, 2048, HE_AR, 0.5, 0.5, 2.0, 0.1, 20),     # tallest channel: 32 end blocks per end
     (24, 1000, NE_AR, 0.4, 0.4, 2.0, 0.2, 30),     # end blocks with a ragged last block
+    (1100, 120, HE_AR, 0.5, 0.5, 2.0, 0.2, 40),    # > 2^17 nodes: piecewise wall function
 ])
 def test_fp64_ragged_and_edge_shapes(nx, ny, pair, cin, cout, theta, kn, steps):
     w = Workload("edge", nx, ny, *pair, cin, cout, theta, kn, steps)
@@ -393,15 +394,22 @@ def test_fp16_storage_reports_error_against_oracle():
     assert abs(cl["cl"] - d.cl) < 5e-3
 
 
-@pytest.mark.parametrize("dtype,tol", [("f64", 4e-16), ("f32", 3e-7)])
-def test_device_wall_function_against_mpmath(dtype, tol):
+@pytest.mark.parametrize("dtype,tol,table", [("f64", 4e-16, True), ("f64", 4e-16, False), ("f32", 3e-7, True)])
+def test_device_wall_function_against_mpmath(dtype, tol, table):
     """The kernel's own psi and psi'/2 (Sec. 3.1) against the identities
-    psi = 1 - 2 E_3 and psi'/2 = E_2, evaluated by mpmath."""
+    psi = 1 - 2 E_3 and psi'/2 = E_2, evaluated by mpmath; in FP64 both
+    evaluations (the piecewise polynomials of large channels, the series form
+    of small ones), across the piecewise table's part and octave edges and
+    below its lower end."""
     import mpmath
 
     mpmath.mp.dps = 40  # 1 - 2 E_3 cancels for small alpha: evaluate it exactly
-    xs = np.concatenate([[0.0], np.geomspace(1e-7, 1, 60), np.linspace(1.0, 70.0, 400), [100.0, 1e3]])
-    psi, h = lbsep.wall_function(torch.from_numpy(xs).cuda(), dtype)
+    edges = np.ldexp(1.0 + np.arange(8) / 8.0, 0)[None, :] * np.ldexp(1.0, np.arange(-20, 6))[:, None]
+    edges = edges.ravel()
+    xs = np.concatenate([[0.0, 1e-9, 2.0 ** -20 * (1 - 2 ** -52)], np.geomspace(1e-7, 1, 60),
+                         np.linspace(1.0, 70.0, 400), [63.999, 64.0, 100.0, 1e3],
+                         edges, np.nextafter(edges, 0.0)])
+    psi, h = lbsep.wall_function(torch.from_numpy(xs).cuda(), dtype, table=table)
     psi, h = psi.cpu().numpy(), h.cpu().numpy()
     ref_psi = np.array([0.0 if x == 0 else float(1 - 2 * mpmath.expint(3, mpmath.mpf(x))) for x in xs])
     ref_h = np.array([1.0 if x == 0 else float(mpmath.expint(2, mpmath.mpf(x))) for x in xs])
