@@ -66,6 +66,20 @@ def test_two_levels_per_launch_match_single_levels(dtype, shape):
     np.testing.assert_allclose(hb[:, 1:3], ha[:, 1:3], rtol=1e-11, atol=1e-14)
 
 
+def test_fp64_two_levels_match_single_levels_with_the_piecewise_wall_function():
+    """An FP64 channel of more than 2^17 nodes evaluates the wall function from
+    the piecewise polynomials: in the single-level sweep compiled for it and,
+    switched at run time, in the two-level kernel; the states stay bitwise
+    equal."""
+    w = Workload("fused-table", 2100, 64, *HE_AR, 0.5, 0.5, 2.0, 0.1, 0)
+    assert w.nx * w.ny > 1 << 17
+    a, b = _pair(w, "f64")
+    for n in (2, 1, 5):
+        a.step(n)
+        b.step(n)
+        _agree(a, b, f"t = {a.t}")
+
+
 # channels of 65 to 128 rows: two end blocks per end in single-level launches,
 # one two-level end block of 512 nodes (deviation storage only)
 TALL = [(200, 100), (90, 128), (150, 65), (9, 127)]
