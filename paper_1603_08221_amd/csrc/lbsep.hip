@@ -1169,6 +1169,24 @@ __device__ __forceinline__ void sweep_block(const KParams& kp, const KBufs& kb,
   }
 }
 
+// One-level tiles are dealt out in groups of 8 kXcdRun: the hardware hands
+// block k of a launch to XCD k mod 8, so placing tile kXcdRun j + t of a group
+// at slot j + 8 t gives each XCD kXcdRun consecutive tiles (x-neighbours in a
+// row band, y-neighbours in a column strip) back to back; the halo lines they
+// share then come from the XCD's own L2 instead of the memory side (64-member
+// table, FP32: fetched bytes 1.109 -> 1.075 times the algorithmic ones). A
+// last partial group keeps the plain order. k_sweep maps its block index
+// here; batches order their block table the same way on the host.
+constexpr int kXcdRun = 4;
+
+__device__ __forceinline__ int xcd_run_block(const KParams& kp, int b) {
+  constexpr int grp = 8 * kXcdRun;
+  const int lin = b - kp.lead;
+  if (lin < 0 || lin >= kp.tiles / grp * grp) return b;
+  const int s = lin % grp;
+  return kp.lead + (lin - s) + kXcdRun * (s % 8) + s / 8;
+}
+
 // REC (a recording step of an FP64 channel): besides the step, ffull receives
 // the pulled (pre-collision) populations and fraw the post-collision ones,
 // both dense [2][9][ny][nx].
@@ -1179,8 +1197,8 @@ __global__ __launch_bounds__(kTX * kWaves<MD>) void k_sweep(KParams kp, KBufs kb
                                                     double* __restrict__ ffull, long long t,
                                                     long long t_first, int jsums) {
   __shared__ double red[kWaves<MD>][kWaves<MD>][kTX];  // up to W quantities (inlet/outlet unit sums)
-  sweep_block<MD, PULL, EVAL, SPLIT, NT, REC>(kp, kb, src, dst, mom, fraw, ffull, t, t_first, (int)blockIdx.x, red,
-                                              jsums != 0);
+  sweep_block<MD, PULL, EVAL, SPLIT, NT, REC>(kp, kb, src, dst, mom, fraw, ffull, t, t_first,
+                                              xcd_run_block(kp, (int)blockIdx.x), red, jsums != 0);
 }
 
 // A batch of channels swept by one launch: entry i holds channel i's constants,
@@ -2872,15 +2890,27 @@ long long batch_grid(lbsep_channel* const* chans, int n, bool two, std::vector<i
       for (int b = L.nendb; b < L.lead; ++b) put(i, b);
     }
   }
-  for (int i = 0; i < n; ++i) {
-    const Layout& L = chans[i]->L;
-    if (two) {
+  if (two) {
+    for (int i = 0; i < n; ++i) {
+      const Layout& L = chans[i]->L;
       while (k & 7) put(i, -1);  // filler block
       for (int b = 0; b < 8 * L.chunk2; ++b) put(i, L.lead2 + b);
-    } else {
-      for (int b = 0; b < L.tiles; ++b) put(i, L.lead + b);
     }
+    return k;
   }
+  // one-level tiles, every member's in its own order, dealt out in runs of
+  // kXcdRun per XCD as k_sweep deals a channel's (xcd_run_block)
+  std::vector<int2> tl;
+  for (int i = 0; i < n; ++i) {
+    const Layout& L = chans[i]->L;
+    for (int b = 0; b < L.tiles; ++b) tl.push_back(make_int2(i, L.lead + b));
+  }
+  const size_t grp = 8 * kXcdRun;
+  const size_t full = tl.size() / grp * grp;
+  for (size_t g = 0; g < full; g += grp)
+    for (int t = 0; t < kXcdRun; ++t)
+      for (int j = 0; j < 8; ++j) put(tl[g + kXcdRun * j + t].x, tl[g + kXcdRun * j + t].y);
+  for (size_t q = full; q < tl.size(); ++q) put(tl[q].x, tl[q].y);
   return k;
 }
 
