@@ -47,12 +47,6 @@ template <> struct E1Traits<float> {
   __device__ static float rcp(float a) { return __builtin_amdgcn_rcpf(a); }
 };
 
-// FP64 psi and h on 2^-20 <= a < 64 from the piecewise table: each octave in
-// eight parts, a degree-10 polynomial per part in the local variable s (exact).
-// The part index is usually the same on every lane of a wavefront (its lanes
-// are neighbouring columns of one row), so the lanes are served one distinct
-// index at a time (the first remaining lane's), with the coefficients as
-// scalar loads shared by the wavefront.
 // c_0 + c_1 s + ... + c_10 s^10 by Horner's rule with fused multiply-adds, the
 // coefficients wavefront-uniform values in scalar registers used in place (the
 // compiler's own choice, the accumulating multiply-add, would first copy each
@@ -77,6 +71,12 @@ __device__ __forceinline__ double horner10_uniform(double s, const double* c) {
   return p;
 }
 
+// FP64 psi and h on 2^-20 <= a < 64 from the piecewise table: each octave in
+// eight parts, a degree-10 polynomial per part in the local variable s (exact).
+// The part index is usually the same on every lane of a wavefront (its lanes
+// are neighbouring columns of one row), so the lanes are served one distinct
+// index at a time (the first remaining lane's), with the coefficients as
+// scalar loads shared by the wavefront.
 template <bool WANT_H>
 __device__ __forceinline__ void wall_psi_pw(double a, double& psi, double& h) {
   constexpr int kPer = LBSEP_PW_F64_PER_OCT, kDeg = LBSEP_PW_F64_DEG;
@@ -111,6 +111,23 @@ __device__ __forceinline__ void wall_psi_pw(double a, double& psi, double& h) {
   if (WANT_H) h = hv;
 }
 
+// psi = A(a) + a^2 ln a and h = B(a) + a ln a (the power series for small a).
+template <typename T, bool WANT_H>
+__device__ __forceinline__ void wall_psi_small(T a, T& psi, T& h) {
+  using E = E1Traits<T>;
+  const T la = E::ln(a);
+  T A = E::pa(E::kSer - 1);
+#pragma unroll
+  for (int k = E::kSer - 2; k >= 1; --k) A = A * a + E::pa(k);
+  psi = A * a + a * a * la;  // alpha_0 = 0
+  if (WANT_H) {
+    T B = E::pb(E::kSer - 1);
+#pragma unroll
+    for (int k = E::kSer - 2; k >= 0; --k) B = B * a + E::pb(k);
+    h = B + a * la;
+  }
+}
+
 // psi(a) = 1 + (a - 1) e^-a - a^2 E1(a) (wall function of Sec. 3.1) and, when
 // WANT_H, h(a) = e^-a - a E1(a) = psi'(a) / 2. FP64 has two evaluations,
 // chosen per channel (`table`, the same in every kernel that steps it); they
@@ -129,23 +146,6 @@ __device__ __forceinline__ void wall_psi_pw(double a, double& psi, double& h) {
 // FP32 (`table` ignored): the series for a <= 1; above, G = P(1/a) / Q(1/a),
 // one (5, 5) rational on all of (1, inf), and e^-a underflows where psi rounds
 // to 1.
-// psi = A(a) + a^2 ln a and h = B(a) + a ln a (the power series for small a).
-template <typename T, bool WANT_H>
-__device__ __forceinline__ void wall_psi_small(T a, T& psi, T& h) {
-  using E = E1Traits<T>;
-  const T la = E::ln(a);
-  T A = E::pa(E::kSer - 1);
-#pragma unroll
-  for (int k = E::kSer - 2; k >= 1; --k) A = A * a + E::pa(k);
-  psi = A * a + a * a * la;  // alpha_0 = 0
-  if (WANT_H) {
-    T B = E::pb(E::kSer - 1);
-#pragma unroll
-    for (int k = E::kSer - 2; k >= 0; --k) B = B * a + E::pb(k);
-    h = B + a * la;
-  }
-}
-
 template <typename T, bool WANT_H>
 __device__ __forceinline__ void wall_psi(T a, T& psi, T& h, bool table) {
   using E = E1Traits<T>;
