@@ -1174,9 +1174,10 @@ __device__ __forceinline__ void sweep_block(const KParams& kp, const KBufs& kb,
 // at slot j + 8 t gives each XCD kXcdRun consecutive tiles (x-neighbours in a
 // row band, y-neighbours in a column strip) back to back; the halo lines they
 // share then come from the XCD's own L2 instead of the memory side (64-member
-// table, FP32: fetched bytes 1.109 -> 1.075 times the algorithmic ones). A
-// last partial group keeps the plain order. k_sweep maps its block index
-// here; batches order their block table the same way on the host.
+// table, FP32: fetched plus written bytes 1.109 -> 1.050 times the
+// algorithmic ones). A last partial group keeps the plain order. k_sweep maps
+// its block index here; batches order their block table the same way on the
+// host.
 constexpr int kXcdRun = 4;
 
 __device__ __forceinline__ int xcd_run_block(const KParams& kp, int b) {
