@@ -174,6 +174,14 @@ __device__ __forceinline__ void wall_psi(T a, T& psi, T& h, bool table) {
     return;
   }
   if constexpr (E::kRational) {
+    // from a = 17 on, e^-a (a - 1 - a G) is below 5e-9 in magnitude and psi
+    // rounds to 1 exactly; h (below 3e-9) enters only as 1 - h, which rounds
+    // to 1 as well: the shortcut gives the same bits downstream
+    if (a >= T(17)) {
+      psi = T(1);
+      h = T(0);
+      return;
+    }
     const T u = E::rcp(a);
     T P = T(lbsep_e1_rat_p_f32[LBSEP_E1_F32_RAT_DEG]);
     T Q = T(lbsep_e1_rat_q_f32[LBSEP_E1_F32_RAT_DEG]);
