@@ -47,6 +47,27 @@ def test_adjoint_step_matches_the_cpu_reverse_sweep(modes):
         assert abs(dp[k] - ref_dp[k]) <= 1e-11 * max(abs(ref_dp[k]), 1e-3), (k, dp[k], ref_dp[k])
 
 
+def test_adjoint_step_with_the_piecewise_wall_function_matches_the_cpu_reverse_sweep():
+    """A channel of more than 2^17 nodes takes psi and h from the piecewise
+    polynomials, in the adjoint's forward relaxation times as in its sweeps:
+    one reverse step against the CPU reverse sweep."""
+    w = SMALL.with_(nx=1100, ny=120)
+    assert w.nx * w.ny > 1 << 17
+    r = r_of(w)
+    print(f"[case] adjoint step {w.nx}x{w.ny}", flush=True)
+    ch = channel(w, r)
+    p = oracle_params(w, r)
+    f = _state(p)
+    lam = np.random.default_rng(12).standard_normal(f.shape)
+    ref_lam, ref_dp = A.step_vjp(f, lam, p)
+    adj = Adjoint(ch)
+    got = adj.step(torch.from_numpy(f).cuda(), torch.from_numpy(lam).cuda()).cpu().numpy()
+    assert _rel(got, ref_lam) <= 1e-12
+    dp = adj.dparams.cpu().numpy()
+    for k in range(3):
+        assert abs(dp[k] - ref_dp[k]) <= 1e-11 * max(abs(ref_dp[k]), 1e-3), (k, dp[k], ref_dp[k])
+
+
 @pytest.mark.parametrize("dtype,tol", [("f64", 1e-13), ("f32", 1e-5)])
 def test_post_collision_state_is_the_collision_of_the_populations(dtype, tol):
     """The forward's own post-collision state f'(t) against the oracle's
